@@ -1,0 +1,107 @@
+"""Seeded synthetic images that stand in for the paper's test pictures.
+
+The paper's images (an MRI scan from a cited publication and private photos,
+Sec. 3.2 and Sec. 4.2) are not available, so every input here is a seeded
+Voronoi mosaic with the value range the paper uses (colours in [0,1], Sec. 2).
+This module is shared input plumbing only: it holds none of the method's
+arithmetic and is imported both by the tests that drive the CPU oracle and by
+the GPU path's tests and benchmark.
+
+Recipe (numpy PCG64, ``default_rng(seed)``; draws in this fixed order):
+  1. sites: ``regions x 2`` uniform in [0,W) x [0,H) (pixel units, (x, y));
+  2. region colours: U[0,1]^C, or smooth spectra when ``spectra=True``;
+  3. per-region linear colour gradient (only when ``gradient_amp > 0``):
+     direction angle U[0,2pi), colour direction U[-1,1]^C;
+  4. i.i.d. Gaussian noise N(0, sigma^2) per pixel and channel.
+Each pixel takes the region whose site is nearest to its centre
+(q+1/2, r+1/2) (ties: lowest site index), adds the region's gradient term
+``amp * d_s * ((x, y) - site_s) . u_s`` in normalised coordinates (x=(q+1/2)/W,
+y=(r+1/2)/H), adds noise, is clipped to [0,1] and stored as float32, HWC
+(channel fastest), row 0 first in memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["voronoi_image", "voronoi_labels", "batch_shapes"]
+
+
+def _nearest_site(H: int, W: int, sites: np.ndarray) -> np.ndarray:
+    xs = np.arange(W, dtype=np.float64) + 0.5
+    ys = np.arange(H, dtype=np.float64) + 0.5
+    best = np.full((H, W), np.inf)
+    lab = np.zeros((H, W), dtype=np.int32)
+    for s, (sx, sy) in enumerate(sites):
+        d2 = (ys[:, None] - sy) ** 2 + (xs[None, :] - sx) ** 2
+        closer = d2 < best  # strict: earlier sites win ties
+        best = np.where(closer, d2, best)
+        lab = np.where(closer, s, lab)
+    return lab
+
+
+def voronoi_image(H: int, W: int, C: int, regions: int, noise_sigma: float,
+                  seed: int, gradient_amp: float = 0.0, spectra: bool = False,
+                  return_labels: bool = False):
+    """Return an ``(H, W, C)`` float32 Voronoi image (and its labels if asked)."""
+    if H < 1 or W < 1 or C < 1 or regions < 1:
+        raise ValueError("H, W, C and regions must be >= 1")
+    rng = np.random.default_rng(seed)
+    sites = rng.uniform(0.0, 1.0, size=(regions, 2)) * np.array([W, H], dtype=np.float64)
+    if spectra:
+        m = rng.uniform(0.2, 0.8, size=regions)
+        qs = np.arange(1, 4, dtype=np.float64)
+        amp = rng.uniform(-1.0, 1.0, size=(regions, 3)) * (0.3 / qs)[None, :]
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=(regions, 3))
+        band = np.arange(C, dtype=np.float64) / max(C - 1, 1) * 30.0
+        spec = m[:, None] + np.sum(
+            amp[:, :, None] * np.cos(np.pi * qs[None, :, None] * band[None, None, :] / 30.0
+                                     + ph[:, :, None]), axis=1)
+        colours = np.clip(spec, 0.0, 1.0)
+    else:
+        colours = rng.uniform(0.0, 1.0, size=(regions, C))
+    lab = _nearest_site(H, W, sites)
+    img = colours[lab]  # (H, W, C) float64
+    if gradient_amp > 0.0:
+        theta = rng.uniform(0.0, 2.0 * np.pi, size=regions)
+        cdir = rng.uniform(-1.0, 1.0, size=(regions, C))
+        x = (np.arange(W, dtype=np.float64) + 0.5) / W
+        y = (np.arange(H, dtype=np.float64) + 0.5) / H
+        sxn = sites[:, 0] / W
+        syn = sites[:, 1] / H
+        proj = ((x[None, :] - sxn[lab]) * np.cos(theta)[lab]
+                + (y[:, None] - syn[lab]) * np.sin(theta)[lab])
+        img = img + gradient_amp * cdir[lab] * proj[:, :, None]
+    if noise_sigma > 0.0:
+        img = img + rng.normal(0.0, noise_sigma, size=(H, W, C))
+    img = np.clip(img, 0.0, 1.0).astype(np.float32)
+    if return_labels:
+        return img, lab
+    return img
+
+
+def voronoi_labels(H: int, W: int, regions: int, seed: int) -> np.ndarray:
+    """Ground-truth region labels of ``voronoi_image`` with the same seed."""
+    rng = np.random.default_rng(seed)
+    sites = rng.uniform(0.0, 1.0, size=(regions, 2)) * np.array([W, H], dtype=np.float64)
+    return _nearest_site(H, W, sites)
+
+
+def batch_shapes(n: int, seed: int, lo: int = 128, hi: int = 1024):
+    """Uneven, non-square image specs for the batched workload.
+
+    Returns ``n`` tuples ``(H, W, regions, sigma, image_seed)`` with sides
+    uniform in [lo, hi] (redrawn when H == W), 4-16 regions, noise sigma
+    uniform in [0.02, 0.1]; image ``i`` uses seed ``seed * 1000 + i``.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        while True:
+            H = int(rng.integers(lo, hi + 1))
+            W = int(rng.integers(lo, hi + 1))
+            if H != W:
+                break
+        regions = int(rng.integers(4, 17))
+        sigma = float(rng.uniform(0.02, 0.1))
+        out.append((H, W, regions, sigma, seed * 1000 + i))
+    return out

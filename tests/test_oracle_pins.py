@@ -1,0 +1,401 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here checks the oracle against something other than itself:
+closed forms, hand-worked values (tests/golden), the paper's printed formulas
+evaluated by brute force on tiny images (tests/brute.py), finite
+differences, invariants and an independent dense end-to-end solve.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from tests import brute
+from paper_2510_16154_amd.synth import voronoi_image
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _P(orc, **kw):
+    return orc.Params(**kw)
+
+
+# ---------------------------------------------------------------- P1 kernel
+def test_kernel_closed_form_values(orc):
+    g = json.load(open(os.path.join(GOLD, "wendland_values.json")))
+    for r, v in g["phi"]:
+        assert orc.phi(r) == pytest.approx(v, abs=1e-15)
+    for r, v in g["dphi"]:
+        assert orc.dphi(r) == pytest.approx(v, abs=1e-15)
+    # the printed sign gives a repulsive self-interaction: phi(0) = -1 (reading A1)
+    assert orc.phi(0.0, literal=True) == g["literal_phi_at_0"]
+
+
+def test_kernel_derivative_matches_fd_and_is_c2(orc):
+    h = 1e-6
+    for r in np.linspace(0.01, 0.99, 37):
+        fd = (orc.phi(r + h) - orc.phi(r - h)) / (2 * h)
+        assert orc.dphi(r) == pytest.approx(fd, rel=1e-8, abs=1e-9)
+        assert orc.dphi(r) == pytest.approx(float(brute.wendland_d(r)), rel=1e-10, abs=1e-13)
+    # C^2 at the support edge: value, slope and curvature vanish from the left
+    for r in (1 - 1e-4, 1 - 1e-5):
+        assert abs(orc.phi(r)) < 1e-14 and abs(orc.dphi(r)) < 1e-10
+    d2 = (orc.dphi(1 - 1e-6) - orc.dphi(1 - 3e-6)) / 2e-6
+    assert abs(d2) < 1e-8
+
+
+# ---------------------------------------------------------------- P2 forward vs all-pairs
+@pytest.mark.parametrize("C", [1, 3])
+def test_forward_step_equals_allpairs_sum(orc, C):
+    c = _rng(2 + C).uniform(0, 1, size=(8, 8, C))
+    P = _P(orc, K=1, R=7, s=1.0 / 64)
+    for ex, ec in [(57.0, 57.0), (2.0, 300.0), (1100.0, 5.0)]:
+        got = orc.forward_step(c, P, ex, ec)
+        want = brute.euler_allpairs(c, ex, ec, 0.25)
+        assert np.max(np.abs(got - want)) < 1e-14
+
+
+def test_forward_window_is_square_and_clipped(orc):
+    H, W, C, R = 7, 6, 2, 2
+    c = _rng(11).uniform(0, 1, size=(H, W, C))
+    P = _P(orc, K=1, R=R, s=0.05)
+    got = orc.forward_step(c, P, 30.0, 40.0)
+    X = brute.positions(H, W)
+    cf = c.reshape(-1, C)
+    F = np.zeros_like(cf)
+    for i in range(H * W):
+        ri, qi = divmod(i, W)
+        for j in range(H * W):
+            rj, qj = divmod(j, W)
+            if abs(rj - ri) > R or abs(qj - qi) > R:
+                continue
+            dxy = X[j] - X[i]
+            dc = cf[j] - cf[i]
+            F[i] += brute.wendland(0.5 * 30.0 * dxy @ dxy + 0.5 * 40.0 * dc @ dc) * dc
+    want = c + 0.25 * 0.05 * F.reshape(H, W, C)
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
+# ---------------------------------------------------------------- P3 invariants
+def test_constant_image_is_fixed_point(orc):
+    c0 = np.full((9, 11, 3), 0.37)
+    P = _P(orc, K=6, R=3)
+    traj = orc.forward_sweep(c0, P)
+    assert np.array_equal(traj[-1], c0)
+
+
+def test_mean_conservation_and_maximum_principle(orc):
+    c0 = voronoi_image(16, 20, 3, 4, 0.08, 7).astype(np.float64)
+    P = _P(orc, K=10, R=2)
+    eps = np.column_stack([np.linspace(2, 300, 10), np.linspace(10, 80, 10)])
+    traj = orc.forward_sweep(c0, P, eps)
+    m0 = c0.reshape(-1, 3).sum(0)
+    for k in range(1, 11):
+        mk = traj[k].reshape(-1, 3).sum(0)
+        assert np.max(np.abs(mk - m0)) < 1e-12 * np.max(np.abs(m0))
+        # dt * s * |W| <= 1 here, so each channel's range cannot grow
+        assert traj[k].min(axis=(0, 1)).min() >= c0.min() - 1e-14
+        assert np.all(traj[k].max(axis=(0, 1)) <= traj[k - 1].max(axis=(0, 1)) + 1e-14)
+        assert np.all(traj[k].min(axis=(0, 1)) >= traj[k - 1].min(axis=(0, 1)) - 1e-14)
+
+
+def test_equivariances(orc):
+    c0 = _rng(5).uniform(0, 1, size=(10, 10, 3))
+    P = _P(orc, K=4, R=2)
+    eps = np.column_stack([np.full(4, 120.0), np.full(4, 25.0)])
+    base = orc.forward_sweep(c0, P, eps)[-1]
+    for f in (lambda a: a[::-1], lambda a: a[:, ::-1], lambda a: a[::-1, ::-1],
+              lambda a: a.transpose(1, 0, 2), lambda a: a[:, :, [2, 0, 1]]):
+        got = orc.forward_sweep(np.ascontiguousarray(f(c0)), P, eps)[-1]
+        assert np.max(np.abs(got - f(base))) < 1e-13
+    shifted = orc.forward_sweep(c0 + 0.25, P, eps)[-1]
+    assert np.max(np.abs(shifted - (base + 0.25))) < 1e-13
+
+
+# ---------------------------------------------------------------- P4 two agents
+def test_two_agents_closed_form(orc):
+    c0 = np.array([[[0.2], [0.5]]])  # 1 x 2 image, s = 1/2
+    P = _P(orc, K=8, R=1, s=0.5)
+    ex, ec = 40.0, 7.0
+    traj = orc.forward_sweep(c0, P, np.tile([ex, ec], (8, 1)))
+    d = 0.3
+    for k in range(1, 9):
+        r = 0.5 * ex * (0.5 ** 2) + 0.5 * ec * d * d  # dx = 1/W = 1/2
+        d = d * (1 - 0.25 * float(brute.wendland(r)))
+        got = traj[k, 0, 1, 0] - traj[k, 0, 0, 0]
+        assert got == pytest.approx(d, rel=1e-14)
+        assert traj[k].sum() == pytest.approx(0.7, rel=1e-15)
+
+
+# ---------------------------------------------------------------- P5 adjoint
+def test_adjoint_step_equals_printed_jacobian_transpose(orc):
+    c = _rng(21).uniform(0, 1, size=(8, 8, 1))
+    p = _rng(22).normal(size=(8, 8, 1))
+    P = _P(orc, K=1, R=7, s=1.0 / 64)
+    for ex, ec in [(57.0, 57.0), (3.0, 400.0)]:
+        got, _ = orc.adjoint_step(c, p, P, ex, ec)
+        J = brute.jacobian_paper_c1(c, ex, ec)
+        want = p.reshape(-1) + 0.25 * J.T @ p.reshape(-1)
+        assert np.max(np.abs(got.reshape(-1) - want)) < 1e-13
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_adjoint_dot_product_with_fd_tangent(orc, C):
+    """<p, (dStep) delta> = <Step^T p, delta>, the tangent taken by central FD."""
+    H, W = 7, 9
+    c = voronoi_image(H, W, C, 3, 0.05, 31).astype(np.float64)
+    p = _rng(32).normal(size=(H, W, C))
+    P = _P(orc, K=1, R=2)
+    ex, ec = 80.0, 30.0
+    for trial in range(3):
+        delta = _rng(40 + trial).normal(size=(H, W, C))
+        h = 1e-6
+        tang = (orc.forward_step(c + h * delta, P, ex, ec) - orc.forward_step(c - h * delta, P, ex, ec)) / (2 * h)
+        lhs = np.sum(p * tang)
+        adj, _ = orc.adjoint_step(c, p, P, ex, ec)
+        rhs = np.sum(adj * delta)
+        assert lhs == pytest.approx(rhs, rel=1e-8)
+
+
+# ---------------------------------------------------------------- P6 control gradient
+def test_control_partials_equal_printed_formulas(orc):
+    c = _rng(51).uniform(0, 1, size=(8, 8, 1))
+    p = _rng(52).normal(size=(8, 8, 1))
+    P = _P(orc, K=1, R=7, s=1.0 / 64)
+    ex, ec = 90.0, 20.0
+    _, gk = orc.adjoint_step(c, p, P, ex, ec)
+    Fx, Fc = brute.deps_paper_c1(c, ex, ec)
+    assert gk[0] == pytest.approx(0.25 * np.dot(p.reshape(-1), Fx), rel=1e-12)
+    assert gk[1] == pytest.approx(0.25 * np.dot(p.reshape(-1), Fc), rel=1e-12)
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_sweep_gradient_matches_central_fd(orc, C):
+    H, W, K = 8, 8, 5
+    c0 = voronoi_image(H, W, C, 3, 0.05, 61 + C).astype(np.float64)
+    w = _rng(62).normal(size=(H, W, C))
+    P = _P(orc, K=K, R=2)
+    eps = np.column_stack([np.linspace(5, 60, K), np.linspace(15, 60, K)])
+    traj = orc.forward_sweep(c0, P, eps)
+    p0, geps = orc.adjoint_sweep(traj, P, w, eps)
+    assert np.all(geps != 0)
+
+    def ell(e=eps, x=c0):
+        return float(np.sum(w * orc.forward_sweep(x, P, e)[-1]))
+
+    scale = np.max(np.abs(geps))
+    for k in range(K):
+        for m in range(2):
+            h = 1e-4 * eps[k, m]
+            ep, em = eps.copy(), eps.copy()
+            ep[k, m] += h
+            em[k, m] -= h
+            fd = (ell(ep) - ell(em)) / (2 * h)
+            assert geps[k, m] == pytest.approx(fd, rel=1e-6, abs=1e-7 * scale)
+    # gradient in the initial state, along random directions
+    for t in range(3):
+        d = _rng(70 + t).normal(size=c0.shape)
+        h = 1e-6
+        fd = (ell(x=c0 + h * d) - ell(x=c0 - h * d)) / (2 * h)
+        assert np.sum(p0 * d) == pytest.approx(fd, rel=1e-7)
+
+
+# ---------------------------------------------------------------- P7 grad#/div
+def test_gradient_closed_forms(orc):
+    H, W = 6, 9
+    q = np.arange(W, dtype=np.float64)
+    c = np.tile((0.3 * q)[None, :, None], (H, 1, 2))
+    g = orc.grad(c)
+    assert np.allclose(g[:, 1:W - 1, 0], 0.3 * W, rtol=0, atol=1e-12)
+    assert np.all(g[:, [0, W - 1], 0] == 0) and np.all(g[:, :, 1] == 0)
+    chk = ((np.add.outer(np.arange(H), np.arange(W)) % 2).astype(np.float64))[:, :, None]
+    assert np.all(orc.grad(chk) == 0)  # stride-2 differences cannot see a 1-px checkerboard
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 1), (7, 5, 3), (1, 6, 2), (2, 2, 1), (5, 1, 1)])
+def test_gradient_equals_paper_index_rule(orc, shape):
+    c = _rng(81).uniform(0, 1, size=shape)
+    assert np.max(np.abs(orc.grad(c) - brute.grad_paper(c))) < 1e-12
+
+
+def test_divergence_is_negative_adjoint_and_matches_paper_inside(orc):
+    H, W, C = 9, 11, 2
+    c = _rng(91).normal(size=(H, W, C))
+    w = _rng(92).normal(size=(H, W, 2, C))
+    lhs = np.sum(orc.grad(c) * w)
+    rhs = -np.sum(c * orc.div(w))
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+    lit = brute.div_paper(w)
+    d = orc.div(w)
+    assert np.max(np.abs(d[2:H - 2, 2:W - 2] - lit[2:H - 2, 2:W - 2])) < 1e-12
+    lap = brute.wide_laplacian_interior(c)
+    dg = orc.div(orc.grad(c))
+    assert np.max(np.abs(dg[2:H - 2, 2:W - 2] - lap[2:H - 2, 2:W - 2])) < 1e-9
+
+
+# ---------------------------------------------------------------- P8 terminal condition
+def test_terminal_is_gradient_of_completed_square(orc):
+    H, W, C = 8, 8, 2
+    c0 = voronoi_image(H, W, C, 3, 0.05, 101).astype(np.float64)
+    c = c0 + _rng(102).normal(scale=0.05, size=c0.shape)
+    v = _rng(103).normal(scale=3.0, size=(H, W, 2, C))
+    mu = _rng(104).normal(scale=0.5, size=(H, W, 2, C))
+    P = _P(orc, alpha=50.0, rho=0.3)
+    pK, Lt = orc.terminal(c, c0, v, mu, P)
+    h = 1e-6
+    for idx in [(0, 0, 0), (3, 4, 1), (7, 7, 0), (1, 6, 1), (4, 0, 0)]:
+        cp, cm = c.copy(), c.copy()
+        cp[idx] += h
+        cm[idx] -= h
+        fd = (orc.terminal(cp, c0, v, mu, P)[1] - orc.terminal(cm, c0, v, mu, P)[1]) / (2 * h)
+        assert pK[idx] == pytest.approx(fd, rel=1e-7, abs=1e-10)
+    # printed form dx dy [-rho Lap# c + div#(mu + rho v) + alpha (c - c0)] in the interior
+    lap = brute.wide_laplacian_interior(c)
+    lit = (1.0 / (H * W)) * (-P.rho * lap + brute.div_paper(mu + P.rho * v) + P.alpha * (c - c0))
+    assert np.max(np.abs(pK[2:H - 2, 2:W - 2] - lit[2:H - 2, 2:W - 2])) < 1e-12
+    # L~ = L + dx dy / (2 rho) sum |mu|^2 (eq. complete_square)
+    E = orc.energies(c, c0, v, mu, P)
+    assert E["Ltilde"] == pytest.approx(E["L"] + np.sum(mu ** 2) / (2 * P.rho * H * W), rel=1e-13)
+    assert Lt == pytest.approx(E["Ltilde"], rel=1e-15)
+
+
+# ---------------------------------------------------------------- P9 shrinkage
+def test_shrinkage_matches_numerical_minimiser(orc):
+    rho = 0.5
+    P = _P(orc, rho=rho, gamma=rho)
+    # a 1 x 3 grey image whose middle pixel has a = grad c - mu/rho = (gx, gy - mu_y/rho)
+    for cl, cr, muy in [(0.0, 1.0, 0.3), (0.0, 0.2, 0.1), (0.5, 0.4, -0.9), (0.3, 0.3, 0.0)]:
+        c = np.array([[[cl], [0.7], [cr]]])
+        mu = np.zeros((1, 3, 2, 1))
+        mu[0, 1, 1, 0] = muy
+        v, _, _ = orc.pd_step(c, c, None, mu, P, update_mu=False)
+        a = np.array([(cr - cl) / (2.0 / 3.0), 0.0 - muy / rho])
+        wmin, fmin = brute.shrink_bruteforce(a, rho)
+        assert np.allclose(v[0, 1, :, 0], wmin, atol=1e-6)
+        assert (np.linalg.norm(a) <= 1 / rho) == np.all(v[0, 1] == 0)
+    # joint shrinkage over 2C components
+    a = _rng(111).normal(size=6) * 3
+    c = np.zeros((1, 1, 3))
+    mu = (-a * rho).reshape(1, 1, 2, 3)
+    v, _, _ = orc.pd_step(c, c, None, mu, P, update_mu=False)
+    wmin, _ = brute.shrink_bruteforce(a, rho)
+    assert np.allclose(v.reshape(-1), wmin, atol=1e-6)
+
+
+# ---------------------------------------------------------------- P10 energies
+def test_energies_of_a_step_edge(orc):
+    H, W, hgt, q0 = 6, 10, 0.4, 5
+    c = np.zeros((H, W, 1))
+    c[:, q0:] = hgt
+    P = _P(orc, alpha=123.0)
+    E = orc.energies(c, c, None, None, P)
+    assert E["TV"] == pytest.approx(hgt, rel=1e-14)  # two columns carry |gx| = h / (2 dx)
+    assert E["fid"] == 0.0
+    v = orc.grad(c)
+    E2 = orc.energies(c, c, v, np.zeros_like(v), P)
+    assert E2["L"] == pytest.approx(E2["K"], rel=1e-14)
+    assert E2["r_abs"] == 0.0
+
+
+# ---------------------------------------------------------------- P11/P12 solver invariants
+def test_armijo_accepts_only_decreasing_steps(orc):
+    c0 = voronoi_image(12, 12, 3, 3, 0.05, 121).astype(np.float64)
+    P = _P(orc, K=6, R=2, alpha=20.0, max_outer=2, max_inner=6)
+    res = orc.solve(c0, P)
+    tr = res["trace"]
+    taken = res["decisions"] > 0
+    assert taken.sum() >= 4
+    assert np.all(tr[..., 1][taken] <= tr[..., 0][taken])
+    # within one control argmin, the objective entering each DAL step does not increase
+    for j in range(2):
+        phis = tr[j, :, 0][tr[j, :, 0] != 0]
+        assert np.all(np.diff(phis) <= 1e-15 * np.abs(phis[:-1]))
+    assert np.all((res["eps"] >= 2.0) & (res["eps"] <= 1100.0))
+
+
+def test_constant_image_solve_returns_input(orc):
+    c0 = np.full((8, 9, 2), 0.6)
+    P = _P(orc, K=5, R=2, max_outer=2, max_inner=3)
+    res = orc.solve(c0, P)
+    assert np.array_equal(res["c"], c0)
+    assert res["stats"]["r_rel"] == 0.0 and res["stats"]["K"] == 0.0
+    assert np.all(res["eps"] == 57.0)  # G = 0: no control update
+
+
+def test_admm_lowers_the_tv_energy(orc):
+    c0 = voronoi_image(24, 24, 3, 4, 0.08, 131).astype(np.float64)
+    P = _P(orc, K=10, R=2, alpha=20.0, max_outer=3, max_inner=5)
+    E0 = orc.energies(c0, c0, None, None, P)
+    res = orc.solve(c0, P)
+    assert res["stats"]["K"] < E0["K"]
+
+
+# ---------------------------------------------------------------- P13 dual fixed point
+def test_dual_fixed_point_is_the_tv_certificate(orc):
+    H, W, C = 10, 12, 2
+    c = voronoi_image(H, W, C, 3, 0.0, 141).astype(np.float64)
+    P = _P(orc, alpha=10.0, rho=0.05, gamma=0.05)
+    v = mu = None
+    for _ in range(400):
+        v, mu, E = orc.pd_step(c, c, v, mu, P, update_mu=True)
+    g = orc.grad(c)
+    ng = np.sqrt(np.sum(g.reshape(H, W, -1) ** 2, axis=2))
+    nz = ng > 0
+    unit = -g.reshape(H, W, -1)[nz] / ng[nz][:, None]
+    assert np.allclose(mu.reshape(H, W, -1)[nz], unit, atol=1e-12)
+    nmu = np.sqrt(np.sum(mu.reshape(H, W, -1) ** 2, axis=2))
+    assert np.all(nmu[~nz] <= 1 + 1e-12)
+    assert np.allclose(v, g, atol=1e-9)
+    assert E["L"] == pytest.approx(E["K"], rel=1e-12)
+
+
+# ---------------------------------------------------------------- P14 end-to-end brute force
+def test_solve_equals_dense_bruteforce(orc):
+    H, W = 6, 6
+    c0 = voronoi_image(H, W, 1, 3, 0.05, 151).astype(np.float64)
+    K, M, Pn = 3, 2, 3
+    P = _P(orc, K=K, R=7, s=1.0 / (H * W), alpha=5.0, rho=0.05, gamma=0.05, max_outer=M, max_inner=Pn)
+    res = orc.solve(c0, P)
+    cb, eb, vb, mb, taus = brute.solve_bruteforce(c0, K, 0.25, np.full((K, 2), 57.0), 5.0, 0.05, 0.05, M, Pn,
+                                                  (2.0, 2.0), (1100.0, 1100.0))
+    assert np.array_equal(res["decisions"], taus)
+    assert np.max(np.abs(res["c"] - cb)) < 1e-12
+    assert np.max(np.abs(res["eps"] - eb)) < 1e-9 * 1100
+    N = H * W
+    v = res["v"][:, :, :, 0]
+    assert np.max(np.abs(v[:, :, 0].ravel() - vb[:N])) < 1e-9
+    assert np.max(np.abs(v[:, :, 1].ravel() - vb[N:])) < 1e-9
+
+
+# ---------------------------------------------------------------- replay and determinism
+def test_replay_reproduces_free_run_and_threads_do_not_matter(orc):
+    c0 = voronoi_image(16, 16, 3, 4, 0.05, 161).astype(np.float64)
+    P = _P(orc, K=8, R=2, alpha=20.0, max_outer=2, max_inner=4)
+    n0 = orc.num_threads()
+    try:
+        orc.set_num_threads(1)
+        a = orc.solve(c0, P)
+        orc.set_num_threads(max(2, n0))
+        b = orc.solve(c0, P)
+    finally:
+        orc.set_num_threads(n0)
+    assert np.array_equal(a["c"], b["c"]) and np.array_equal(a["decisions"], b["decisions"])
+    r = orc.solve(c0, P, decisions=a["decisions"])
+    assert np.array_equal(r["c"], a["c"]) and np.array_equal(r["eps"], a["eps"])
+
+
+def test_default_parameters_are_the_papers(orc):
+    g = json.load(open(os.path.join(GOLD, "paper_parameters.json")))
+    P = orc.Params()
+    assert P.dt == g["dt"]["value"]
+    assert list(P.eps_min) == [g["eps_box"]["value"][0]] * 2
+    assert list(P.eps_max) == [g["eps_box"]["value"][1]] * 2
+    assert P.eps_init == g["eps_init"]["value"]
+    assert (P.sigma0, P.armijo_b, P.armijo_c) == (g["sigma0"]["value"], g["armijo_b"]["value"],
+                                                 g["armijo_c"]["value"])
+    assert (P.rho, P.gamma) == (g["rho"]["value"], g["gamma"]["value"])
