@@ -1,0 +1,180 @@
+"""Benchmark of the solver's hot path on one MI355X.
+
+Workload: 512 x 512 RGB Voronoi image (12 regions, colour gradients of
+amplitude 0.1, noise sigma 0.08), window radius R = 5, K = 50 Euler steps.
+
+One timed step is one pass over the whole hot path, as one iteration of the
+control argmin runs it: terminal condition and objective, adjoint sweep with
+the control-gradient reduction (K adjoint steps), the projected control
+update, the forward sweep storing the trajectory (K steps), the objective of
+the trial, then one shrinkage / multiplier update, each with the host reads
+the solver does.  value = agent-steps per second = H * W * K / (step time),
+counting one forward and one adjoint sweep per step.
+
+Also reported: forward and adjoint sweep times alone (HIP events on the
+stream the kernels run on), the roofline of the dominant kernel (the adjoint
+step), and the FP64 CPU oracle timed on a bounded sample of the same work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def window_pairs(H: int, W: int, R: int) -> int:
+    """Ordered in-image pairs (i, j), j != i, with |row diff|, |col diff| <= R."""
+    rows = sum((H - abs(a)) for a in range(-R, R + 1) if abs(a) < H)
+    cols = sum((W - abs(b)) for b in range(-R, R + 1) if abs(b) < W)
+    return rows * cols - H * W
+
+
+def flops_per_pair(C: int, kind: str) -> int:
+    # forward: D (C), |D|^2 (2C), r (2), phi (6), accumulation (2C)
+    # adjoint: forward terms + phi' + (p_j - p_i), D.dp, two accumulations, two gradient integrands
+    return 5 * C + 8 if kind == "fwd" else 12 * C + 18
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=10,
+                    help="Euler steps of the oracle sample (forward + adjoint) on the full image")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
+              "single device, see the design notes for how it would shard)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2510_16154_amd as A
+    from paper_2510_16154_amd.workloads import VORONOI512 as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    H, W, C, K, R = wl.H, wl.W, wl.C, wl.K, wl.R
+    params = wl.params()
+    c0n = wl.image()
+    c0 = torch.as_tensor(c0n, device=dev)
+    eps = torch.full((K, 2), params.eps_init, dtype=torch.float32, device=dev)
+    eps_try = eps.clone()
+    v = torch.zeros((H, W, 2, C), dtype=torch.float32, device=dev)
+    mu = torch.zeros_like(v)
+    ws_f = torch.empty(max(A.abc_workspace_bytes(A.ABC_WS_FORWARD, H, W, C, params), 1), dtype=torch.uint8,
+                       device=dev)
+    ws_a = torch.empty(A.abc_workspace_bytes(A.ABC_WS_ADJOINT, H, W, C, params), dtype=torch.uint8, device=dev)
+    traj = torch.empty((K + 1, H, W, C), dtype=torch.float32, device=dev)
+    traj2 = torch.empty_like(traj)
+    g0 = torch.empty_like(c0)
+    geps = torch.empty((K, 2), dtype=torch.float32, device=dev)
+
+    A.abc_forward_dynamics(c0, eps, params, traj=traj, ws=ws_f)
+    A.abc_pd_step(traj[-1], c0, v, mu, params, update_mu=False, want_stats=False)
+
+    def step():
+        gK, phi0 = A.abc_pd_terminal(traj[-1], c0, v, mu, params)
+        A.abc_adjoint_dynamics(traj, eps, params, gK, g0=g0, geps=geps, ws=ws_a)
+        G = geps.cpu().double().numpy() / params.dt
+        e_new = np.clip(eps.cpu().double().numpy() - 1.0 * G, params.eps_min[0], params.eps_max[0])
+        eps_try.copy_(torch.as_tensor(e_new, dtype=torch.float32))
+        A.abc_forward_dynamics(c0, eps_try, params, traj=traj2, ws=ws_f)
+        _, phit = A.abc_pd_terminal(traj2[-1], c0, v, mu, params, want_gradient=False)
+        return A.abc_pd_step(traj[-1], c0, v, mu, params, update_mu=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+
+    # sweep-only timings with HIP events on the kernels' stream
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = 10
+    fwd_ms, adj_ms = [], []
+    gK = torch.randn((H, W, C), generator=torch.Generator().manual_seed(0)).to(dev)
+    for _ in range(reps):
+        ev[0].record(stream)
+        A.abc_forward_dynamics(c0, eps, params, traj=traj, ws=ws_f)
+        ev[1].record(stream)
+        A.abc_adjoint_dynamics(traj, eps, params, gK, g0=g0, geps=geps, ws=ws_a)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        fwd_ms.append(ev[0].elapsed_time(ev[1]))
+        adj_ms.append(ev[1].elapsed_time(ev[2]))
+    t_fwd = float(np.median(fwd_ms)) * 1e-3
+    t_adj = float(np.median(adj_ms)) * 1e-3
+
+    pairs = window_pairs(H, W, R)
+    adj_launch = t_adj / K  # one adjoint-step launch (sweep time / K, launch gaps included)
+    adj_flops = pairs * flops_per_pair(C, "adj")
+    fwd_flops = pairs * flops_per_pair(C, "fwd")
+    achieved = adj_flops / adj_launch / 1e12
+    value = H * W * K / t_step
+    out = {
+        "metric": "agent-steps/sec (fwd+adjoint)",
+        "value": value,
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Voronoi image)",
+        "config": {"workload": wl.name, "H": H, "W": W, "C": C, "R": R, "K": K,
+                   "step": "terminal+adjoint sweep+control update+forward sweep+objective+pd_step"},
+        "sweeps": {"fwd_ms": t_fwd * 1e3, "adj_ms": t_adj * 1e3,
+                   "agent_steps_per_s_sweeps_only": H * W * K / (t_fwd + t_adj),
+                   "fwd_tflops": fwd_flops * K / t_fwd / 1e12, "adj_tflops": adj_flops * K / t_adj / 1e12},
+        "roofline": {"kernel": "adj_step_kernel<3,5>", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": None, "flops_per_launch": adj_flops, "launch_ms": adj_launch * 1e3},
+        "last_step_stats": {k: st[k] for k in ("K", "TV", "fid", "r_rel")},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c0n, wl, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline(c0n, wl, ksample: int) -> dict:
+    """The FP64 oracle on the host cores: forward + adjoint over `ksample` Euler
+    steps of the same image (the sweep cost is linear in K), scaled to the
+    benchmark's unit."""
+    from oracle import oracle as O
+    P = O.Params(K=ksample, R=wl.R)
+    eps = np.full((ksample, 2), 57.0)
+    t0 = time.perf_counter()
+    traj = O.forward_sweep(c0n, P, eps)
+    pK = np.random.default_rng(0).normal(size=c0n.shape)
+    O.adjoint_sweep(traj, P, pK, eps)
+    dt = time.perf_counter() - t0
+    return {"value": wl.H * wl.W * ksample / dt, "unit": "agent-steps/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"forward+adjoint sweep, {ksample} of {wl.K} Euler steps, full {wl.H}x{wl.W}x{wl.C} "
+                      f"image, R={wl.R}, FP64 ({dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,210 @@
+/*
+ * abc.h -- C ABI of the gfx950 (AMD Instinct MI355X) solver for the
+ * agent-based optimal-control method of "Agent-Based Optimal Control for
+ * Image Processing" (Oliviero, Cacace, Visconti, arXiv 2510.16154).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays are FP32 and live in DEVICE memory unless marked "host".  The
+ *    caller allocates all of them (inputs, outputs and the workspace); the
+ *    library never allocates or frees memory the caller can see.
+ *  - Colour fields are H x W x C, channel fastest ("HWC"), row 0 first in
+ *    memory.  Two-vector fields (the splitting variable v, the multiplier
+ *    mu, gradients) are H x W x 2 x C: component 0 along columns (x),
+ *    component 1 along rows (y).  The paper orders rows bottom to top
+ *    (Sec. 2); with rows in memory order the y-components of v and mu flip
+ *    sign and nothing else changes.
+ *  - Controls are K x 2: eps[2k] = eps_x on step k, eps[2k+1] = eps_c
+ *    (piecewise constant in time).
+ *  - Grid spacing dx = 1/W, dy = 1/H (Def. 3.1); positions are normalised.
+ *  - All work is ordered on `stream` (a hipStream_t; NULL = the null stream).
+ *    Calls that return host scalars synchronise that stream.
+ *  - Return value: ABC_OK (0), a negative error or a positive warning.
+ *    Arguments are validated before anything is launched.  No C++ exception
+ *    crosses this boundary.  abc_last_error() describes the last failure of
+ *    the calling thread.
+ *  - Adjoint sign: the library returns gradients (p = dl/dc), i.e. p is minus
+ *    the adjoint state lambda of the paper's optimality system (Sec. 3.1).
+ */
+#ifndef ABC_H
+#define ABC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABC_OK 0
+#define ABC_EINVAL (-1)     /* bad argument, size or workspace too small          */
+#define ABC_EHIP (-2)       /* HIP runtime failure (message has the HIP error)    */
+#define ABC_ENONFINITE (-3) /* NaN or Inf found in an input image or control      */
+#define ABC_ENOCONV 1       /* warning: caps reached before tol_alm; outputs valid */
+
+#define ABC_MAX_CHANNELS 64
+#define ABC_MAX_RADIUS 16
+
+/* Solver parameters.  abc_default_params() fills the paper's values
+ * (Sec. 3.2: dt = 0.25, E = [2,1100]^2, eps0 = 57, sigma0 = 1, b = 1/2,
+ * c = 1e-4; Sec. 4.2: rho = gamma = 1e-2). */
+typedef struct abc_params {
+    int32_t K;           /* explicit Euler steps (horizon T = K dt)                 */
+    float dt;            /* time step                                               */
+    int32_t R;           /* interaction window radius in pixels (square window)     */
+    float inv_norm;      /* s scaling the interaction sum; 0 => 1/min(N,(2R+1)^2)  */
+    float eps_min[2];    /* control box E = [eps_min, eps_max] per component       */
+    float eps_max[2];
+    float eps_init;      /* control used where eps is not supplied                  */
+    float alpha;         /* fidelity weight                                         */
+    float rho;           /* penalty of the splitting (eq. cost_tv_regular)          */
+    float gamma;         /* multiplier ascent step (eq. dual_ascent)                */
+    int32_t max_outer;   /* multiplier iterations M (Alg. 2)                        */
+    int32_t max_inner;   /* DAL iterations per control argmin P (Alg. 1)            */
+    int32_t max_ls;      /* cap on Armijo trials per DAL iteration                  */
+    double tol_alm;      /* stop when r_rel < tol_alm; 0 => run max_outer           */
+    double tol_dal;      /* stop the inner loop when |dPhi|/|Phi| < tol_dal; 0 => P */
+    double sigma0;       /* initial Armijo step                                     */
+    double armijo_b;     /* Armijo factor b in (0,1)                                */
+    double armijo_c;     /* sufficient-decrease constant c in (0,1)                 */
+    int32_t ckpt_every;  /* 0 => full trajectory; k > 0 => checkpoint every k steps  */
+    int32_t tile_x;      /* interaction tile width in pixels; 0 => library default  */
+    int32_t tile_y;      /* interaction tile height in pixels; 0 => library default */
+} abc_params;
+
+/* Statistics of a solve or of one primal/dual update (host struct). */
+typedef struct abc_stats {
+    int32_t status;      /* ABC_OK or ABC_ENOCONV                                   */
+    int32_t outer_iters; /* multiplier iterations run                               */
+    int32_t inner_iters; /* DAL iterations run (adjoint sweeps)                     */
+    int32_t ls_evals;    /* Armijo trials (forward sweeps after the first)          */
+    double K;            /* TV + fidelity energy (eq. cost_TV)                      */
+    double TV, fid;      /* its two parts                                           */
+    double L;            /* regularised Lagrangian (eq. cost_tv_regular)            */
+    double Ltilde;       /* completed square (eq. complete_square)                  */
+    double r_rel;        /* |v - grad c| / max(|grad c|, |v|)                        */
+    double r_abs;        /* sqrt(dx dy sum |v - grad c|^2)                           */
+    double gap_rel;      /* |L_j - L_{j-1}| / |L_{j-1}| (NaN after one iteration)    */
+    double phi_first;    /* inner objective at the first DAL iteration              */
+    double phi_last;     /* inner objective at the last DAL iteration               */
+} abc_stats;
+
+/* Workspace kinds for abc_workspace_bytes(). */
+#define ABC_WS_SOLVE 0
+#define ABC_WS_FORWARD 1
+#define ABC_WS_ADJOINT 2
+#define ABC_WS_PD 3
+
+/* Library version, major*10000 + minor*100 + patch. */
+int abc_version(void);
+
+/* Description of the calling thread's last failure ("" if none).  Valid until
+ * the next call on the same thread. */
+const char* abc_last_error(void);
+
+/* Fill *p with the paper's parameter values (see abc_params).  Host only.
+ * K = 20, R = 2, alpha = 3000, M = 5, P = 50, max_ls = 40 are this library's
+ * defaults where the paper gives none. */
+int abc_default_params(abc_params* p);
+
+/* Bytes of device workspace the entry point `kind` (ABC_WS_*) needs for an
+ * H x W x C image under *p.  Host only; launches nothing. */
+int abc_workspace_bytes(int kind, int H, int W, int C, const abc_params* p, size_t* bytes);
+
+/* Number of trajectory slots abc_forward_dynamics writes: K + 1 when
+ * p->ckpt_every == 0, else ceil(K / ckpt_every) + 1 (slot m holds the state
+ * after min(m * ckpt_every, K) steps).  Host only. */
+int abc_traj_slots(const abc_params* p, int* slots);
+
+/* Forward dynamics (eq. MAsystem with the distance of eq. ellipsoid, the
+ * Wendland kernel of eq. kernel, explicit Euler, Sec. 3.2):
+ *   c_i <- c_i + dt s sum_{|a|,|b| <= R, j inside} phi(r_ij) (c_j - c_i),
+ *   r_ij = eps_x/2 ((b dx)^2 + (a dy)^2) + eps_c/2 |c_j - c_i|^2,
+ *   phi(r) = (1 + 4 r)(1 - r)^4 on [0,1], 0 beyond.
+ * c0: H x W x C.  eps: K x 2.  traj: abc_traj_slots() fields of H x W x C;
+ * slot 0 receives a copy of c0.  ws: ABC_WS_FORWARD bytes (may be 0 when
+ * ckpt_every == 0).  Asynchronous. */
+int abc_forward_dynamics(const float* c0, int H, int W, int C, const float* eps,
+                         const abc_params* p, float* traj, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Discrete adjoint of abc_forward_dynamics (transpose of each Euler step,
+ * Jacobians of Sec. 3.1) and the gradient in the controls:
+ *   p^k_i = p^{k+1}_i + dt s sum_j [ phi (p_j - p_i)
+ *                                   + eps_c phi' D_ij (D_ij . (p_j - p_i)) ],
+ *   dl/deps_x^k = dt s/2 sum_i sum_j phi' d_ij^2   (p_i . D_ij),
+ *   dl/deps_c^k = dt s/2 sum_i sum_j phi' |D_ij|^2 (p_i . D_ij),
+ * with D_ij = c^k_j - c^k_i, phi at (c^k, eps^k) and p = p^{k+1}.
+ * traj: as written by abc_forward_dynamics with the same p (checkpointed
+ * trajectories are recomputed segment by segment inside ws).  gK = dl/dc^K
+ * (H x W x C).  g0 receives dl/dc^0 (may equal gK).  geps receives K x 2
+ * values dl/deps^k.  ws: ABC_WS_ADJOINT bytes.  Asynchronous. */
+int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* eps,
+                         const abc_params* p, const float* gK, float* g0, float* geps,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Terminal condition of the adjoint for the completed-square functional
+ * (eq. complete_square, eq. admm_terminal with div = -grad#^T):
+ *   gK = dx dy [ div(mu + rho (v - grad# cK)) + alpha (cK - c0) ],
+ * and, when Ltilde (host) is non-NULL, the value of L~(cK, v, mu).
+ * cK, c0: H x W x C; v, mu: H x W x 2 x C (NULL = zero).  gK may be NULL
+ * (objective only).  ws: ABC_WS_PD bytes.  Synchronises when Ltilde != NULL. */
+int abc_pd_terminal(const float* cK, const float* c0, const float* v, const float* mu,
+                    int H, int W, int C, const abc_params* p, float* gK, double* Ltilde,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* One primal/dual update of the splitting (Alg. 2, eq. soft_threshold and
+ * eq. dual_ascent): with g = grad# cK and a = g - mu/rho per pixel over all
+ * 2C components,
+ *   v = (|a| - 1/rho) a/|a| if |a| > 1/rho, else 0;
+ *   mu <- mu + gamma (v - g)             (only when update_mu != 0).
+ * v, mu: H x W x 2 x C, updated in place (mu is read even when
+ * update_mu == 0).  st (host, may be NULL) receives the energies and
+ * residuals at (cK, v, mu) after the update; then the stream is
+ * synchronised.  ws: ABC_WS_PD bytes. */
+int abc_pd_step(const float* cK, const float* c0, int H, int W, int C, const abc_params* p,
+                float* v, float* mu, int update_mu, abc_stats* st, void* ws, size_t ws_bytes,
+                void* stream);
+
+/* Optional record / replay of the control argmin for abc_solve (host arrays,
+ * each may be NULL).  Slots are [max_outer][max_inner], one per DAL
+ * iteration, in order.
+ *   decisions_in:  accepted step tau to take in each slot instead of running
+ *                  the line search; a slot <= 0 ends that inner loop.
+ *   decisions_out: the accepted step of each slot of this run (0 = none).
+ *   eps_replay:    [slots][K][2] controls to adopt after each accepted step
+ *                  instead of Pi_E(eps - tau G) (needs decisions_in).  The
+ *                  gradient is still computed and logged.
+ *   grad_out:      [slots][K][2] control gradient G (FP64) of each DAL
+ *                  iteration (dPhi/deps^k divided by dt).
+ *   phi_out:       [slots][3] objective before the step, after it, trials. */
+typedef struct abc_solve_log {
+    const double* decisions_in;
+    double* decisions_out;
+    const double* eps_replay;
+    double* grad_out;
+    double* phi_out;
+} abc_solve_log;
+
+/* Full solve: method of multipliers (Alg. 2) whose control argmin is the
+ * direct-adjoint loop with a two-way projected Armijo search (Alg. 1 with the
+ * terminal condition above).  Returns the final colour field c(T) for the
+ * optimised controls ("the quantised field").
+ *   c0: H x W x C input image.
+ *   eps: K x 2 controls in/out, or NULL (start from eps_init, not returned).
+ *   mu: H x W x 2 x C multiplier in/out, or NULL (start from 0, not returned).
+ *   v_out: H x W x 2 x C final splitting variable, or NULL.
+ *   c_out: H x W x C final field.
+ *   ws: ABC_WS_SOLVE bytes.  st: host, may be NULL.
+ *   log: host, may be NULL (see abc_solve_log).
+ * Returns ABC_OK, or ABC_ENOCONV when tol_alm > 0 was not reached within
+ * max_outer iterations.  Synchronises the stream before returning. */
+int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* eps, float* mu,
+              float* v_out, float* c_out, void* ws, size_t ws_bytes, void* stream, abc_stats* st,
+              abc_solve_log* log);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABC_H */

@@ -471,7 +471,9 @@ void or_pd_step(const double* c, const double* c0, int H, int W, int C, const or
 /* the inner loop ended without a step.  With decisions_in the search is */
 /* replaced by the recorded steps (replay).  trace_out, when given, gets */
 /* three doubles per DAL iteration: Phi before the step, Phi after it    */
-/* (0 when no step was taken) and the number of trials.                  */
+/* (0 when no step was taken) and the number of trials.  eps_log and     */
+/* grad_log ([max_outer][max_inner][K][2]) receive the controls after    */
+/* each accepted step and the gradient G of each DAL iteration.          */
 
 static double clampd(double x, double lo, double hi)
 {
@@ -507,7 +509,8 @@ static int armijo_trial(const double* c0, int H, int W, int C, const or_params* 
 int or_solve(const double* c0, int H, int W, int C, const or_params* P,
              double* eps /* [K*2] in/out */, double* mu /* [N*2C] in/out */,
              double* v /* [N*2C] out */, double* cK /* [N*C] out */,
-             const double* decisions_in, double* decisions_out, double* trace_out, or_stats* st)
+             const double* decisions_in, double* decisions_out, double* trace_out,
+             double* eps_log, double* grad_log, or_stats* st)
 {
     if (!c0 || !eps || !mu || !v || !cK || H < 1 || W < 1 || C < 1 || P->K < 1 || P->R < 0 ||
         P->dt <= 0 || P->rho <= 0 || P->max_outer < 0 || P->max_inner < 0 || P->max_ls < 1)
@@ -534,6 +537,9 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
         for (int k = 0; k < P->max_outer * P->max_inner; ++k) decisions_out[k] = 0.0;
     if (trace_out)
         for (int k = 0; k < 3 * P->max_outer * P->max_inner; ++k) trace_out[k] = 0.0;
+    const size_t nlog = (size_t)P->max_outer * P->max_inner * 2 * (size_t)P->K;
+    if (eps_log) memset(eps_log, 0, nlog * sizeof(double));
+    if (grad_log) memset(grad_log, 0, nlog * sizeof(double));
 
     double sigma = P->sigma0;
     /* Alg. 2: forward integration, then v^(0) = argmin_v L(c^(0), v, mu^(0)). */
@@ -563,6 +569,7 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
             }
             S.inner_iters++;
             if (trace_out) trace_out[3 * slot + 0] = phi0;
+            if (grad_log) memcpy(grad_log + (size_t)slot * 2 * K, G, 2 * (size_t)K * sizeof(double));
             if (decisions_in && decisions_in[slot] <= 0.0) break;
             if (!decisions_in && all_zero) break;
 
@@ -625,6 +632,7 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
             { double* t = base; base = cand; cand = t; }
             if (decisions_out) decisions_out[slot] = accepted;
             if (trace_out) trace_out[3 * slot + 1] = phi_acc;
+            if (eps_log) memcpy(eps_log + (size_t)slot * 2 * K, eps, 2 * (size_t)K * sizeof(double));
             if (P->tol_dal > 0.0 && fabs(phi_acc - phi0) < P->tol_dal * fabs(phi0)) break;
         }
         /* v- and mu-updates (Alg. 2, eq. soft_threshold and eq. dual_ascent) */

@@ -116,7 +116,7 @@ def lib():
         L.or_pd_step.argtypes = [_dp, _dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params), _dp, _dp,
                                  ct.c_int, ct.POINTER(_Energies)]
         L.or_solve.argtypes = [_dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params), _dp, _dp, _dp, _dp,
-                               _dp, _dp, _dp, ct.POINTER(_Stats)]
+                               _dp, _dp, _dp, _dp, _dp, ct.POINTER(_Stats)]
         L.or_solve.restype = ct.c_int
         L.or_num_threads.restype = ct.c_int
         L.or_set_num_threads.argtypes = [ct.c_int]
@@ -271,7 +271,9 @@ def solve(c0, P: Params, eps=None, mu=None, decisions=None):
     to replay instead of running the line search.  Returns a dict with the
     final field ``c``, ``eps``, ``v``, ``mu``, the decision log, a per-DAL
     iteration trace ``(max_outer, max_inner, 3)`` = (Phi before, Phi after,
-    trials) and stats.
+    trials), the controls after every accepted step ``eps_log`` and the
+    gradient of every DAL iteration ``grad_log`` (both ``(M, P, K, 2)``) and
+    stats.
     """
     c0 = _f64(c0)
     H, W, C = c0.shape
@@ -282,11 +284,14 @@ def solve(c0, P: Params, eps=None, mu=None, decisions=None):
     dec_out = np.zeros((max(P.max_outer, 1), max(P.max_inner, 1)))
     dec_in = None if decisions is None else _f64(decisions).reshape(P.max_outer, P.max_inner).copy()
     trace = np.zeros((max(P.max_outer, 1), max(P.max_inner, 1), 3))
+    eps_log = np.zeros((max(P.max_outer, 1), max(P.max_inner, 1), P.K, 2))
+    grad_log = np.zeros_like(eps_log)
     st = _Stats()
     pc = P.to_c(H, W)
     rc = lib().or_solve(_ptr(c0), H, W, C, ct.byref(pc), _ptr(e), _ptr(m), _ptr(v), _ptr(cK),
-                        _ptr(dec_in), _ptr(dec_out), _ptr(trace), ct.byref(st))
+                        _ptr(dec_in), _ptr(dec_out), _ptr(trace), _ptr(eps_log), _ptr(grad_log), ct.byref(st))
     if rc != 0:
         raise ValueError(f"oracle solve failed with code {rc}")
     stats = {n: getattr(st, n) for n, _ in _Stats._fields_}
-    return {"c": cK, "eps": e, "v": v, "mu": m, "decisions": dec_out, "trace": trace, "stats": stats}
+    return {"c": cK, "eps": e, "v": v, "mu": m, "decisions": dec_out, "trace": trace, "eps_log": eps_log,
+            "grad_log": grad_log, "stats": stats}

@@ -1,0 +1,307 @@
+"""Thin ctypes binding of ``libabc.so`` (declared in ``include/abc.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Tensors must be float32, contiguous and on the current HIP device; work is
+ordered on torch's current stream.  The library must be built
+(``python -m paper_2510_16154_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import re
+from dataclasses import dataclass, fields
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "abc.h")
+
+ABC_OK, ABC_EINVAL, ABC_EHIP, ABC_ENONFINITE, ABC_ENOCONV = 0, -1, -2, -3, 1
+ABC_WS_SOLVE, ABC_WS_FORWARD, ABC_WS_ADJOINT, ABC_WS_PD = 0, 1, 2, 3
+
+
+class AbcParams(ct.Structure):
+    _fields_ = [
+        ("K", ct.c_int32), ("dt", ct.c_float), ("R", ct.c_int32), ("inv_norm", ct.c_float),
+        ("eps_min", ct.c_float * 2), ("eps_max", ct.c_float * 2), ("eps_init", ct.c_float),
+        ("alpha", ct.c_float), ("rho", ct.c_float), ("gamma", ct.c_float),
+        ("max_outer", ct.c_int32), ("max_inner", ct.c_int32), ("max_ls", ct.c_int32),
+        ("tol_alm", ct.c_double), ("tol_dal", ct.c_double),
+        ("sigma0", ct.c_double), ("armijo_b", ct.c_double), ("armijo_c", ct.c_double),
+        ("ckpt_every", ct.c_int32), ("tile_x", ct.c_int32), ("tile_y", ct.c_int32),
+    ]
+
+
+class AbcSolveLog(ct.Structure):
+    _fields_ = [("decisions_in", ct.POINTER(ct.c_double)), ("decisions_out", ct.POINTER(ct.c_double)),
+                ("eps_replay", ct.POINTER(ct.c_double)), ("grad_out", ct.POINTER(ct.c_double)),
+                ("phi_out", ct.POINTER(ct.c_double))]
+
+
+class AbcStats(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("outer_iters", ct.c_int32), ("inner_iters", ct.c_int32),
+                ("ls_evals", ct.c_int32)] + [(n, ct.c_double) for n in (
+                    "K", "TV", "fid", "L", "Ltilde", "r_rel", "r_abs", "gap_rel", "phi_first", "phi_last")]
+
+
+@dataclass
+class Params:
+    """Python mirror of ``abc_params``; defaults are the library's (``abc_default_params``)."""
+    K: int = 20
+    dt: float = 0.25
+    R: int = 2
+    inv_norm: float = 0.0
+    eps_min: tuple = (2.0, 2.0)
+    eps_max: tuple = (1100.0, 1100.0)
+    eps_init: float = 57.0
+    alpha: float = 3000.0
+    rho: float = 1e-2
+    gamma: float = 1e-2
+    max_outer: int = 5
+    max_inner: int = 50
+    max_ls: int = 40
+    tol_alm: float = 0.0
+    tol_dal: float = 0.0
+    sigma0: float = 1.0
+    armijo_b: float = 0.5
+    armijo_c: float = 1e-4
+    ckpt_every: int = 0
+    tile_x: int = 0
+    tile_y: int = 0
+
+    def to_c(self) -> AbcParams:
+        p = AbcParams()
+        for f in fields(self):
+            val = getattr(self, f.name)
+            if f.name in ("eps_min", "eps_max"):
+                arr = getattr(p, f.name)
+                arr[0], arr[1] = float(val[0]), float(val[1])
+            else:
+                setattr(p, f.name, val)
+        return p
+
+    @staticmethod
+    def from_c(p: AbcParams) -> "Params":
+        kw = {}
+        for f in fields(Params):
+            v = getattr(p, f.name)
+            kw[f.name] = (float(v[0]), float(v[1])) if f.name in ("eps_min", "eps_max") else v
+        return Params(**kw)
+
+    def replace(self, **kw) -> "Params":
+        d = {f.name: getattr(self, f.name) for f in fields(self)}
+        d.update(kw)
+        return Params(**d)
+
+
+class AbcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"abc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp = ct.c_void_p
+
+
+def exported_names():
+    """Entry points declared in include/abc.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(abc_[a-z_]+)\s*\(", txt, re.M)))
+
+
+def lib():
+    """Load libabc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_16154_amd.build`")
+    L = ct.CDLL(LIB_PATH)
+    L.abc_version.restype = ct.c_int
+    L.abc_last_error.restype = ct.c_char_p
+    L.abc_default_params.argtypes = [ct.POINTER(AbcParams)]
+    L.abc_workspace_bytes.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams),
+                                      ct.POINTER(ct.c_size_t)]
+    L.abc_traj_slots.argtypes = [ct.POINTER(AbcParams), ct.POINTER(ct.c_int)]
+    L.abc_forward_dynamics.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, _vp, ct.POINTER(AbcParams), _vp, _vp,
+                                       ct.c_size_t, _vp]
+    L.abc_adjoint_dynamics.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, _vp, ct.POINTER(AbcParams), _vp, _vp,
+                                       _vp, _vp, ct.c_size_t, _vp]
+    L.abc_pd_terminal.argtypes = [_vp, _vp, _vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp,
+                                  ct.POINTER(ct.c_double), _vp, ct.c_size_t, _vp]
+    L.abc_pd_step.argtypes = [_vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp, _vp, ct.c_int,
+                              ct.POINTER(AbcStats), _vp, ct.c_size_t, _vp]
+    L.abc_solve.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp, _vp, _vp, _vp, _vp,
+                            ct.c_size_t, _vp, ct.POINTER(AbcStats), ct.POINTER(AbcSolveLog)]
+    for name in exported_names():
+        if name not in ("abc_version", "abc_last_error"):
+            getattr(L, name).restype = ct.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, allow=(ABC_OK,)):
+    if rc not in allow:
+        raise AbcError(rc, lib().abc_last_error().decode())
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("tensors must be contiguous float32 on the GPU")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stats_dict(s: AbcStats) -> dict:
+    return {n: getattr(s, n) for n, _ in AbcStats._fields_}
+
+
+# ------------------------------------------------------------------ host-only calls
+def abc_version() -> int:
+    return lib().abc_version()
+
+
+def abc_default_params() -> Params:
+    p = AbcParams()
+    _check(lib().abc_default_params(ct.byref(p)))
+    return Params.from_c(p)
+
+
+def abc_workspace_bytes(kind: int, H: int, W: int, C: int, params: Params) -> int:
+    n = ct.c_size_t(0)
+    p = params.to_c()
+    _check(lib().abc_workspace_bytes(kind, H, W, C, ct.byref(p), ct.byref(n)))
+    return n.value
+
+
+def abc_traj_slots(params: Params) -> int:
+    n = ct.c_int(0)
+    p = params.to_c()
+    _check(lib().abc_traj_slots(ct.byref(p), ct.byref(n)))
+    return n.value
+
+
+def _workspace(kind, H, W, C, params, device):
+    torch = _torch()
+    nb = abc_workspace_bytes(kind, H, W, C, params)
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device), nb
+
+
+# ------------------------------------------------------------------ device calls
+def abc_forward_dynamics(c0, eps, params: Params, traj=None, ws=None):
+    """Trajectory ``(slots, H, W, C)`` of the agent dynamics (see abc_forward_dynamics in abc.h)."""
+    torch = _torch()
+    H, W, C = c0.shape
+    slots = abc_traj_slots(params)
+    if traj is None:
+        traj = torch.empty((slots, H, W, C), dtype=torch.float32, device=c0.device)
+    if ws is None:
+        ws, nb = _workspace(ABC_WS_FORWARD, H, W, C, params, c0.device)
+    else:
+        nb = ws.numel()
+    p = params.to_c()
+    _check(lib().abc_forward_dynamics(_ptr(c0), H, W, C, _ptr(eps), ct.byref(p), _ptr(traj),
+                                      ct.c_void_p(ws.data_ptr()), nb, _stream()))
+    return traj
+
+
+def abc_adjoint_dynamics(traj, eps, params: Params, gK, g0=None, geps=None, ws=None):
+    """(dl/dc^0, dl/deps) from dl/dc^K by the discrete adjoint sweep (see abc.h)."""
+    torch = _torch()
+    H, W, C = gK.shape
+    if g0 is None:
+        g0 = torch.empty_like(gK)
+    if geps is None:
+        geps = torch.empty((params.K, 2), dtype=torch.float32, device=gK.device)
+    if ws is None:
+        ws, nb = _workspace(ABC_WS_ADJOINT, H, W, C, params, gK.device)
+    else:
+        nb = ws.numel()
+    p = params.to_c()
+    _check(lib().abc_adjoint_dynamics(_ptr(traj), H, W, C, _ptr(eps), ct.byref(p), _ptr(gK), _ptr(g0),
+                                      _ptr(geps), ct.c_void_p(ws.data_ptr()), nb, _stream()))
+    return g0, geps
+
+
+def abc_pd_terminal(cK, c0, v, mu, params: Params, want_gradient=True, want_objective=True):
+    """(dL~/dc at cK or None, L~ or None) -- the adjoint terminal condition (see abc.h)."""
+    torch = _torch()
+    H, W, C = cK.shape
+    gK = torch.empty_like(cK) if want_gradient else None
+    ws, nb = _workspace(ABC_WS_PD, H, W, C, params, cK.device)
+    Lt = ct.c_double(0.0)
+    p = params.to_c()
+    _check(lib().abc_pd_terminal(_ptr(cK), _ptr(c0), _ptr(v), _ptr(mu), H, W, C, ct.byref(p), _ptr(gK),
+                                 ct.byref(Lt) if want_objective else None, ct.c_void_p(ws.data_ptr()), nb,
+                                 _stream()))
+    return gK, (Lt.value if want_objective else None)
+
+
+def abc_pd_step(cK, c0, v, mu, params: Params, update_mu=True, want_stats=True):
+    """Shrinkage of v and multiplier ascent, in place on v and mu; returns the stats dict."""
+    H, W, C = cK.shape
+    ws, nb = _workspace(ABC_WS_PD, H, W, C, params, cK.device)
+    st = AbcStats()
+    p = params.to_c()
+    _check(lib().abc_pd_step(_ptr(cK), _ptr(c0), H, W, C, ct.byref(p), _ptr(v), _ptr(mu), int(bool(update_mu)),
+                             ct.byref(st) if want_stats else None, ct.c_void_p(ws.data_ptr()), nb, _stream()))
+    return _stats_dict(st) if want_stats else None
+
+
+def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None, eps_replay=None, ws=None):
+    """Full solve (see abc_solve in abc.h).  Returns a dict with the field ``c``,
+    ``eps`` and ``mu`` (the tensors passed in, updated, when given), ``v``,
+    ``stats``, and the logs (numpy): ``decisions`` (max_outer x max_inner),
+    ``grad_log`` (M x P x K x 2) and ``phi_log`` (M x P x 3).  ``decisions``
+    and ``eps_replay`` (M x P x K x 2) replay a recorded control argmin."""
+    import numpy as np
+    torch = _torch()
+    H, W, C = c0.shape
+    dev = c0.device
+    c_out = torch.empty_like(c0)
+    v = torch.empty((H, W, 2, C), dtype=torch.float32, device=dev) if want_v else None
+    if ws is None:
+        ws, nb = _workspace(ABC_WS_SOLVE, H, W, C, params, dev)
+    else:
+        nb = ws.numel()
+    M, P, K = max(params.max_outer, 1), max(params.max_inner, 1), params.K
+    dp = ct.POINTER(ct.c_double)
+    dec_out = np.zeros((M, P), dtype=np.float64)
+    grad_log = np.zeros((M, P, K, 2), dtype=np.float64)
+    phi_log = np.zeros((M, P, 3), dtype=np.float64)
+    log = AbcSolveLog()
+    keep = []
+    if decisions is not None:
+        dec_in = np.ascontiguousarray(np.asarray(decisions, dtype=np.float64).reshape(M, P))
+        keep.append(dec_in)
+        log.decisions_in = dec_in.ctypes.data_as(dp)
+    if eps_replay is not None:
+        er = np.ascontiguousarray(np.asarray(eps_replay, dtype=np.float64).reshape(M, P, K, 2))
+        keep.append(er)
+        log.eps_replay = er.ctypes.data_as(dp)
+    log.decisions_out = dec_out.ctypes.data_as(dp)
+    log.grad_out = grad_log.ctypes.data_as(dp)
+    log.phi_out = phi_log.ctypes.data_as(dp)
+    st = AbcStats()
+    p = params.to_c()
+    rc = lib().abc_solve(_ptr(c0), H, W, C, ct.byref(p), _ptr(eps), _ptr(mu), _ptr(v), _ptr(c_out),
+                         ct.c_void_p(ws.data_ptr()), nb, _stream(), ct.byref(st), ct.byref(log))
+    _check(rc, allow=(ABC_OK, ABC_ENOCONV))
+    return {"c": c_out, "eps": eps, "mu": mu, "v": v, "stats": _stats_dict(st), "decisions": dec_out,
+            "grad_log": grad_log, "phi_log": phi_log, "status": rc}

@@ -1,0 +1,68 @@
+// Internal interface between the host solver and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace abc {
+
+// Tile of pixels handled by one workgroup of the windowed interaction kernels
+// (one thread per pixel; the workgroup stages the tile plus an R-pixel halo
+// in LDS).
+struct Tile {
+    int tx, ty;
+};
+
+// Number of workgroups (= tiles) covering an H x W image.
+int tile_count(int H, int W, Tile t);
+
+// LDS bytes of one interaction workgroup (fields = 1 forward, 2 adjoint).
+size_t tile_lds_bytes(int C, int R, Tile t, int fields);
+
+// Default tile for (C, R) and kernel kind (fields = 1 forward, 2 adjoint).
+Tile default_tile(int C, int R, int fields);
+
+// True when the (C, R, tile) combination fits the hardware limits.
+bool tile_ok(int C, int R, Tile t, int fields);
+
+// One explicit Euler step of the agent dynamics: cout = cin + dts * F(cin, eps^k).
+// eps points to the K x 2 device control array; step k reads eps[2k], eps[2k+1].
+hipError_t launch_forward_step(const float* cin, float* cout, const float* eps, int k, int H, int W,
+                               int C, int R, float dts, Tile t, hipStream_t s);
+
+// Transposed Euler step: pout = pin + dts * (dF/dc)^T pin at (c, eps^k), and per
+// workgroup FP64 partial sums of the two control-gradient integrands written to
+// part[2*tile + {0,1}] (raw sums of d^2 q and |D|^2 q, q = (phi'/20)(D . dp)).
+hipError_t launch_adjoint_step(const float* c, const float* pin, float* pout, const float* eps, int k,
+                               int H, int W, int C, int R, float dts, Tile t, double* part,
+                               hipStream_t s);
+
+// FP64 version of launch_reduce_rows; out (FP64) and out_f (FP32) may be NULL.
+hipError_t launch_reduce_rows_f64(const double* part, int nrows, int nblk, int nq, double scale,
+                                  double* out, float* out_f, hipStream_t s);
+
+// out[r*nq + q] = scale * sum_i part[(r*nblk + i)*nq + q] for r < nrows, q < nq
+// (strided per-thread sums, then the workgroup tree).
+hipError_t launch_reduce_rows(const float* part, int nrows, int nblk, int nq, float* out, float scale,
+                              hipStream_t s);
+
+// Workgroups used by the per-pixel primal/dual kernels.
+int pd_blocks(int H, int W);
+
+// Terminal condition and objective partials (one float per workgroup in part).
+hipError_t launch_terminal(const float* c, const float* c0, const float* v, const float* mu, int H,
+                           int W, int C, float rho, float alpha, float area, float* pK, float* part,
+                           hipStream_t s);
+
+// Shrinkage / multiplier update with 7 partial sums per workgroup in part:
+// |v-g|^2, |g|^2, |v|^2, |g|, |c-c0|^2, |v| + mu.(v-g), rho/2|v-g+mu/rho|^2 + |v|.
+constexpr int kPdQuantities = 7;
+hipError_t launch_pd_step(const float* c, const float* c0, float* v, float* mu, int update_mu, int H,
+                          int W, int C, float rho, float gamma, float* part, hipStream_t s);
+
+// Sets *flag (device int) to nonzero when x[0..n) holds a NaN or an Inf.
+hipError_t launch_nonfinite(const float* x, size_t n, int* flag, hipStream_t s);
+
+}  // namespace abc

@@ -1,0 +1,653 @@
+// gfx950 kernels of the agent-based optimal-control solver.
+//
+// Windowed interaction (forward Euler step of eq. MAsystem and its transpose,
+// Sec. 3.1): one thread per pixel, one workgroup per tile.  The workgroup
+// stages its tile plus an R-pixel halo in LDS (channel-interleaved, one extra
+// slot per pixel that is 1 inside the image and 0 for halo cells beyond the
+// border), then every thread sums its (2R+1)^2 window in a fixed offset order
+// (a = -R..R outer, b = -R..R inner, self skipped).  Each output therefore
+// depends only on its own window and not on the tile shape.  Workgroups whose
+// halo lies inside the image skip the border mask.
+//
+// The Wendland kernel is evaluated through t = clamp(1 - r, 0, 1):
+//   phi  = (1 + 4r)(1 - r)^4 = (5 - 4t) t^4,
+//   phi' = -20 r (1 - r)^3   = 20 (t - 1) t^3,
+// and t itself comes from one fused multiply-add per neighbour,
+//   t = clamp(om_ab - eps_c/2 |D|^2),  om_ab = 1 - eps_x/2 ((b dx)^2 + (a dy)^2).
+//
+// Reductions are deterministic: butterfly sums inside a wavefront, then a
+// fixed-order sum over the wavefronts of a workgroup, then a tree over
+// workgroups in a second kernel.  No floating-point atomics anywhere.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "abc_internal.h"
+
+namespace abc {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kMaxThreads = 256;
+constexpr size_t kMaxLds = 160 * 1024;
+
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum of v over the workgroup, valid in thread 0.  `red` holds >= 16 floats.
+__device__ __forceinline__ float block_sum(float v, float* red) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    v = wave_sum(v);
+    const int w = tid / kWave;
+    if ((tid % kWave) == 0) red[w] = v;
+    __syncthreads();
+    float s = 0.0f;
+    if (tid == 0) {
+        const int nw = (nthreads + kWave - 1) / kWave;
+        for (int i = 0; i < nw; ++i) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// FP64 sum of v over the workgroup, valid in thread 0.  `red` holds >= 16 doubles.
+__device__ __forceinline__ double block_sum_f64(double v, double* red) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    v = wave_sum_f64(v);
+    const int w = tid / kWave;
+    if ((tid % kWave) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0) {
+        const int nw = (nthreads + kWave - 1) / kWave;
+        for (int i = 0; i < nw; ++i) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous run of tiles so that neighbouring tiles share halo data in the
+// same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int per = nb / 8, rem = nb % 8;
+    const int x = bid % 8, idx = bid / 8;
+    return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+// Stage rows [y0-R, y0+TY+R) x cols [x0-R, x0+TX+R) of a HWC field into LDS
+// with stride CP+1 per pixel; channels >= C and cells outside the image are 0,
+// slot CP holds the inside mask when `mask` is set.
+template <int CP>
+__device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__ src, int H, int W, int C,
+                                           int x0, int y0, int R, int LW, int LH, bool mask) {
+    constexpr int CS = CP + 1;
+    for (int ly = threadIdx.y; ly < LH; ly += blockDim.y) {
+        const int gy = y0 - R + ly;
+        for (int lx = threadIdx.x; lx < LW; lx += blockDim.x) {
+            const int gx = x0 - R + lx;
+            const bool in = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+            const float* s = src + (in ? ((size_t)gy * W + gx) * C : 0);
+            float* d = dst + (ly * LW + lx) * CS;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) d[ch] = (in && ch < C) ? s[ch] : 0.0f;
+            if (mask) d[CP] = in ? 1.0f : 0.0f;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Forward step.
+template <int CP, int RT, bool BORDER>
+__device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const float (&ci)[CP],
+                                           float (&acc)[CP], float Ax, float Ay, float ech) {
+    constexpr int CS = CP + 1;
+    const int RR = RT > 0 ? RT : R;
+#pragma unroll
+    for (int a = -RR; a <= RR; ++a) {
+        const float* row = me + a * LW * CS;
+        const float om_row = fmaf(-Ay, (float)(a * a), 1.0f);
+#pragma unroll
+        for (int b = -RR; b <= RR; ++b) {
+            if (a == 0 && b == 0) continue;
+            const float* cj = row + b * CS;
+            const float om = fmaf(-Ax, (float)(b * b), om_row);
+            float d[CP];
+            float n2 = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) {
+                d[ch] = cj[ch] - ci[ch];
+                n2 = fmaf(d[ch], d[ch], n2);
+            }
+            const float t = clamp01(fmaf(-ech, n2, om));
+            const float t2 = t * t;
+            float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
+            if (BORDER) w *= cj[CP];
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(w, d[ch], acc[ch]);
+        }
+    }
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxThreads)
+fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps,
+                int k, int H, int W, int C, int Rrt, int tiles_x, float dts, float dx2, float dy2) {
+    constexpr int CS = CP + 1;
+    extern __shared__ float lds[];
+    const int R = RT > 0 ? RT : Rrt;
+    const int TX = blockDim.x, TY = blockDim.y;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int LW = TX + 2 * R, LH = TY + 2 * R;
+    const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
+    stage_tile<CP>(lds, cin, H, W, C, x0, y0, R, LW, LH, !interior);
+    __syncthreads();
+    const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
+    if (gx >= W || gy >= H) return;
+    const float exh = 0.5f * eps[2 * k], ech = 0.5f * eps[2 * k + 1];
+    const float* me = lds + ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
+    float ci[CP], acc[CP];
+#pragma unroll
+    for (int ch = 0; ch < CP; ++ch) {
+        ci[ch] = me[ch];
+        acc[ch] = 0.0f;
+    }
+    if (interior)
+        fwd_window<CP, RT, false>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech);
+    else
+        fwd_window<CP, RT, true>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech);
+    float* o = cout + ((size_t)gy * W + gx) * C;
+#pragma unroll
+    for (int ch = 0; ch < CP; ++ch)
+        if (ch < C) o[ch] = fmaf(dts, acc[ch], ci[ch]);
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint step.  With q = (phi'/20)(D . dp), dp = p_j - p_i:
+//   acc += phi dp + 20 eps_c q D,
+//   sx  += d^2 q,  sc += |D|^2 q.
+// The control gradient uses the symmetric-window identity
+//   sum_i sum_j phi' w (p_i . D_ij) = -1/2 sum_i sum_j phi' w (D_ij . (p_j - p_i))
+// (w symmetric, D antisymmetric), so dl/deps_x^k = -5 dt s sum sx and
+// dl/deps_c^k = -5 dt s sum sc.  Each pixel sums its window in FP32; the sum
+// over pixels is carried in FP64 (the solver's projected steps can reach
+// 1e13 or more, which amplifies rounding in this sum directly into the
+// controls).
+template <int CP, int RT, bool BORDER>
+__device__ __forceinline__ void adj_window(const float* mc, const float* mp, int LW, int R,
+                                           const float (&ci)[CP], const float (&pi)[CP], float (&acc)[CP],
+                                           float& sx, float& sc, float Ax, float Ay, float ech, float ec20,
+                                           float dx2, float dy2) {
+    constexpr int CS = CP + 1;
+    const int RR = RT > 0 ? RT : R;
+#pragma unroll
+    for (int a = -RR; a <= RR; ++a) {
+        const float* rowc = mc + a * LW * CS;
+        const float* rowp = mp + a * LW * CS;
+        const float om_row = fmaf(-Ay, (float)(a * a), 1.0f);
+        const float d2_row = dy2 * (float)(a * a);
+#pragma unroll
+        for (int b = -RR; b <= RR; ++b) {
+            if (a == 0 && b == 0) continue;
+            const float* cj = rowc + b * CS;
+            const float* pj = rowp + b * CS;
+            const float om = fmaf(-Ax, (float)(b * b), om_row);
+            const float d2 = fmaf(dx2, (float)(b * b), d2_row);
+            float d[CP];
+            float n2 = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) {
+                d[ch] = cj[ch] - ci[ch];
+                n2 = fmaf(d[ch], d[ch], n2);
+            }
+            const float t = clamp01(fmaf(-ech, n2, om));
+            const float t2 = t * t;
+            const float t3 = t2 * t;
+            float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
+            float u = (t - 1.0f) * t3;
+            if (BORDER) {
+                w *= cj[CP];
+                u *= cj[CP];
+            }
+            float dp[CP];
+            float ddp = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) {
+                dp[ch] = pj[ch] - pi[ch];
+                ddp = fmaf(d[ch], dp[ch], ddp);
+            }
+            const float q = u * ddp;
+            const float coef = ec20 * q;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(coef, d[ch], fmaf(w, dp[ch], acc[ch]));
+            sx = fmaf(d2, q, sx);
+            sc = fmaf(n2, q, sc);
+        }
+    }
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxThreads)
+adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
+                const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, float dts,
+                float dx2, float dy2, double* __restrict__ part) {
+    constexpr int CS = CP + 1;
+    extern __shared__ float lds[];
+    __shared__ double red[16];
+    const int R = RT > 0 ? RT : Rrt;
+    const int TX = blockDim.x, TY = blockDim.y;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int LW = TX + 2 * R, LH = TY + 2 * R;
+    const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
+    float* ldc = lds;
+    float* ldp = lds + LW * LH * CS;
+    stage_tile<CP>(ldc, c, H, W, C, x0, y0, R, LW, LH, !interior);
+    stage_tile<CP>(ldp, pin, H, W, C, x0, y0, R, LW, LH, false);
+    __syncthreads();
+    const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
+    float sx = 0.0f, sc = 0.0f;
+    if (gx < W && gy < H) {
+        const float ex = eps[2 * k], ec = eps[2 * k + 1];
+        const float exh = 0.5f * ex, ech = 0.5f * ec;
+        const int off = ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
+        const float* mc = ldc + off;
+        const float* mp = ldp + off;
+        float ci[CP], pi[CP], acc[CP];
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch) {
+            ci[ch] = mc[ch];
+            pi[ch] = mp[ch];
+            acc[ch] = 0.0f;
+        }
+        if (interior)
+            adj_window<CP, RT, false>(mc, mp, LW, R, ci, pi, acc, sx, sc, exh * dx2, exh * dy2, ech, 20.0f * ec,
+                                      dx2, dy2);
+        else
+            adj_window<CP, RT, true>(mc, mp, LW, R, ci, pi, acc, sx, sc, exh * dx2, exh * dy2, ech, 20.0f * ec,
+                                     dx2, dy2);
+        float* o = pout + ((size_t)gy * W + gx) * C;
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch)
+            if (ch < C) o[ch] = fmaf(dts, acc[ch], pi[ch]);
+    }
+    const double bx = block_sum_f64((double)sx, red);
+    const double bc = block_sum_f64((double)sc, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[2 * tile + 0] = bx;
+        part[2 * tile + 1] = bc;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Reductions over workgroup partials: grid (nrows, nq); each workgroup sums one
+// column of one row with strided per-thread sums followed by the block tree.
+__global__ void __launch_bounds__(kMaxThreads)
+reduce_rows_kernel(const float* __restrict__ part, int nblk, int nq, float scale, float* __restrict__ out) {
+    __shared__ float red[16];
+    const int r = blockIdx.x, q = blockIdx.y;
+    const float* base = part + (size_t)r * nblk * nq + q;
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += base[(size_t)i * nq];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[r * nq + q] = scale * s;
+}
+
+// FP64 variant for the control-gradient partials; writes FP64 and, when
+// out_f is set, an FP32 copy.
+__global__ void __launch_bounds__(kMaxThreads)
+reduce_rows_f64_kernel(const double* __restrict__ part, int nblk, int nq, double scale, double* __restrict__ out,
+                       float* __restrict__ out_f) {
+    __shared__ double red[16];
+    const int r = blockIdx.x, q = blockIdx.y;
+    const double* base = part + (size_t)r * nblk * nq + q;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += base[(size_t)i * nq];
+    s = block_sum_f64(s, red);
+    if (threadIdx.x == 0) {
+        if (out) out[r * nq + q] = scale * s;
+        if (out_f) out_f[r * nq + q] = (float)(scale * s);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Per-pixel primal/dual kernels.  grad# is the central difference of Def. 3.1,
+// zero on the first/last column (row) by the reflective rule.
+
+__device__ __forceinline__ float grad_x(const float* __restrict__ c, size_t i, int q, int W, int C, int ch,
+                                        float inv2dx) {
+    return (q >= 1 && q <= W - 2) ? (c[(i + 1) * C + ch] - c[(i - 1) * C + ch]) * inv2dx : 0.0f;
+}
+
+__device__ __forceinline__ float grad_y(const float* __restrict__ c, size_t i, int r, int H, int W, int C,
+                                        int ch, float inv2dy) {
+    return (r >= 1 && r <= H - 2) ? (c[(i + W) * C + ch] - c[(i - W) * C + ch]) * inv2dy : 0.0f;
+}
+
+// gK = area [ div(mu + rho (v - grad c)) + alpha (c - c0) ], div = -grad#^T, and the
+// per-pixel objective rho/2 |v - g + mu/rho|^2 + |v| + alpha/2 |c - c0|^2.
+__global__ void __launch_bounds__(kMaxThreads)
+terminal_kernel(const float* __restrict__ c, const float* __restrict__ c0, const float* __restrict__ v,
+                const float* __restrict__ mu, int H, int W, int C, float rho, float alpha, float area,
+                float inv2dx, float inv2dy, float* __restrict__ pK, float* __restrict__ part) {
+    __shared__ float red[16];
+    const size_t N = (size_t)H * W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float obj = 0.0f;
+    if (i < N) {
+        const int r = (int)(i / W), q = (int)(i % W);
+        const float inv_rho = 1.0f / rho;
+        float sh2 = 0.0f, nv2 = 0.0f, nf2 = 0.0f;
+        for (int ch = 0; ch < C; ++ch) {
+            const float cc = c[i * C + ch];
+            const float gx = grad_x(c, i, q, W, C, ch, inv2dx);
+            const float gy = grad_y(c, i, r, H, W, C, ch, inv2dy);
+            const float vx = v ? v[(i * 2 + 0) * C + ch] : 0.0f;
+            const float vy = v ? v[(i * 2 + 1) * C + ch] : 0.0f;
+            const float mx = mu ? mu[(i * 2 + 0) * C + ch] : 0.0f;
+            const float my = mu ? mu[(i * 2 + 1) * C + ch] : 0.0f;
+            const float shx = fmaf(mx, inv_rho, vx - gx);
+            const float shy = fmaf(my, inv_rho, vy - gy);
+            sh2 = fmaf(shx, shx, fmaf(shy, shy, sh2));
+            nv2 = fmaf(vx, vx, fmaf(vy, vy, nv2));
+            const float e = cc - c0[i * C + ch];
+            nf2 = fmaf(e, e, nf2);
+            if (pK) {
+                float dv = 0.0f;
+                if (q + 1 <= W - 2) {
+                    const size_t j = i + 1;
+                    const float g = (c[(j + 1) * C + ch] - cc) * inv2dx;
+                    const float vv = v ? v[(j * 2 + 0) * C + ch] : 0.0f;
+                    const float mm = mu ? mu[(j * 2 + 0) * C + ch] : 0.0f;
+                    dv = fmaf(fmaf(rho, vv - g, mm), inv2dx, dv);
+                }
+                if (q - 1 >= 1) {
+                    const size_t j = i - 1;
+                    const float g = (cc - c[(j - 1) * C + ch]) * inv2dx;
+                    const float vv = v ? v[(j * 2 + 0) * C + ch] : 0.0f;
+                    const float mm = mu ? mu[(j * 2 + 0) * C + ch] : 0.0f;
+                    dv = fmaf(-fmaf(rho, vv - g, mm), inv2dx, dv);
+                }
+                if (r + 1 <= H - 2) {
+                    const size_t j = i + W;
+                    const float g = (c[(j + W) * C + ch] - cc) * inv2dy;
+                    const float vv = v ? v[(j * 2 + 1) * C + ch] : 0.0f;
+                    const float mm = mu ? mu[(j * 2 + 1) * C + ch] : 0.0f;
+                    dv = fmaf(fmaf(rho, vv - g, mm), inv2dy, dv);
+                }
+                if (r - 1 >= 1) {
+                    const size_t j = i - W;
+                    const float g = (cc - c[(j - W) * C + ch]) * inv2dy;
+                    const float vv = v ? v[(j * 2 + 1) * C + ch] : 0.0f;
+                    const float mm = mu ? mu[(j * 2 + 1) * C + ch] : 0.0f;
+                    dv = fmaf(-fmaf(rho, vv - g, mm), inv2dy, dv);
+                }
+                pK[i * C + ch] = area * fmaf(alpha, e, dv);
+            }
+        }
+        obj = fmaf(0.5f * rho, sh2, sqrtf(nv2)) + 0.5f * alpha * nf2;
+    }
+    obj = block_sum(obj, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = obj;
+}
+
+// v = shrink(grad c - mu/rho) jointly over the 2C components of each pixel;
+// mu += gamma (v - grad c) when update_mu.  Partial sums (kPdQuantities).
+__global__ void __launch_bounds__(kMaxThreads)
+pd_step_kernel(const float* __restrict__ c, const float* __restrict__ c0, float* __restrict__ v,
+               float* __restrict__ mu, int update_mu, int H, int W, int C, float rho, float gamma,
+               float inv2dx, float inv2dy, float* __restrict__ part) {
+    __shared__ float red[16];
+    const size_t N = (size_t)H * W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float qv[kPdQuantities] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < N) {
+        const int r = (int)(i / W), q = (int)(i % W);
+        const float inv_rho = 1.0f / rho;
+        float na2 = 0.0f;
+        for (int ch = 0; ch < C; ++ch) {
+            const float ax = grad_x(c, i, q, W, C, ch, inv2dx) - mu[(i * 2 + 0) * C + ch] * inv_rho;
+            const float ay = grad_y(c, i, r, H, W, C, ch, inv2dy) - mu[(i * 2 + 1) * C + ch] * inv_rho;
+            na2 = fmaf(ax, ax, fmaf(ay, ay, na2));
+        }
+        const float na = sqrtf(na2);
+        const float fac = na > inv_rho ? (na - inv_rho) / na : 0.0f;
+        float svg = 0, sg = 0, sv = 0, sf = 0, muvg = 0, sh2 = 0;
+        for (int ch = 0; ch < C; ++ch) {
+            for (int dim = 0; dim < 2; ++dim) {
+                const size_t o = (i * 2 + dim) * C + ch;
+                const float g = dim == 0 ? grad_x(c, i, q, W, C, ch, inv2dx) : grad_y(c, i, r, H, W, C, ch, inv2dy);
+                const float m = mu[o];
+                const float vn = fac * (g - m * inv_rho);
+                const float mn = update_mu ? fmaf(gamma, vn - g, m) : m;
+                v[o] = vn;
+                if (update_mu) mu[o] = mn;
+                const float vg = vn - g;
+                svg = fmaf(vg, vg, svg);
+                sg = fmaf(g, g, sg);
+                sv = fmaf(vn, vn, sv);
+                muvg = fmaf(mn, vg, muvg);
+                const float sh = fmaf(mn, inv_rho, vg);
+                sh2 = fmaf(sh, sh, sh2);
+            }
+            const float e = c[i * C + ch] - c0[i * C + ch];
+            sf = fmaf(e, e, sf);
+        }
+        const float nv = sqrtf(sv);
+        qv[0] = svg;
+        qv[1] = sg;
+        qv[2] = sv;
+        qv[3] = sqrtf(sg);
+        qv[4] = sf;
+        qv[5] = nv + muvg;
+        qv[6] = fmaf(0.5f * rho, sh2, nv);
+    }
+#pragma unroll
+    for (int m = 0; m < kPdQuantities; ++m) {
+        const float s = block_sum(qv[m], red);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * kPdQuantities + m] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kMaxThreads)
+nonfinite_kernel(const float* __restrict__ x, size_t n, int* __restrict__ flag) {
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(x[i]);
+    if (__any(bad) && (threadIdx.x % kWave) == 0) atomicOr(flag, 1);
+}
+
+// ----------------------------------------------------------------------------
+// Dispatch over the padded channel count CP and the compile-time radius.
+constexpr int kChannelSteps[] = {1, 2, 3, 4, 8, 16, 31, 32, 64};
+
+int padded_channels(int C) {
+    for (int cp : kChannelSteps)
+        if (C <= cp) return cp;
+    return -1;
+}
+
+template <int CP, int RT>
+hipError_t fwd_launch_t(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
+                        float dts, Tile t, hipStream_t s) {
+    const int tiles_x = (W + t.tx - 1) / t.tx;
+    const int nb = tile_count(H, W, t);
+    const size_t lds = tile_lds_bytes(CP, R, t, 1);
+    auto fn = fwd_step_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty), lds, s, cin, cout, eps, k, H, W, C, R, tiles_x, dts, dx2,
+                       dy2);
+    return hipGetLastError();
+}
+
+template <int CP, int RT>
+hipError_t adj_launch_t(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
+                        int C, int R, float dts, Tile t, double* part, hipStream_t s) {
+    const int tiles_x = (W + t.tx - 1) / t.tx;
+    const int nb = tile_count(H, W, t);
+    const size_t lds = tile_lds_bytes(CP, R, t, 2);
+    auto fn = adj_step_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty), lds, s, c, pin, pout, eps, k, H, W, C, R, tiles_x, dts,
+                       dx2, dy2, part);
+    return hipGetLastError();
+}
+
+// Compile-time radii for the small-channel kernels (full unroll of the window);
+// wider channel counts and other radii use the runtime-radius kernel.
+template <int CP>
+hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
+                        float dts, Tile t, hipStream_t s) {
+    if constexpr (CP <= 4) {
+        switch (R) {
+            case 1: return fwd_launch_t<CP, 1>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+            case 2: return fwd_launch_t<CP, 2>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+            case 3: return fwd_launch_t<CP, 3>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+            case 4: return fwd_launch_t<CP, 4>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+            case 5: return fwd_launch_t<CP, 5>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+            default: break;
+        }
+    } else if constexpr (CP == 31) {
+        if (R == 2) return fwd_launch_t<CP, 2>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+    }
+    return fwd_launch_t<CP, 0>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+}
+
+template <int CP>
+hipError_t adj_launch_r(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
+                        int C, int R, float dts, Tile t, double* part, hipStream_t s) {
+    if constexpr (CP <= 4) {
+        switch (R) {
+            case 1: return adj_launch_t<CP, 1>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+            case 2: return adj_launch_t<CP, 2>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+            case 3: return adj_launch_t<CP, 3>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+            case 4: return adj_launch_t<CP, 4>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+            case 5: return adj_launch_t<CP, 5>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+            default: break;
+        }
+    } else if constexpr (CP == 31) {
+        if (R == 2) return adj_launch_t<CP, 2>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+    }
+    return adj_launch_t<CP, 0>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+}
+
+}  // namespace
+
+int tile_count(int H, int W, Tile t) { return ((W + t.tx - 1) / t.tx) * ((H + t.ty - 1) / t.ty); }
+
+size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
+    const int cp = padded_channels(C);
+    if (cp < 0) return (size_t)-1;
+    return (size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)(cp + 1) * sizeof(float);
+}
+
+bool tile_ok(int C, int R, Tile t, int fields) {
+    if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > kMaxThreads) return false;
+    if ((t.tx * t.ty) % kWave != 0) return false;
+    return tile_lds_bytes(C, R, t, fields) <= kMaxLds;
+}
+
+Tile default_tile(int C, int R, int fields) {
+    static const Tile cands[] = {{32, 8}, {16, 16}, {64, 4}, {16, 8}, {32, 4}, {8, 16}, {8, 8}, {64, 1}};
+    const size_t budget = 64 * 1024;
+    for (const Tile& t : cands)
+        if (tile_ok(C, R, t, fields) && tile_lds_bytes(C, R, t, fields) <= budget) return t;
+    for (const Tile& t : cands)
+        if (tile_ok(C, R, t, fields)) return t;
+    return Tile{0, 0};
+}
+
+hipError_t launch_forward_step(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
+                               float dts, Tile t, hipStream_t s) {
+    switch (padded_channels(C)) {
+        case 1: return fwd_launch_r<1>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 2: return fwd_launch_r<2>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 3: return fwd_launch_r<3>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 4: return fwd_launch_r<4>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 8: return fwd_launch_r<8>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 16: return fwd_launch_r<16>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 31: return fwd_launch_r<31>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 32: return fwd_launch_r<32>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        case 64: return fwd_launch_r<64>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adjoint_step(const float* c, const float* pin, float* pout, const float* eps, int k, int H,
+                               int W, int C, int R, float dts, Tile t, double* part, hipStream_t s) {
+    switch (padded_channels(C)) {
+        case 1: return adj_launch_r<1>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 2: return adj_launch_r<2>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 3: return adj_launch_r<3>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 4: return adj_launch_r<4>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 8: return adj_launch_r<8>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 16: return adj_launch_r<16>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 31: return adj_launch_r<31>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 32: return adj_launch_r<32>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        case 64: return adj_launch_r<64>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce_rows(const float* part, int nrows, int nblk, int nq, float* out, float scale,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(nrows, nq), dim3(kMaxThreads), 0, s, part, nblk, nq, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows_f64(const double* part, int nrows, int nblk, int nq, double scale, double* out,
+                                  float* out_f, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_rows_f64_kernel, dim3(nrows, nq), dim3(kMaxThreads), 0, s, part, nblk, nq, scale, out,
+                       out_f);
+    return hipGetLastError();
+}
+
+int pd_blocks(int H, int W) { return (int)(((size_t)H * W + kMaxThreads - 1) / kMaxThreads); }
+
+hipError_t launch_terminal(const float* c, const float* c0, const float* v, const float* mu, int H, int W, int C,
+                           float rho, float alpha, float area, float* pK, float* part, hipStream_t s) {
+    const float inv2dx = 0.5f * (float)W, inv2dy = 0.5f * (float)H;
+    hipLaunchKernelGGL(terminal_kernel, dim3(pd_blocks(H, W)), dim3(kMaxThreads), 0, s, c, c0, v, mu, H, W, C, rho,
+                       alpha, area, inv2dx, inv2dy, pK, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_pd_step(const float* c, const float* c0, float* v, float* mu, int update_mu, int H, int W, int C,
+                          float rho, float gamma, float* part, hipStream_t s) {
+    const float inv2dx = 0.5f * (float)W, inv2dy = 0.5f * (float)H;
+    hipLaunchKernelGGL(pd_step_kernel, dim3(pd_blocks(H, W)), dim3(kMaxThreads), 0, s, c, c0, v, mu, update_mu, H,
+                       W, C, rho, gamma, inv2dx, inv2dy, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const float* x, size_t n, int* flag, hipStream_t s) {
+    const size_t want = (n + kMaxThreads - 1) / kMaxThreads;
+    const int nb = (int)std::min<size_t>(std::max<size_t>(want, 1), 4096);
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(nb), dim3(kMaxThreads), 0, s, x, n, flag);
+    return hipGetLastError();
+}
+
+}  // namespace abc

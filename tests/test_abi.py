@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/abc.h, and validates arguments before touching the GPU."""
+import ctypes as ct
+import json
+import os
+import subprocess
+
+import pytest
+
+import paper_2510_16154_amd as A
+from paper_2510_16154_amd import binding as B
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_exports_every_declared_symbol():
+    names = B.exported_names()
+    assert len(names) >= 10
+    L = B.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert f" T {n}" in out, n
+
+
+def test_default_params_carry_the_papers_values():
+    g = json.load(open(os.path.join(GOLD, "paper_parameters.json")))
+    p = A.abc_default_params()
+    assert p.dt == g["dt"]["value"]
+    assert p.eps_min == (g["eps_box"]["value"][0],) * 2 and p.eps_max == (g["eps_box"]["value"][1],) * 2
+    assert p.eps_init == g["eps_init"]["value"]
+    assert (p.sigma0, p.armijo_b, p.armijo_c) == (g["sigma0"]["value"], g["armijo_b"]["value"],
+                                                 g["armijo_c"]["value"])
+    assert p.rho == pytest.approx(g["rho"]["value"], rel=1e-7)
+    assert p.gamma == pytest.approx(g["gamma"]["value"], rel=1e-7)
+    assert A.abc_version() >= 100
+
+
+def test_workspace_sizes_and_slots():
+    p = A.Params(K=50, R=5)
+    ws = A.abc_workspace_bytes(A.ABC_WS_SOLVE, 512, 512, 3, p)
+    field = 512 * 512 * 3 * 4
+    assert ws >= 3 * 51 * field  # three trajectories
+    assert A.abc_workspace_bytes(A.ABC_WS_FORWARD, 512, 512, 3, p) == 0
+    assert A.abc_workspace_bytes(A.ABC_WS_FORWARD, 512, 512, 3, p.replace(ckpt_every=10)) >= 2 * field
+    assert A.abc_traj_slots(p) == 51
+    assert A.abc_traj_slots(p.replace(K=100, ckpt_every=10)) == 11
+    assert A.abc_traj_slots(p.replace(K=95, ckpt_every=10)) == 11
+
+
+@pytest.mark.parametrize("bad", [dict(K=0), dict(R=-1), dict(R=17), dict(dt=0.0), dict(rho=0.0),
+                                 dict(eps_min=(5.0, 2.0), eps_max=(4.0, 1100.0)), dict(max_ls=0),
+                                 dict(armijo_b=1.0), dict(ckpt_every=-1), dict(tile_x=7, tile_y=3)])
+def test_invalid_parameters_are_rejected_on_the_host(bad):
+    with pytest.raises(A.AbcError) as e:
+        A.abc_workspace_bytes(A.ABC_WS_SOLVE, 32, 32, 3, A.Params().replace(**bad))
+    assert e.value.code == A.ABC_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(0, 4, 3), (4, 0, 3), (4, 4, 0), (4, 4, 65)])
+def test_invalid_shapes_are_rejected_before_any_launch(shape):
+    L = B.lib()
+    p = A.Params().to_c()
+    H, W, C = shape
+    dummy = ct.c_void_p(16)  # never dereferenced: validation fails first
+    rc = L.abc_forward_dynamics(dummy, H, W, C, dummy, ct.byref(p), dummy, None, 0, None)
+    assert rc == A.ABC_EINVAL
+    assert "must" in L.abc_last_error().decode()
+    rc = L.abc_solve(dummy, H, W, C, ct.byref(p), None, None, None, dummy, dummy, 1 << 30, None, None, None)
+    assert rc == A.ABC_EINVAL
+
+
+def test_null_pointers_are_rejected():
+    L = B.lib()
+    p = A.Params().to_c()
+    assert L.abc_forward_dynamics(None, 8, 8, 3, None, ct.byref(p), None, None, 0, None) == A.ABC_EINVAL
+    assert L.abc_solve(None, 8, 8, 3, ct.byref(p), None, None, None, None, None, 0, None, None,
+                       None) == A.ABC_EINVAL
+    assert L.abc_pd_step(None, None, 8, 8, 3, ct.byref(p), None, None, 1, None, None, 0, None) == A.ABC_EINVAL

@@ -399,3 +399,27 @@ def test_default_parameters_are_the_papers(orc):
     assert (P.sigma0, P.armijo_b, P.armijo_c) == (g["sigma0"]["value"], g["armijo_b"]["value"],
                                                  g["armijo_c"]["value"])
     assert (P.rho, P.gamma) == (g["rho"]["value"], g["gamma"]["value"])
+
+
+def test_solve_logs_are_consistent(orc):
+    """The gradient logged at the first DAL step is the adjoint of the terminal
+    condition at the initial trajectory (divided by dt), and every logged
+    control is the projected step eps - tau G from the previous one."""
+    c0 = voronoi_image(12, 14, 3, 3, 0.05, 171).astype(np.float64)
+    P = _P(orc, K=6, R=2, alpha=20.0, max_outer=2, max_inner=3)
+    res = orc.solve(c0, P)
+    traj = orc.forward_sweep(c0, P)
+    v0, mu0, _ = orc.pd_step(traj[-1], c0, None, None, P, update_mu=False)
+    pK, _ = orc.terminal(traj[-1], c0, v0, mu0, P)
+    _, ge = orc.adjoint_sweep(traj, P, pK)
+    assert np.allclose(res["grad_log"][0, 0], ge / P.dt, rtol=1e-12, atol=0)
+    prev = np.full((P.K, 2), P.eps_init)
+    for j in range(2):
+        for it in range(3):
+            tau = res["decisions"][j, it]
+            if tau <= 0:
+                break
+            want = np.clip(prev - tau * res["grad_log"][j, it], 2.0, 1100.0)
+            assert np.array_equal(res["eps_log"][j, it], want)
+            prev = want
+    assert np.array_equal(prev, res["eps"])
