@@ -2,9 +2,10 @@
 //
 // Windowed interaction (forward Euler step of eq. MAsystem and its transpose,
 // Sec. 3.1): one thread per pixel, one workgroup per tile.  The workgroup
-// stages its tile plus an R-pixel halo in LDS (channel-interleaved, one extra
-// slot per pixel that is 1 inside the image and 0 for halo cells beyond the
-// border), then every thread sums its (2R+1)^2 window in a fixed offset order
+// stages its tile plus an R-pixel halo in LDS (channel-interleaved 16-byte
+// slots with one extra value per pixel that is 1 inside the image and 0 for
+// halo cells beyond the border), then every thread sums its (2R+1)^2 window in
+// a fixed offset order
 // (a = -R..R outer, b = -R..R inner, self skipped).  Each output therefore
 // depends only on its own window and not on the tile shape.  Workgroups whose
 // halo lies inside the image skip the border mask.
@@ -89,23 +90,64 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
 }
 
+// LDS slot of one pixel: CP channels, then the inside mask, padded to whole
+// 16-byte vectors (8 bytes for one channel) so that a neighbour is read with
+// ds_read_b128 / b64: consecutive lanes then touch consecutive 16-byte slots
+// and the reads are free of bank conflicts.
+template <int CP>
+struct Slot {
+    static constexpr int NV = CP == 1 ? 1 : (CP + 1 + 3) / 4;  // vectors per pixel
+    static constexpr int CS = CP == 1 ? 2 : 4 * NV;             // floats per pixel
+};
+
+template <int CP>
+__device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m) {
+    if constexpr (CP == 1) {
+        const float2 x = *reinterpret_cast<const float2*>(p);
+        v[0] = x.x;
+        m = x.y;
+    } else {
+        constexpr int NV = Slot<CP>::NV;
+        float t[4 * NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const float4 x = reinterpret_cast<const float4*>(p)[i];
+            t[4 * i + 0] = x.x;
+            t[4 * i + 1] = x.y;
+            t[4 * i + 2] = x.z;
+            t[4 * i + 3] = x.w;
+        }
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch) v[ch] = t[ch];
+        m = t[CP];
+    }
+}
+
 // Stage rows [y0-R, y0+TY+R) x cols [x0-R, x0+TX+R) of a HWC field into LDS
-// with stride CP+1 per pixel; channels >= C and cells outside the image are 0,
-// slot CP holds the inside mask when `mask` is set.
+// slots; channels >= C and cells outside the image are 0, the mask slot is 1
+// inside the image and 0 outside.
 template <int CP>
 __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__ src, int H, int W, int C,
-                                           int x0, int y0, int R, int LW, int LH, bool mask) {
-    constexpr int CS = CP + 1;
+                                           int x0, int y0, int R, int LW, int LH) {
+    constexpr int NV = Slot<CP>::NV, CS = Slot<CP>::CS;
     for (int ly = threadIdx.y; ly < LH; ly += blockDim.y) {
         const int gy = y0 - R + ly;
         for (int lx = threadIdx.x; lx < LW; lx += blockDim.x) {
             const int gx = x0 - R + lx;
             const bool in = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
             const float* s = src + (in ? ((size_t)gy * W + gx) * C : 0);
-            float* d = dst + (ly * LW + lx) * CS;
+            float t[CS];
 #pragma unroll
-            for (int ch = 0; ch < CP; ++ch) d[ch] = (in && ch < C) ? s[ch] : 0.0f;
-            if (mask) d[CP] = in ? 1.0f : 0.0f;
+            for (int ch = 0; ch < CS; ++ch) t[ch] = (in && ch < CP && ch < C) ? s[ch] : 0.0f;
+            t[CP] = in ? 1.0f : 0.0f;
+            float* d = dst + (ly * LW + lx) * CS;
+            if constexpr (CP == 1) {
+                *reinterpret_cast<float2*>(d) = make_float2(t[0], t[1]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    reinterpret_cast<float4*>(d)[i] = make_float4(t[4 * i], t[4 * i + 1], t[4 * i + 2], t[4 * i + 3]);
+            }
         }
     }
 }
@@ -115,7 +157,7 @@ __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__
 template <int CP, int RT, bool BORDER>
 __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const float (&ci)[CP],
                                            float (&acc)[CP], float Ax, float Ay, float ech) {
-    constexpr int CS = CP + 1;
+    constexpr int CS = Slot<CP>::CS;
     const int RR = RT > 0 ? RT : R;
 #pragma unroll
     for (int a = -RR; a <= RR; ++a) {
@@ -124,7 +166,8 @@ __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const
 #pragma unroll
         for (int b = -RR; b <= RR; ++b) {
             if (a == 0 && b == 0) continue;
-            const float* cj = row + b * CS;
+            float cj[CP], mj;
+            load_px<CP>(row + b * CS, cj, mj);
             const float om = fmaf(-Ax, (float)(b * b), om_row);
             float d[CP];
             float n2 = 0.0f;
@@ -136,7 +179,7 @@ __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const
             const float t = clamp01(fmaf(-ech, n2, om));
             const float t2 = t * t;
             float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
-            if (BORDER) w *= cj[CP];
+            if (BORDER) w *= mj;
 #pragma unroll
             for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(w, d[ch], acc[ch]);
         }
@@ -147,7 +190,7 @@ template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxThreads)
 fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps,
                 int k, int H, int W, int C, int Rrt, int tiles_x, float dts, float dx2, float dy2) {
-    constexpr int CS = CP + 1;
+    constexpr int CS = Slot<CP>::CS;
     extern __shared__ float lds[];
     const int R = RT > 0 ? RT : Rrt;
     const int TX = blockDim.x, TY = blockDim.y;
@@ -155,18 +198,16 @@ fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const f
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
-    stage_tile<CP>(lds, cin, H, W, C, x0, y0, R, LW, LH, !interior);
+    stage_tile<CP>(lds, cin, H, W, C, x0, y0, R, LW, LH);
     __syncthreads();
     const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
     if (gx >= W || gy >= H) return;
     const float exh = 0.5f * eps[2 * k], ech = 0.5f * eps[2 * k + 1];
     const float* me = lds + ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
-    float ci[CP], acc[CP];
+    float ci[CP], acc[CP], mi;
+    load_px<CP>(me, ci, mi);
 #pragma unroll
-    for (int ch = 0; ch < CP; ++ch) {
-        ci[ch] = me[ch];
-        acc[ch] = 0.0f;
-    }
+    for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
     if (interior)
         fwd_window<CP, RT, false>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech);
     else
@@ -193,7 +234,7 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
                                            const float (&ci)[CP], const float (&pi)[CP], float (&acc)[CP],
                                            float& sx, float& sc, float Ax, float Ay, float ech, float ec20,
                                            float dx2, float dy2) {
-    constexpr int CS = CP + 1;
+    constexpr int CS = Slot<CP>::CS;
     const int RR = RT > 0 ? RT : R;
 #pragma unroll
     for (int a = -RR; a <= RR; ++a) {
@@ -204,8 +245,9 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
 #pragma unroll
         for (int b = -RR; b <= RR; ++b) {
             if (a == 0 && b == 0) continue;
-            const float* cj = rowc + b * CS;
-            const float* pj = rowp + b * CS;
+            float cj[CP], pj[CP], mj, unused;
+            load_px<CP>(rowc + b * CS, cj, mj);
+            load_px<CP>(rowp + b * CS, pj, unused);
             const float om = fmaf(-Ax, (float)(b * b), om_row);
             const float d2 = fmaf(dx2, (float)(b * b), d2_row);
             float d[CP];
@@ -221,8 +263,8 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
             float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
             float u = (t - 1.0f) * t3;
             if (BORDER) {
-                w *= cj[CP];
-                u *= cj[CP];
+                w *= mj;
+                u *= mj;
             }
             float dp[CP];
             float ddp = 0.0f;
@@ -246,7 +288,7 @@ __global__ void __launch_bounds__(kMaxThreads)
 adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
                 const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, float dts,
                 float dx2, float dy2, double* __restrict__ part) {
-    constexpr int CS = CP + 1;
+    constexpr int CS = Slot<CP>::CS;
     extern __shared__ float lds[];
     __shared__ double red[16];
     const int R = RT > 0 ? RT : Rrt;
@@ -257,8 +299,8 @@ adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, floa
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
     float* ldc = lds;
     float* ldp = lds + LW * LH * CS;
-    stage_tile<CP>(ldc, c, H, W, C, x0, y0, R, LW, LH, !interior);
-    stage_tile<CP>(ldp, pin, H, W, C, x0, y0, R, LW, LH, false);
+    stage_tile<CP>(ldc, c, H, W, C, x0, y0, R, LW, LH);
+    stage_tile<CP>(ldp, pin, H, W, C, x0, y0, R, LW, LH);
     __syncthreads();
     const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
     float sx = 0.0f, sc = 0.0f;
@@ -268,13 +310,11 @@ adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, floa
         const int off = ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
         const float* mc = ldc + off;
         const float* mp = ldp + off;
-        float ci[CP], pi[CP], acc[CP];
+        float ci[CP], pi[CP], acc[CP], mi;
+        load_px<CP>(mc, ci, mi);
+        load_px<CP>(mp, pi, mi);
 #pragma unroll
-        for (int ch = 0; ch < CP; ++ch) {
-            ci[ch] = mc[ch];
-            pi[ch] = mp[ch];
-            acc[ch] = 0.0f;
-        }
+        for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
         if (interior)
             adj_window<CP, RT, false>(mc, mp, LW, R, ci, pi, acc, sx, sc, exh * dx2, exh * dy2, ech, 20.0f * ec,
                                       dx2, dy2);
@@ -561,7 +601,8 @@ int tile_count(int H, int W, Tile t) { return ((W + t.tx - 1) / t.tx) * ((H + t.
 size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     const int cp = padded_channels(C);
     if (cp < 0) return (size_t)-1;
-    return (size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)(cp + 1) * sizeof(float);
+    const int cs = cp == 1 ? 2 : 4 * ((cp + 1 + 3) / 4);
+    return (size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)cs * sizeof(float);
 }
 
 bool tile_ok(int C, int R, Tile t, int fields) {
