@@ -32,6 +32,20 @@ if ROOT not in sys.path:
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per adjoint-step launch at this workload from the rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the SHA-256 of
+# the kernel source they were taken with; reported as null for any other source.
+PROFILED_TRAFFIC = {
+    "kernel_sha256": "89ab6d3e02e978e4bdf0b2c3b909925d8a71ea605a716737be164d6e4df140a2",
+    "bytes_per_launch": 11.02e6,
+}
+KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")
+
+
+def kernel_sha() -> str:
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
 
 def window_pairs(H: int, W: int, R: int) -> int:
     """Ordered in-image pairs (i, j), j != i, with |row diff|, |col diff| <= R."""
@@ -52,8 +66,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=10,
-                    help="Euler steps of the oracle sample (forward + adjoint) on the full image")
+    ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
+                    help="repeat the oracle's full forward+adjoint sweep until this much time has passed")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times) and exit; used to calibrate "
+                         "the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
@@ -61,6 +78,16 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": 5}))
+        return 0
 
     import paper_2510_16154_amd as A
     from paper_2510_16154_amd.workloads import VORONOI512 as wl
@@ -128,6 +155,7 @@ def main() -> int:
     adj_flops = pairs * flops_per_pair(C, "adj")
     fwd_flops = pairs * flops_per_pair(C, "fwd")
     achieved = adj_flops / adj_launch / 1e12
+    traffic = PROFILED_TRAFFIC["bytes_per_launch"] if PROFILED_TRAFFIC["kernel_sha256"] == kernel_sha() else None
     value = H * W * K / t_step
     out = {
         "metric": "agent-steps/sec (fwd+adjoint)",
@@ -149,31 +177,35 @@ def main() -> int:
                    "fwd_tflops": fwd_flops * K / t_fwd / 1e12, "adj_tflops": adj_flops * K / t_adj / 1e12},
         "roofline": {"kernel": "adj_step_kernel<3,5>", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": None, "flops_per_launch": adj_flops, "launch_ms": adj_launch * 1e3},
+                     "traffic": traffic, "flops_per_launch": adj_flops, "launch_ms": adj_launch * 1e3},
         "last_step_stats": {k: st[k] for k in ("K", "TV", "fid", "r_rel")},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(c0n, wl, args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(c0n, wl, args.cpu_min_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
 
-def cpu_baseline(c0n, wl, ksample: int) -> dict:
-    """The FP64 oracle on the host cores: forward + adjoint over `ksample` Euler
-    steps of the same image (the sweep cost is linear in K), scaled to the
-    benchmark's unit."""
+def cpu_baseline(c0n, wl, min_seconds: float) -> dict:
+    """The FP64 oracle on the host cores: full forward + adjoint sweeps (K Euler
+    steps each) of the benchmark image, repeated until `min_seconds` passed."""
     from oracle import oracle as O
-    P = O.Params(K=ksample, R=wl.R)
-    eps = np.full((ksample, 2), 57.0)
-    t0 = time.perf_counter()
-    traj = O.forward_sweep(c0n, P, eps)
+    P = O.Params(K=wl.K, R=wl.R)
+    eps = np.full((wl.K, 2), 57.0)
     pK = np.random.default_rng(0).normal(size=c0n.shape)
-    O.adjoint_sweep(traj, P, pK, eps)
-    dt = time.perf_counter() - t0
-    return {"value": wl.H * wl.W * ksample / dt, "unit": "agent-steps/s", "cores": O.num_threads(),
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        traj = O.forward_sweep(c0n, P, eps)
+        O.adjoint_sweep(traj, P, pK, eps)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    return {"value": wl.H * wl.W * wl.K * reps / dt, "unit": "agent-steps/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"forward+adjoint sweep, {ksample} of {wl.K} Euler steps, full {wl.H}x{wl.W}x{wl.C} "
-                      f"image, R={wl.R}, FP64 ({dt:.1f} s)"}
+            "sample": f"{reps} x (forward + adjoint sweep, {wl.K} Euler steps) of the {wl.H}x{wl.W}x{wl.C} "
+                      f"image, R={wl.R}, FP64, {dt:.1f} s"}
 
 
 if __name__ == "__main__":
