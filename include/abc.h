@@ -70,7 +70,11 @@ typedef struct abc_params {
     int32_t ckpt_every;  /* 0 => full trajectory; k > 0 => checkpoint every k steps  */
     int32_t tile_x;      /* interaction tile width in pixels; 0 => library default  */
     int32_t tile_y;      /* interaction tile height in pixels; 0 => library default */
+    int32_t cost;        /* ABC_COST_TV or ABC_COST_QUADRATIC (see abc_solve)         */
 } abc_params;
+
+#define ABC_COST_TV 0        /* TV + fidelity (eq. cost_TV), method of multipliers (Alg. 2)  */
+#define ABC_COST_QUADRATIC 1 /* quadratic J (Def. 3.2), direct-adjoint loop alone (Alg. 1) */
 
 /* Statistics of a solve or of one primal/dual update (host struct). */
 typedef struct abc_stats {
@@ -197,6 +201,11 @@ typedef struct abc_solve_log {
  *   c_out: H x W x C final field.
  *   ws: ABC_WS_SOLVE bytes.  st: host, may be NULL.
  *   log: host, may be NULL (see abc_solve_log).
+ * With p->cost == ABC_COST_QUADRATIC the direct-adjoint loop runs once (at
+ * most max_inner iterations) on J(c) = dx dy/2 sum [|grad# c|^2 + alpha
+ * (c - c0)^2] (Def. 3.2), whose adjoint terminal condition dJ/dc = dx dy
+ * [-div grad# c + alpha (c - c0)] (Sec. 3.1) is the TV one at v = mu = 0 and
+ * rho = 1; v and mu stay 0 and st->Ltilde reports J.
  * Returns ABC_OK, or ABC_ENOCONV when tol_alm > 0 was not reached within
  * max_outer iterations.  Synchronises the stream before returning. */
 int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* eps, float* mu,

@@ -77,6 +77,8 @@ typedef struct {
     double armijo_b;   /* step factor (Sec. 3.2: 1/2)                     */
     double armijo_c;   /* sufficient decrease (Sec. 3.2: 1e-4)            */
     int literal_kernel;/* 1: use the printed (4r-1)(1-r)^4 (debug only)   */
+    int cost;          /* 0: TV cost, method of multipliers (Alg. 2);
+                          1: quadratic cost J (Def. 3.2), DAL alone (Alg. 1) */
 } or_params;
 
 /* Results of one primal/dual update or energy evaluation. */
@@ -466,6 +468,12 @@ void or_pd_step(const double* c, const double* c0, int H, int W, int C, const or
 /* direct-adjoint loop with two-way projected Armijo search (Alg. 1,     */
 /* terminal condition of eq. admm_terminal).                             */
 /*                                                                       */
+/* With P->cost == 1 the same DAL loop runs once on the quadratic cost   */
+/* J of Def. 3.2 (Sec. 3.1): J(c) = dx dy sum [|grad c|^2 + alpha        */
+/* (c - c0)^2] / 2 and dJ/dc = dx dy [-div grad c + alpha (c - c0)],     */
+/* which is L~ and its gradient at v = mu = 0, rho = 1; there are no     */
+/* v / mu updates.                                                       */
+/*                                                                       */
 /* decisions_in / decisions_out hold one double per DAL iteration, laid  */
 /* out [max_outer][max_inner]: the accepted step tau (> 0), or 0 where   */
 /* the inner loop ended without a step.  With decisions_in the search is */
@@ -533,6 +541,12 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
     }
     or_stats S;
     memset(&S, 0, sizeof(S));
+    const int quad = P->cost == 1;
+    or_params Pq = *P;   /* parameters of the inner objective */
+    if (quad) Pq.rho = 1.0;
+    const double* tv = quad ? NULL : v;   /* v, mu seen by the inner objective */
+    const double* tmu = quad ? NULL : mu;
+    const int n_outer = quad ? (P->max_outer > 0 ? 1 : 0) : P->max_outer;
     if (decisions_out)
         for (int k = 0; k < P->max_outer * P->max_inner; ++k) decisions_out[k] = 0.0;
     if (trace_out)
@@ -544,18 +558,23 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
     double sigma = P->sigma0;
     /* Alg. 2: forward integration, then v^(0) = argmin_v L(c^(0), v, mu^(0)). */
     or_forward_sweep(c0, H, W, C, P, eps, base);
-    or_pd_step(base + (size_t)K * n, c0, H, W, C, P, v, mu, 0, NULL);
+    if (quad) {
+        memset(v, 0, 2 * n * sizeof(double));
+        memset(mu, 0, 2 * n * sizeof(double));
+    } else {
+        or_pd_step(base + (size_t)K * n, c0, H, W, C, P, v, mu, 0, NULL);
+    }
     double L_prev = NAN;
     int phi_seen = 0;
     or_energies E;
     memset(&E, 0, sizeof(E));
 
-    for (int j = 0; j < P->max_outer; ++j) {
+    for (int j = 0; j < n_outer; ++j) {
         /* control argmin: DAL iterations */
         for (int it = 0; it < P->max_inner; ++it) {
             const int slot = j * P->max_inner + it;
             double phi0;
-            or_terminal(base + (size_t)K * n, c0, v, mu, H, W, C, P, pK, &phi0);
+            or_terminal(base + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, pK, &phi0);
             if (!phi_seen) {
                 S.phi_first = phi0;
                 phi_seen = 1;
@@ -578,13 +597,13 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
                 accepted = decisions_in[slot];
                 project_step(eps, G, accepted, P, e_cand);
                 or_forward_sweep(c0, H, W, C, P, e_cand, cand);
-                or_terminal(cand + (size_t)K * n, c0, v, mu, H, W, C, P, NULL, &phi_acc);
+                or_terminal(cand + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, NULL, &phi_acc);
                 S.ls_evals++;
             } else {
                 /* Two-way search along the projected path (Alg. 1). */
                 double tau = sigma, phit;
                 int evals = 0, have = 0;
-                int ok = armijo_trial(c0, H, W, C, P, v, mu, eps, G, tau, phi0, e_try, trial, &phit);
+                int ok = armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial, &phit);
                 evals++;
                 if (ok) {
                     /* expanding branch: grow tau while the test keeps passing */
@@ -598,7 +617,7 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
                         if (memcmp(e_next, e_cand, 2 * (size_t)K * sizeof(double)) == 0)
                             break; /* the projected point no longer moves */
                         tau /= P->armijo_b;
-                        ok = armijo_trial(c0, H, W, C, P, v, mu, eps, G, tau, phi0, e_try, trial, &phit);
+                        ok = armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial, &phit);
                         evals++;
                         if (!ok) break;
                         { double* t = cand; cand = trial; trial = t; }
@@ -610,7 +629,7 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
                     /* backtracking branch: shrink tau until the test passes */
                     while (evals < P->max_ls) {
                         tau *= P->armijo_b;
-                        ok = armijo_trial(c0, H, W, C, P, v, mu, eps, G, tau, phi0, e_try, trial, &phit);
+                        ok = armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial, &phit);
                         evals++;
                         if (ok) {
                             { double* t = cand; cand = trial; trial = t; }
@@ -635,6 +654,11 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
             if (eps_log) memcpy(eps_log + (size_t)slot * 2 * K, eps, 2 * (size_t)K * sizeof(double));
             if (P->tol_dal > 0.0 && fabs(phi_acc - phi0) < P->tol_dal * fabs(phi0)) break;
         }
+        if (quad) {
+            or_energies_eval(base + (size_t)K * n, c0, NULL, NULL, H, W, C, &Pq, &E);
+            S.outer_iters = 1;
+            break;
+        }
         /* v- and mu-updates (Alg. 2, eq. soft_threshold and eq. dual_ascent) */
         or_pd_step(base + (size_t)K * n, c0, H, W, C, P, v, mu, 1, &E);
         S.outer_iters = j + 1;
@@ -642,7 +666,7 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
         L_prev = E.L;
         if (P->tol_alm > 0.0 && E.r_rel < P->tol_alm) break;
     }
-    if (S.outer_iters == 0) or_energies_eval(base + (size_t)K * n, c0, v, mu, H, W, C, P, &E);
+    if (S.outer_iters == 0) or_energies_eval(base + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, &E);
     memcpy(cK, base + (size_t)K * n, n * sizeof(double));
     S.K = E.K;
     S.TV = E.TV;
@@ -651,7 +675,7 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
     S.Ltilde = E.Ltilde;
     S.r_rel = E.r_rel;
     S.r_abs = E.r_abs;
-    S.status = (P->tol_alm > 0.0 && !(E.r_rel < P->tol_alm)) ? 1 : 0;
+    S.status = (!quad && P->tol_alm > 0.0 && !(E.r_rel < P->tol_alm)) ? 1 : 0;
     if (st) *st = S;
     free(base); free(cand); free(trial); free(pK); free(p0); free(G);
     free(e_try); free(e_cand); free(e_next);

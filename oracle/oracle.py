@@ -30,7 +30,7 @@ class _Params(ct.Structure):
         ("max_outer", ct.c_int), ("max_inner", ct.c_int), ("max_ls", ct.c_int),
         ("tol_alm", ct.c_double), ("tol_dal", ct.c_double),
         ("sigma0", ct.c_double), ("armijo_b", ct.c_double), ("armijo_c", ct.c_double),
-        ("literal_kernel", ct.c_int),
+        ("literal_kernel", ct.c_int), ("cost", ct.c_int),
     ]
 
 
@@ -68,6 +68,7 @@ class Params:
     armijo_b: float = 0.5            # Sec. 3.2
     armijo_c: float = 1e-4           # Sec. 3.2
     literal_kernel: int = 0
+    cost: int = 0                    # 0: TV / method of multipliers, 1: quadratic J / DAL alone
     extra: dict = field(default_factory=dict)
 
     def norm(self, H: int, W: int) -> float:
@@ -86,6 +87,7 @@ class Params:
         p.tol_alm, p.tol_dal = self.tol_alm, self.tol_dal
         p.sigma0, p.armijo_b, p.armijo_c = self.sigma0, self.armijo_b, self.armijo_c
         p.literal_kernel = self.literal_kernel
+        p.cost = self.cost
         return p
 
 

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "abc.h")
 
 ABC_OK, ABC_EINVAL, ABC_EHIP, ABC_ENONFINITE, ABC_ENOCONV = 0, -1, -2, -3, 1
 ABC_WS_SOLVE, ABC_WS_FORWARD, ABC_WS_ADJOINT, ABC_WS_PD = 0, 1, 2, 3
+ABC_COST_TV, ABC_COST_QUADRATIC = 0, 1
 
 
 class AbcParams(ct.Structure):
@@ -28,7 +29,7 @@ class AbcParams(ct.Structure):
         ("max_outer", ct.c_int32), ("max_inner", ct.c_int32), ("max_ls", ct.c_int32),
         ("tol_alm", ct.c_double), ("tol_dal", ct.c_double),
         ("sigma0", ct.c_double), ("armijo_b", ct.c_double), ("armijo_c", ct.c_double),
-        ("ckpt_every", ct.c_int32), ("tile_x", ct.c_int32), ("tile_y", ct.c_int32),
+        ("ckpt_every", ct.c_int32), ("tile_x", ct.c_int32), ("tile_y", ct.c_int32), ("cost", ct.c_int32),
     ]
 
 
@@ -68,6 +69,7 @@ class Params:
     ckpt_every: int = 0
     tile_x: int = 0
     tile_y: int = 0
+    cost: int = 0  # ABC_COST_TV (0) or ABC_COST_QUADRATIC (1)
 
     def to_c(self) -> AbcParams:
         p = AbcParams()

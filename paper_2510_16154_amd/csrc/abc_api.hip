@@ -86,6 +86,7 @@ int check_params(const abc_params* p) {
         !(p->armijo_c > 0.0 && p->armijo_c < 1.0))
         return fail(ABC_EINVAL, "Armijo parameters: sigma0 > 0, b and c in (0,1)");
     if (p->ckpt_every < 0) return fail(ABC_EINVAL, "ckpt_every must be >= 0");
+    if (p->cost != ABC_COST_TV && p->cost != ABC_COST_QUADRATIC) return fail(ABC_EINVAL, "unknown cost");
     return ABC_OK;
 }
 
@@ -488,6 +489,9 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     const float dts = p->dt * snorm;
     float* vv = v_out ? v_out : w.v;
     float* mm = mu ? mu : w.mu;
+    const bool quad = p->cost == ABC_COST_QUADRATIC;
+    abc_params pq = *p;  // parameters of the inner objective
+    if (quad) pq.rho = 1.0f;
 
     if ((rc = check_finite(c0, f, w.pd, st, "input image"))) return rc;
     std::vector<double> e_base((size_t)K * 2), e_try((size_t)K * 2), e_cand((size_t)K * 2), e_next((size_t)K * 2);
@@ -500,7 +504,8 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     } else {
         std::fill(e_base.begin(), e_base.end(), (double)p->eps_init);
     }
-    if (!mu) ABC_HIP(hipMemsetAsync(mm, 0, 2 * f * sizeof(float), st));
+    if (!mu || quad) ABC_HIP(hipMemsetAsync(mm, 0, 2 * f * sizeof(float), st));
+    if (quad) ABC_HIP(hipMemsetAsync(vv, 0, 2 * f * sizeof(float), st));
 
     auto upload = [&](const std::vector<double>& e, float* dev) -> int {
         std::vector<float> h(e.size());
@@ -524,7 +529,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
         int r2 = upload(e_try, w.eps[trial]);
         if (r2) return r2;
         if ((r2 = forward_sweep_full(c0, w.traj[trial], w.eps[trial], s, p, dts, tf, st))) return r2;
-        if ((r2 = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, p, w.pd, st, phit))) return r2;
+        if ((r2 = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, phit))) return r2;
         double ip = 0.0;
         for (int i = 0; i < 2 * K; ++i) ip += G[i] * (e_try[i] - e_base[i]);
         ip *= (double)p->dt;
@@ -544,7 +549,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     // Alg. 2: forward integration, v^(0) = argmin_v L(c^(0), v, mu^(0)).
     if ((rc = upload(e_base, w.eps[base]))) return rc;
     if ((rc = forward_sweep_full(c0, w.traj[base], w.eps[base], s, p, dts, tf, st))) return rc;
-    if ((rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 0, s, p, w.pd, st, nullptr))) return rc;
+    if (!quad && (rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 0, s, p, w.pd, st, nullptr))) return rc;
 
     double sigma = p->sigma0;
     double L_prev = NAN;
@@ -552,11 +557,12 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     abc_stats E;
     std::memset(&E, 0, sizeof(E));
     std::vector<double> G;
-    for (int j = 0; j < M; ++j) {
+    const int n_outer = quad ? std::min(M, 1) : M;
+    for (int j = 0; j < n_outer; ++j) {
         for (int it = 0; it < P; ++it) {
             const size_t slot = (size_t)j * P + it;
             double phi0 = 0.0;
-            if ((rc = objective(w.traj[base] + traj_stride, c0, vv, mm, w.adj.pa, s, p, w.pd, st, &phi0))) return rc;
+            if ((rc = objective(w.traj[base] + traj_stride, c0, vv, mm, w.adj.pa, s, &pq, w.pd, st, &phi0))) return rc;
             if (!phi_seen) {
                 S.phi_first = phi0;
                 phi_seen = true;
@@ -591,7 +597,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                     e_try.assign(eps_replay + slot * 2 * K, eps_replay + (slot + 1) * 2 * K);
                     if ((rc = upload(e_try, w.eps[trial]))) return rc;
                     if ((rc = forward_sweep_full(c0, w.traj[trial], w.eps[trial], s, p, dts, tf, st))) return rc;
-                    if ((rc = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, p, w.pd, st, &phi_acc)))
+                    if ((rc = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, &phi_acc)))
                         return rc;
                 } else if ((rc = run_trial(G, accepted, phi0, &phi_acc, &ok))) {
                     return rc;
@@ -652,6 +658,10 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
             if (phi_out) phi_out[3 * slot + 1] = phi_acc;
             if (p->tol_dal > 0.0 && std::fabs(phi_acc - phi0) < p->tol_dal * std::fabs(phi0)) break;
         }
+        if (quad) {
+            S.outer_iters = 1;
+            break;
+        }
         // v- and mu-updates (eq. soft_threshold, eq. dual_ascent)
         if ((rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 1, s, p, w.pd, st, &E))) return rc;
         S.outer_iters = j + 1;
@@ -659,7 +669,20 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
         L_prev = E.L;
         if (p->tol_alm > 0.0 && E.r_rel < p->tol_alm) break;
     }
-    if (S.outer_iters == 0) {
+    if (quad) {
+        // TV and fidelity of the final field from the pd kernel on scratch copies (v, mu stay 0);
+        // the inner objective is J itself
+        // the two spare trajectories are free here and each holds at least 2 fields (K >= 1)
+        float* sv = w.traj[trial];
+        float* sm = w.traj[cand];
+        ABC_HIP(hipMemsetAsync(sv, 0, 2 * f * sizeof(float), st));
+        ABC_HIP(hipMemsetAsync(sm, 0, 2 * f * sizeof(float), st));
+        if ((rc = pd_update(w.traj[base] + traj_stride, c0, sv, sm, 0, s, p, w.pd, st, &E))) return rc;
+        double J = 0.0;
+        if ((rc = objective(w.traj[base] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, &J))) return rc;
+        E.L = E.Ltilde = J;
+        E.r_rel = E.r_abs = 0.0;
+    } else if (S.outer_iters == 0) {
         // no multiplier step taken: energies at the initial state (v is unchanged by this call)
         if ((rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 0, s, p, w.pd, st, &E))) return rc;
     }
@@ -677,7 +700,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     S.Ltilde = E.Ltilde;
     S.r_rel = E.r_rel;
     S.r_abs = E.r_abs;
-    S.status = (p->tol_alm > 0.0 && !(E.r_rel < p->tol_alm)) ? ABC_ENOCONV : ABC_OK;
+    S.status = (!quad && p->tol_alm > 0.0 && !(E.r_rel < p->tol_alm)) ? ABC_ENOCONV : ABC_OK;
     if (stats) *stats = S;
     return S.status;
 }

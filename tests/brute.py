@@ -208,9 +208,13 @@ def grad_matrix(H, W):
 
 
 def solve_bruteforce(c0, K, dt, eps0, alpha, rho, gamma, M, P, emin, emax, sigma0=1.0, b=0.5,
-                     cA=1e-4, max_ls=40):
+                     cA=1e-4, max_ls=40, quadratic=False):
     """Alg. 2 with the Alg. 1 control argmin on a tiny grey image, all-pairs dynamics
-    (s = 1/N), dense Jacobians and dense grad#.  Returns (c^K, eps, v, mu, taus)."""
+    (s = 1/N), dense Jacobians and dense grad#.  Returns (c^K, eps, v, mu, taus).
+    With ``quadratic`` the DAL loop runs once on J of Def. 3.2 (v = mu = 0, rho = 1,
+    no multiplier updates)."""
+    if quadratic:
+        rho, M = 1.0, 1
     H, W, C = c0.shape
     assert C == 1
     N = H * W
@@ -259,7 +263,7 @@ def solve_bruteforce(c0, K, dt, eps0, alpha, rho, gamma, M, P, emin, emax, sigma
     hi = np.array(emax, dtype=np.float64)
     mu = np.zeros(2 * N)
     traj = sweep(eps)
-    v = shrink(traj[-1], mu)
+    v = np.zeros(2 * N) if quadratic else shrink(traj[-1], mu)
     sigma = sigma0
     taus = np.zeros((M, P))
 
@@ -302,6 +306,8 @@ def solve_bruteforce(c0, K, dt, eps0, alpha, rho, gamma, M, P, emin, emax, sigma
                 break
             sigma, eps, traj = best
             taus[j, it] = sigma
+        if quadratic:
+            break
         g = D @ traj[-1]
         v = shrink(traj[-1], mu)
         mu = mu + gamma * (v - g)

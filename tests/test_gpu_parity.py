@@ -241,3 +241,60 @@ def test_full_size_512_sweep_matches_oracle(orc):
     p0, ge = orc.adjoint_sweep(want, op, gK, eps)
     assert relinf(N(g0), p0) < FIELD_TOL
     assert rel2(N(geps), ge) < FIELD_TOL
+
+
+def test_quadratic_cost_dal_with_replayed_controls_matches_oracle(orc):
+    """Alg. 1 alone on the quadratic cost J of Def. 3.2 (32 x 32 x 3, R = 2, K = 20,
+    alpha = 20, 10 DAL iterations), oracle controls replayed as above."""
+    c0 = voronoi_image(32, 32, 3, 4, 0.05, 1001)
+    gp, op = both_params(orc, 32, 32, K=20, R=2, alpha=20.0, max_outer=1, max_inner=10)
+    gp = gp.replace(cost=A.ABC_COST_QUADRATIC)
+    op.cost = 1
+    ref = orc.solve(c0, op)
+    assert np.count_nonzero(ref["decisions"]) >= 3
+    out = A.abc_solve(T(c0), gp, decisions=ref["decisions"], eps_replay=ref["eps_log"])
+    assert relinf(N(out["c"]), ref["c"]) < FIELD_TOL
+    assert np.all(N(out["v"]) == 0)
+    for key in ("K", "TV", "fid", "Ltilde"):
+        assert abs(out["stats"][key] - ref["stats"][key]) <= ENERGY_TOL * abs(ref["stats"][key]), key
+    ran = np.any(ref["grad_log"] != 0, axis=(2, 3))
+    g_err = [rel2(out["grad_log"][j, i], ref["grad_log"][j, i]) for j, i in zip(*np.nonzero(ran))]
+    assert np.median(g_err) < FIELD_TOL
+    # free-running: J decreases monotonically over the accepted steps
+    free = A.abc_solve(T(c0), gp)
+    ph = free["phi_log"][0]
+    taken = free["decisions"][0] > 0
+    assert taken.any() and np.all(ph[taken, 1] <= ph[taken, 0])
+
+
+def test_high_resolution_transfer_matches_oracle(orc):
+    """Sec. 4.3: controls solved on a 32 x 32 image, applied to its 2x upsampled
+    version with one forward sweep (window 2R, normalisation s/4)."""
+    from paper_2510_16154_amd.transfer import transfer, transfer_params
+    c_lo = voronoi_image(32, 32, 3, 4, 0.05, 1001)
+    gp = A.Params(K=20, R=2, alpha=20.0, max_outer=1, max_inner=4)
+    eps = T(np.full((20, 2), 57.0))
+    A.abc_solve(T(c_lo), gp, eps=eps)
+    c_hi = np.repeat(np.repeat(c_lo, 2, axis=0), 2, axis=1)
+    got = N(transfer(T(c_hi), eps, gp, 32, 32, 2))
+    ph = transfer_params(gp, 32, 32, 2)
+    assert ph.R == 4 and abs(ph.inv_norm - 1.0 / 100.0) < 1e-9
+    want = orc.forward_sweep(c_hi, orc.Params(K=20, R=4, s=ph.inv_norm), N(eps))[-1]
+    assert relinf(got, want) < FIELD_TOL / 10
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_unwindowed_paper_sum_matches_oracle(orc, C):
+    """eq. MAsystem literally: a window covering the whole 16 x 16 image and s = 1/N
+    (the oracle's windowed sum equals the all-pairs sum there, see the CPU pins)."""
+    H = W = 16
+    c0 = voronoi_image(H, W, C, 3, 0.05, 77)
+    eps = rand_eps(6, 78, lo=2.0, hi=60.0)
+    gp, op = both_params(orc, H, W, K=6, R=15, inv_norm=1.0 / (H * W))
+    traj = A.abc_forward_dynamics(T(c0), T(eps), gp)
+    want = orc.forward_sweep(c0, op, eps)
+    assert relinf(N(traj), want) < FIELD_TOL / 10
+    gK = np.random.default_rng(79).normal(size=c0.shape)
+    g0, geps = A.abc_adjoint_dynamics(traj, T(eps), gp, T(gK))
+    p0, ge = orc.adjoint_sweep(want, op, gK, eps)
+    assert relinf(N(g0), p0) < FIELD_TOL and rel2(N(geps), ge) < FIELD_TOL

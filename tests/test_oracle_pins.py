@@ -60,6 +60,14 @@ def test_forward_step_equals_allpairs_sum(orc, C):
         assert np.max(np.abs(got - want)) < 1e-14
 
 
+def test_whole_image_window_is_the_papers_sum(orc):
+    c = _rng(9).uniform(0, 1, size=(12, 11, 3))
+    P = _P(orc, K=1, R=11, s=1.0 / 132)
+    got = orc.forward_step(c, P, 20.0, 35.0)
+    want = brute.euler_allpairs(c, 20.0, 35.0, 0.25)
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
 def test_forward_window_is_square_and_clipped(orc):
     H, W, C, R = 7, 6, 2, 2
     c = _rng(11).uniform(0, 1, size=(H, W, C))
@@ -423,3 +431,38 @@ def test_solve_logs_are_consistent(orc):
             assert np.array_equal(res["eps_log"][j, it], want)
             prev = want
     assert np.array_equal(prev, res["eps"])
+
+
+# ---------------------------------------------------------------- quadratic cost J (Def. 3.2), Alg. 1 alone
+def test_quadratic_cost_terminal_is_printed_dJdc(orc):
+    """J = dx dy/2 sum [|grad# c|^2 + alpha (c - c0)^2] and, away from the border,
+    dJ/dc = dx dy [-Lap# c + alpha (c - c0)] with the printed wide Laplacian."""
+    H, W = 9, 10
+    c0 = voronoi_image(H, W, 1, 3, 0.05, 181).astype(np.float64)
+    c = c0 + _rng(182).normal(scale=0.05, size=c0.shape)
+    P = _P(orc, alpha=30.0, rho=1.0)
+    pK, J = orc.terminal(c, c0, None, None, P)
+    g = brute.grad_paper(c)
+    area = 1.0 / (H * W)
+    want_J = 0.5 * area * (np.sum(g ** 2) + 30.0 * np.sum((c - c0) ** 2))
+    assert J == pytest.approx(want_J, rel=1e-13)
+    lap = brute.wide_laplacian_interior(c)
+    lit = area * (-lap + 30.0 * (c - c0))
+    assert np.max(np.abs(pK[2:H - 2, 2:W - 2] - lit[2:H - 2, 2:W - 2])) < 1e-12
+
+
+def test_quadratic_dal_equals_dense_bruteforce(orc):
+    H, W = 6, 6
+    c0 = voronoi_image(H, W, 1, 3, 0.05, 191).astype(np.float64)
+    K, Pn = 3, 4
+    P = _P(orc, K=K, R=7, s=1.0 / (H * W), alpha=5.0, max_outer=1, max_inner=Pn, cost=1)
+    res = orc.solve(c0, P)
+    cb, eb, vb, mb, taus = brute.solve_bruteforce(c0, K, 0.25, np.full((K, 2), 57.0), 5.0, 0.0, 0.0, 1, Pn,
+                                                  (2.0, 2.0), (1100.0, 1100.0), quadratic=True)
+    assert np.array_equal(res["decisions"], taus)
+    assert np.max(np.abs(res["c"] - cb)) < 1e-12
+    assert np.all(res["v"] == 0) and np.all(res["mu"] == 0)
+    tr = res["trace"][0]
+    taken = res["decisions"][0] > 0
+    assert np.all(tr[taken, 1] <= tr[taken, 0])
+    assert res["stats"]["Ltilde"] == pytest.approx(tr[taken, 1][-1] if taken.any() else tr[0, 0], rel=1e-12)
