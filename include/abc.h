@@ -212,6 +212,36 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
               float* v_out, float* c_out, void* ws, size_t ws_bytes, void* stream, abc_stats* st,
               abc_solve_log* log);
 
+/* One image of a batched solve: device pointers, sizes in pixels. */
+typedef struct abc_image {
+    const float* c0; /* H x W x C input                                       */
+    float* c_out;    /* H x W x C final field                                 */
+    float* eps;      /* K x 2 controls in/out, or NULL (start from eps_init)  */
+    float* mu;       /* H x W x 2 x C multiplier in/out, or NULL (start at 0) */
+    int32_t H, W;
+} abc_image;
+
+/* Bytes of device workspace abc_solve_batched needs for n images of sizes
+ * H[i] x W[i] x C.  Host only. */
+int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C, const abc_params* p,
+                                size_t* bytes);
+
+/* Solves n independent images of different sizes with the same parameters
+ * (the method of abc_solve, same arithmetic per image).  The images advance in
+ * lockstep rounds: each round launches one kernel per Euler step that covers
+ * the tiles of every image still in that phase (terminal condition, adjoint
+ * sweep, the next Armijo trial of every image that needs one, or the
+ * multiplier update), so that small images share the GPU instead of running
+ * one after another.  An image leaves the rounds when its own loops end.
+ *   imgs: host array of n descriptors.  C: channels (shared).
+ *   st: host array of n stats (may be NULL).
+ *   finish_ms: host array of n completion times in ms after the call began
+ *     (may be NULL).
+ * Returns ABC_OK, or ABC_ENOCONV when some image did not reach tol_alm.
+ * Synchronises the stream before returning. */
+int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, void* ws, size_t ws_bytes,
+                      void* stream, abc_stats* st, double* finish_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,11 @@ class AbcSolveLog(ct.Structure):
                 ("phi_out", ct.POINTER(ct.c_double))]
 
 
+class AbcImage(ct.Structure):
+    _fields_ = [("c0", ct.c_void_p), ("c_out", ct.c_void_p), ("eps", ct.c_void_p), ("mu", ct.c_void_p),
+                ("H", ct.c_int32), ("W", ct.c_int32)]
+
+
 class AbcStats(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("outer_iters", ct.c_int32), ("inner_iters", ct.c_int32),
                 ("ls_evals", ct.c_int32)] + [(n, ct.c_double) for n in (
@@ -136,6 +141,10 @@ def lib():
                               ct.POINTER(AbcStats), _vp, ct.c_size_t, _vp]
     L.abc_solve.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp, _vp, _vp, _vp, _vp,
                             ct.c_size_t, _vp, ct.POINTER(AbcStats), ct.POINTER(AbcSolveLog)]
+    L.abc_workspace_bytes_batched.argtypes = [ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.c_int, ct.c_int,
+                                              ct.POINTER(AbcParams), ct.POINTER(ct.c_size_t)]
+    L.abc_solve_batched.argtypes = [ct.POINTER(AbcImage), ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp,
+                                    ct.c_size_t, _vp, ct.POINTER(AbcStats), ct.POINTER(ct.c_double)]
     for name in exported_names():
         if name not in ("abc_version", "abc_last_error"):
             getattr(L, name).restype = ct.c_int
@@ -307,3 +316,46 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     _check(rc, allow=(ABC_OK, ABC_ENOCONV))
     return {"c": c_out, "eps": eps, "mu": mu, "v": v, "stats": _stats_dict(st), "decisions": dec_out,
             "grad_log": grad_log, "phi_log": phi_log, "status": rc}
+
+
+def abc_workspace_bytes_batched(shapes, C: int, params: Params) -> int:
+    n = len(shapes)
+    Hs = (ct.c_int32 * n)(*[int(h) for h, _ in shapes])
+    Ws = (ct.c_int32 * n)(*[int(w) for _, w in shapes])
+    nb = ct.c_size_t(0)
+    p = params.to_c()
+    _check(lib().abc_workspace_bytes_batched(Hs, Ws, n, C, ct.byref(p), ct.byref(nb)))
+    return nb.value
+
+
+def abc_solve_batched(images, params: Params, eps=None, mu=None, ws=None):
+    """Batched solve of a list of H x W x C images (see abc_solve_batched in
+    abc.h).  ``eps`` / ``mu``: optional lists of per-image tensors (in/out).
+    Returns (list of final fields, list of stats dicts, finish times in ms)."""
+    import numpy as np
+    torch = _torch()
+    n = len(images)
+    C = images[0].shape[2]
+    outs = [torch.empty_like(x) for x in images]
+    descs = (AbcImage * n)()
+    for i, x in enumerate(images):
+        if x.shape[2] != C:
+            raise ValueError("all images must have the same channel count")
+        descs[i].c0 = x.data_ptr()
+        descs[i].c_out = outs[i].data_ptr()
+        descs[i].eps = _ptr(eps[i]).value if eps is not None and eps[i] is not None else None
+        descs[i].mu = _ptr(mu[i]).value if mu is not None and mu[i] is not None else None
+        descs[i].H, descs[i].W = x.shape[0], x.shape[1]
+        _ptr(x)
+    if ws is None:
+        nb = abc_workspace_bytes_batched([(x.shape[0], x.shape[1]) for x in images], C, params)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=images[0].device)
+    else:
+        nb = ws.numel()
+    st = (AbcStats * n)()
+    fin = np.zeros(n, dtype=np.float64)
+    p = params.to_c()
+    rc = lib().abc_solve_batched(descs, n, C, ct.byref(p), ct.c_void_p(ws.data_ptr()), nb, _stream(), st,
+                                 fin.ctypes.data_as(ct.POINTER(ct.c_double)))
+    _check(rc, allow=(ABC_OK, ABC_ENOCONV))
+    return outs, [_stats_dict(s) for s in st], fin

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -703,6 +704,606 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     S.status = (!quad && p->tol_alm > 0.0 && !(E.r_rel < p->tol_alm)) ? ABC_ENOCONV : ABC_OK;
     if (stats) *stats = S;
     return S.status;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched solve: lockstep rounds over many images of different sizes.
+namespace {
+
+struct BImg {
+    // geometry
+    int H, W;
+    size_t f;
+    int tiles_f, tiles_a, pdb;
+    float snorm, dts;
+    double area;
+    // device buffers
+    float* traj[3];
+    float* pa;
+    float* pb;
+    double* gpart;
+    float* v;
+    float* mu;
+    float* pdpart;
+    // caller's arrays
+    const float* c0;
+    float* c_out;
+    float* eps_user;
+    float* mu_user;
+    // host state
+    std::vector<double> e_base, e_try, e_cand, e_next, G;
+    double sigma = 0, phi0 = 0, phi_acc = 0, accepted = 0, tau = 0, L_prev = NAN;
+    int base = 0, cand = 1, trial = 2;
+    int evals = 0, branch = 0;  // 0: first trial, 1: expanding, 2: backtracking
+    bool have = false, outer_done = false, inner_done = false, ls_done = false, phi_seen = false;
+    abc_stats S;
+    abc_stats E;
+    double finish_ms = 0;
+};
+
+struct BatchWs {
+    abc::StepJob* step_jobs;
+    abc::PixJob* pix_jobs;
+    abc::RedJob* red_jobs;
+    float* eps_all;    // n x 3 x K x 2
+    double* g_all;     // n x K x 2
+    float* q_all;      // n x kPdQuantities
+};
+
+void carve_batch(Carve& cv, int n, int K, BatchWs& b) {
+    b.step_jobs = cv.take<abc::StepJob>(n);
+    b.pix_jobs = cv.take<abc::PixJob>(n);
+    b.red_jobs = cv.take<abc::RedJob>(n);
+    b.eps_all = cv.take<float>((size_t)n * 3 * K * 2);
+    b.g_all = cv.take<double>((size_t)n * K * 2);
+    b.q_all = cv.take<float>((size_t)n * abc::kPdQuantities);
+}
+
+void carve_bimg(Carve& cv, BImg& m, int K, int C) {
+    for (int i = 0; i < 3; ++i) m.traj[i] = cv.take<float>((size_t)(K + 1) * m.f);
+    m.pa = cv.take<float>(m.f);
+    m.pb = cv.take<float>(m.f);
+    m.gpart = cv.take<double>((size_t)K * m.tiles_a * 2);
+    m.v = cv.take<float>(2 * m.f);
+    m.mu = cv.take<float>(2 * m.f);
+    m.pdpart = cv.take<float>((size_t)m.pdb * abc::kPdQuantities);
+    (void)C;
+}
+
+struct Batch {
+    int n, C, K;
+    const abc_params* p;
+    abc_params pq;  // inner-objective parameters (rho = 1 for the quadratic cost)
+    bool quad;
+    abc::Tile tf, ta;
+    hipStream_t st;
+    std::vector<BImg> im;
+    BatchWs w;
+    std::vector<float> eps_host;  // mirror of eps_all
+
+    float* eps_dev(int i, int slot) const { return w.eps_all + ((size_t)i * 3 + slot) * K * 2; }
+
+    int upload_eps(const std::vector<int>& who, const std::vector<int>& slot,
+                   const std::vector<const std::vector<double>*>& vals) {
+        for (size_t j = 0; j < who.size(); ++j) {
+            float* h = eps_host.data() + ((size_t)who[j] * 3 + slot[j]) * K * 2;
+            for (int q = 0; q < 2 * K; ++q) h[q] = (float)(*vals[j])[q];
+        }
+        ABC_HIP(hipMemcpyAsync(w.eps_all, eps_host.data(), eps_host.size() * sizeof(float), hipMemcpyHostToDevice,
+                               st));
+        return ABC_OK;
+    }
+
+    // K forward steps of every listed image into its trajectory `slot[j]`.
+    int forward(const std::vector<int>& who, const std::vector<int>& slot) {
+        if (who.empty()) return ABC_OK;
+        std::vector<abc::StepJob> jobs(who.size());
+        int total = 0;
+        for (size_t j = 0; j < who.size(); ++j) {
+            const BImg& m = im[who[j]];
+            abc::StepJob& J = jobs[j];
+            std::memset(&J, 0, sizeof(J));
+            J.traj = m.traj[slot[j]];
+            J.eps = eps_dev(who[j], slot[j]);
+            J.H = m.H;
+            J.W = m.W;
+            J.tiles_x = (m.W + tf.tx - 1) / tf.tx;
+            J.tiles = m.tiles_f;
+            J.start = total;
+            J.dts = m.dts;
+            J.dx2 = 1.0f / ((float)m.W * (float)m.W);
+            J.dy2 = 1.0f / ((float)m.H * (float)m.H);
+            total += m.tiles_f;
+        }
+        ABC_HIP(hipMemcpyAsync(w.step_jobs, jobs.data(), jobs.size() * sizeof(abc::StepJob), hipMemcpyHostToDevice,
+                               st));
+        for (int k = 0; k < K; ++k) {
+            if (p->R == 0) {
+                for (size_t j = 0; j < who.size(); ++j) {
+                    const BImg& m = im[who[j]];
+                    float* t = m.traj[slot[j]];
+                    ABC_HIP(hipMemcpyAsync(t + (size_t)(k + 1) * m.f, t, m.f * sizeof(float), hipMemcpyDeviceToDevice,
+                                           st));
+                }
+            } else {
+                ABC_HIP(abc::launch_forward_step_batched(w.step_jobs, (int)jobs.size(), total, k, C, p->R, tf, st));
+            }
+        }
+        return ABC_OK;
+    }
+
+    // Terminal condition (into pa) and/or objective of trajectory `slot[j]`; fills phi[j].
+    int objective(const std::vector<int>& who, const std::vector<int>& slot, bool want_pK, std::vector<double>& phi) {
+        phi.assign(who.size(), 0.0);
+        if (who.empty()) return ABC_OK;
+        std::vector<abc::PixJob> jobs(who.size());
+        std::vector<abc::RedJob> reds(who.size());
+        int total = 0;
+        for (size_t j = 0; j < who.size(); ++j) {
+            const BImg& m = im[who[j]];
+            abc::PixJob& J = jobs[j];
+            J.c = m.traj[slot[j]] + (size_t)K * m.f;
+            J.c0 = m.c0;
+            J.v = m.v;
+            J.mu = m.mu;
+            J.pK = want_pK ? m.pa : nullptr;
+            J.part = m.pdpart;
+            J.H = m.H;
+            J.W = m.W;
+            J.start = total;
+            J.area = (float)m.area;
+            J.inv2dx = 0.5f * (float)m.W;
+            J.inv2dy = 0.5f * (float)m.H;
+            total += m.pdb;
+            abc::RedJob& Rj = reds[j];
+            std::memset(&Rj, 0, sizeof(Rj));
+            Rj.part_f = m.pdpart;
+            Rj.out_f = w.q_all + (size_t)j * abc::kPdQuantities;
+            Rj.rows = 1;
+            Rj.nblk = m.pdb;
+        }
+        ABC_HIP(hipMemcpyAsync(w.pix_jobs, jobs.data(), jobs.size() * sizeof(abc::PixJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(abc::launch_terminal_batched(w.pix_jobs, (int)jobs.size(), total, C, pq.rho, pq.alpha, st));
+        ABC_HIP(abc::launch_reduce_jobs(w.red_jobs, (int)reds.size(), 1, st));
+        std::vector<float> q(who.size() * abc::kPdQuantities);
+        ABC_HIP(hipMemcpyAsync(q.data(), w.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        ABC_HIP(hipStreamSynchronize(st));
+        for (size_t j = 0; j < who.size(); ++j) phi[j] = im[who[j]].area * (double)q[j * abc::kPdQuantities];
+        return ABC_OK;
+    }
+
+    // Adjoint sweep from p^K (in pa) over each image's base trajectory; fills G.
+    int adjoint(const std::vector<int>& who) {
+        if (who.empty()) return ABC_OK;
+        std::vector<abc::StepJob> jobs(who.size());
+        std::vector<abc::RedJob> reds(who.size());
+        int total = 0;
+        for (size_t j = 0; j < who.size(); ++j) {
+            BImg& m = im[who[j]];
+            abc::StepJob& J = jobs[j];
+            J.traj = m.traj[m.base];
+            J.eps = eps_dev(who[j], m.base);
+            J.pa = m.pa;
+            J.pb = m.pb;
+            J.part = m.gpart;
+            J.H = m.H;
+            J.W = m.W;
+            J.tiles_x = (m.W + ta.tx - 1) / ta.tx;
+            J.tiles = m.tiles_a;
+            J.start = total;
+            J.dts = m.dts;
+            J.dx2 = 1.0f / ((float)m.W * (float)m.W);
+            J.dy2 = 1.0f / ((float)m.H * (float)m.H);
+            total += m.tiles_a;
+            abc::RedJob& Rj = reds[j];
+            std::memset(&Rj, 0, sizeof(Rj));
+            Rj.part_d = m.gpart;
+            Rj.out_d = w.g_all + (size_t)j * K * 2;
+            Rj.scale = -5.0 * (double)m.snorm;
+            Rj.rows = K;
+            Rj.nblk = m.tiles_a;
+        }
+        if (p->R > 0) {
+            ABC_HIP(hipMemcpyAsync(w.step_jobs, jobs.data(), jobs.size() * sizeof(abc::StepJob),
+                                   hipMemcpyHostToDevice, st));
+            ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice,
+                                   st));
+            for (int k = K - 1; k >= 0; --k)
+                ABC_HIP(abc::launch_adjoint_step_batched(w.step_jobs, (int)jobs.size(), total, k, K, C, p->R, ta, st));
+            ABC_HIP(abc::launch_reduce_jobs_f64(w.red_jobs, (int)reds.size(), K, 2, st));
+            std::vector<double> g(who.size() * K * 2);
+            ABC_HIP(hipMemcpyAsync(g.data(), w.g_all, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+            ABC_HIP(hipStreamSynchronize(st));
+            for (size_t j = 0; j < who.size(); ++j)
+                im[who[j]].G.assign(g.begin() + j * K * 2, g.begin() + (j + 1) * K * 2);
+        } else {
+            for (int i : who) im[i].G.assign((size_t)K * 2, 0.0);
+        }
+        return ABC_OK;
+    }
+
+    // Shrinkage / multiplier update of each listed image's final field; energies into E.
+    int pd(const std::vector<int>& who, int update_mu, bool want) {
+        if (who.empty()) return ABC_OK;
+        std::vector<abc::PixJob> jobs(who.size());
+        std::vector<abc::RedJob> reds(who.size());
+        int total = 0;
+        for (size_t j = 0; j < who.size(); ++j) {
+            const BImg& m = im[who[j]];
+            abc::PixJob& J = jobs[j];
+            std::memset(&J, 0, sizeof(J));
+            J.c = m.traj[m.base] + (size_t)K * m.f;
+            J.c0 = m.c0;
+            J.v = m.v;
+            J.mu = m.mu;
+            J.part = m.pdpart;
+            J.H = m.H;
+            J.W = m.W;
+            J.start = total;
+            J.area = (float)m.area;
+            J.inv2dx = 0.5f * (float)m.W;
+            J.inv2dy = 0.5f * (float)m.H;
+            total += m.pdb;
+            abc::RedJob& Rj = reds[j];
+            std::memset(&Rj, 0, sizeof(Rj));
+            Rj.part_f = m.pdpart;
+            Rj.out_f = w.q_all + (size_t)j * abc::kPdQuantities;
+            Rj.rows = 1;
+            Rj.nblk = m.pdb;
+        }
+        ABC_HIP(hipMemcpyAsync(w.pix_jobs, jobs.data(), jobs.size() * sizeof(abc::PixJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(abc::launch_pd_step_batched(w.pix_jobs, (int)jobs.size(), total, update_mu, C, p->rho, p->gamma, st));
+        if (!want) return ABC_OK;
+        ABC_HIP(abc::launch_reduce_jobs(w.red_jobs, (int)reds.size(), abc::kPdQuantities, st));
+        std::vector<float> q(who.size() * abc::kPdQuantities);
+        ABC_HIP(hipMemcpyAsync(q.data(), w.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        ABC_HIP(hipStreamSynchronize(st));
+        for (size_t j = 0; j < who.size(); ++j) {
+            Shape sh{im[who[j]].H, im[who[j]].W, C};
+            energies_from(q.data() + j * abc::kPdQuantities, sh, p, &im[who[j]].E);
+        }
+        return ABC_OK;
+    }
+
+    void project(const BImg& m, double tau, std::vector<double>& out) const {
+        for (int k = 0; k < K; ++k)
+            for (int q = 0; q < 2; ++q) {
+                const double x = m.e_base[2 * k + q] - tau * m.G[2 * k + q];
+                out[2 * k + q] = std::min<double>(std::max<double>(x, p->eps_min[q]), p->eps_max[q]);
+            }
+    }
+};
+
+size_t batch_ws_bytes(const int32_t* H, const int32_t* W, int n, int C, const abc_params* p, abc::Tile ta) {
+    Carve cv(nullptr);
+    BatchWs bw;
+    carve_batch(cv, n, p->K, bw);
+    for (int i = 0; i < n; ++i) {
+        BImg m;
+        m.H = H[i];
+        m.W = W[i];
+        m.f = (size_t)H[i] * W[i] * C;
+        m.tiles_a = abc::tile_count(H[i], W[i], ta);
+        m.pdb = abc::pd_blocks(H[i], W[i]);
+        carve_bimg(cv, m, p->K, C);
+    }
+    return cv.used;
+}
+
+}  // namespace
+
+extern "C" {
+
+int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C, const abc_params* p, size_t* bytes) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!H || !W || !bytes || n < 1) return fail(ABC_EINVAL, "H, W, bytes must be non-NULL and n >= 1");
+    for (int i = 0; i < n; ++i)
+        if ((rc = check_shape(H[i], W[i], C))) return rc;
+    abc::Tile ta;
+    if ((rc = pick_tile(p, C, 2, &ta))) return rc;
+    *bytes = batch_ws_bytes(H, W, n, C, p, ta);
+    return ABC_OK;
+}
+
+int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, void* ws, size_t ws_bytes,
+                      void* stream, abc_stats* st, double* finish_ms) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!imgs || n < 1) return fail(ABC_EINVAL, "imgs must be non-NULL and n >= 1");
+    if (p->ckpt_every != 0) return fail(ABC_EINVAL, "abc_solve_batched stores full trajectories; set ckpt_every = 0");
+    std::vector<int32_t> Hs(n), Ws(n);
+    for (int i = 0; i < n; ++i) {
+        if ((rc = check_shape(imgs[i].H, imgs[i].W, C))) return rc;
+        if (!imgs[i].c0 || !imgs[i].c_out) return fail(ABC_EINVAL, "every image needs c0 and c_out");
+        Hs[i] = imgs[i].H;
+        Ws[i] = imgs[i].W;
+    }
+    Batch B;
+    B.n = n;
+    B.C = C;
+    B.K = p->K;
+    B.p = p;
+    B.pq = *p;
+    B.quad = p->cost == ABC_COST_QUADRATIC;
+    if (B.quad) B.pq.rho = 1.0f;
+    if ((rc = pick_tile(p, C, 1, &B.tf))) return rc;
+    if ((rc = pick_tile(p, C, 2, &B.ta))) return rc;
+    const size_t need = batch_ws_bytes(Hs.data(), Ws.data(), n, C, p, B.ta);
+    if (!ws || ws_bytes < need) return fail(ABC_EINVAL, "batched workspace too small");
+    B.st = (hipStream_t)stream;
+    const int K = p->K;
+    Carve cv(ws);
+    carve_batch(cv, n, K, B.w);
+    B.im.resize(n);
+    B.eps_host.assign((size_t)n * 3 * K * 2, 0.0f);
+    const auto t_start = std::chrono::steady_clock::now();
+    auto now_ms = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    for (int i = 0; i < n; ++i) {
+        BImg& m = B.im[i];
+        m.H = imgs[i].H;
+        m.W = imgs[i].W;
+        m.f = (size_t)m.H * m.W * C;
+        m.tiles_f = abc::tile_count(m.H, m.W, B.tf);
+        m.tiles_a = abc::tile_count(m.H, m.W, B.ta);
+        m.pdb = abc::pd_blocks(m.H, m.W);
+        Shape sh{m.H, m.W, C};
+        m.snorm = norm_factor(p, sh);
+        m.dts = p->dt * m.snorm;
+        m.area = sh.area();
+        carve_bimg(cv, m, K, C);
+        m.c0 = imgs[i].c0;
+        m.c_out = imgs[i].c_out;
+        m.eps_user = imgs[i].eps;
+        m.mu_user = imgs[i].mu;
+        m.e_base.assign((size_t)K * 2, (double)p->eps_init);
+        m.e_try = m.e_cand = m.e_next = m.e_base;
+        m.sigma = p->sigma0;
+        std::memset(&m.S, 0, sizeof(m.S));
+        std::memset(&m.E, 0, sizeof(m.E));
+        m.S.gap_rel = NAN;
+        if (m.eps_user) {
+            std::vector<float> h((size_t)K * 2);
+            ABC_HIP(hipMemcpyAsync(h.data(), m.eps_user, h.size() * sizeof(float), hipMemcpyDeviceToHost, B.st));
+            ABC_HIP(hipStreamSynchronize(B.st));
+            for (int q = 0; q < 2 * K; ++q) {
+                if (!std::isfinite(h[q])) return fail(ABC_ENONFINITE, "controls hold a NaN or Inf");
+                m.e_base[q] = h[q];
+            }
+        }
+        // slot 0 of every trajectory buffer holds c0 for the whole solve
+        for (int b = 0; b < 3; ++b)
+            ABC_HIP(hipMemcpyAsync(m.traj[b], m.c0, m.f * sizeof(float), hipMemcpyDeviceToDevice, B.st));
+        if (m.mu_user && !B.quad)
+            ABC_HIP(hipMemcpyAsync(m.mu, m.mu_user, 2 * m.f * sizeof(float), hipMemcpyDeviceToDevice, B.st));
+        else
+            ABC_HIP(hipMemsetAsync(m.mu, 0, 2 * m.f * sizeof(float), B.st));
+        if (B.quad) ABC_HIP(hipMemsetAsync(m.v, 0, 2 * m.f * sizeof(float), B.st));
+    }
+    std::vector<int> all(n), slots;
+    for (int i = 0; i < n; ++i) all[i] = i;
+    {
+        std::vector<int> s0(n, 0);
+        std::vector<const std::vector<double>*> vals(n);
+        for (int i = 0; i < n; ++i) vals[i] = &B.im[i].e_base;
+        if ((rc = B.upload_eps(all, s0, vals))) return rc;
+        if ((rc = B.forward(all, s0))) return rc;
+        if (!B.quad && (rc = B.pd(all, 0, false))) return rc;
+    }
+    const int M = B.quad ? std::min(p->max_outer, 1) : p->max_outer;
+    const int P = p->max_inner;
+    std::vector<double> phi;
+    for (int j = 0; j < M; ++j) {
+        std::vector<int> outer;
+        for (int i = 0; i < n; ++i)
+            if (!B.im[i].outer_done) {
+                outer.push_back(i);
+                B.im[i].inner_done = false;
+            }
+        if (outer.empty()) break;
+        for (int it = 0; it < P; ++it) {
+            std::vector<int> act;
+            for (int i : outer)
+                if (!B.im[i].inner_done) act.push_back(i);
+            if (act.empty()) break;
+            std::vector<int> bslot;
+            for (int i : act) bslot.push_back(B.im[i].base);
+            if ((rc = B.objective(act, bslot, true, phi))) return rc;
+            if ((rc = B.adjoint(act))) return rc;
+            std::vector<int> search;
+            for (size_t a = 0; a < act.size(); ++a) {
+                BImg& m = B.im[act[a]];
+                m.phi0 = phi[a];
+                if (!m.phi_seen) {
+                    m.S.phi_first = m.phi0;
+                    m.phi_seen = true;
+                }
+                m.S.phi_last = m.phi0;
+                m.S.inner_iters++;
+                bool all_zero = true;
+                for (double g : m.G) all_zero = all_zero && (g == 0.0);
+                if (all_zero) {
+                    m.inner_done = true;
+                    continue;
+                }
+                m.tau = m.sigma;
+                m.evals = 0;
+                m.branch = 0;
+                m.have = false;
+                m.ls_done = false;
+                m.accepted = 0.0;
+                m.phi_acc = m.phi0;
+                search.push_back(act[a]);
+            }
+            // Armijo rounds: every image that needs a trial gets one per round
+            while (!search.empty()) {
+                std::vector<int> tslot;
+                std::vector<const std::vector<double>*> vals;
+                for (int i : search) {
+                    BImg& m = B.im[i];
+                    B.project(m, m.tau, m.e_try);
+                    tslot.push_back(m.trial);
+                    vals.push_back(&m.e_try);
+                }
+                if ((rc = B.upload_eps(search, tslot, vals))) return rc;
+                if ((rc = B.forward(search, tslot))) return rc;
+                if ((rc = B.objective(search, tslot, false, phi))) return rc;
+                std::vector<int> next;
+                for (size_t a = 0; a < search.size(); ++a) {
+                    BImg& m = B.im[search[a]];
+                    m.evals++;
+                    double ip = 0.0;
+                    for (int q = 0; q < 2 * K; ++q) ip += m.G[q] * (m.e_try[q] - m.e_base[q]);
+                    ip *= (double)p->dt;
+                    const bool ok = phi[a] <= m.phi0 + p->armijo_c * ip;
+                    auto keep = [&]() {
+                        std::swap(m.cand, m.trial);
+                        m.e_cand = m.e_try;
+                        m.accepted = m.tau;
+                        m.phi_acc = phi[a];
+                        m.have = true;
+                    };
+                    bool more = false;
+                    if (m.branch == 0) {
+                        if (ok) {
+                            keep();
+                            m.branch = 1;
+                        } else {
+                            m.branch = 2;
+                        }
+                    } else if (m.branch == 1) {
+                        if (ok) keep();
+                        else m.ls_done = true;
+                    } else {
+                        if (ok) {
+                            keep();
+                            m.ls_done = true;
+                        }
+                    }
+                    if (!m.ls_done && m.evals < p->max_ls) {
+                        if (m.branch == 1) {
+                            B.project(m, m.tau / p->armijo_b, m.e_next);
+                            if (m.e_next != m.e_cand) {
+                                m.tau /= p->armijo_b;
+                                more = true;
+                            }
+                        } else {
+                            m.tau *= p->armijo_b;
+                            more = true;
+                        }
+                    }
+                    if (more) {
+                        next.push_back(search[a]);
+                    } else {
+                        m.S.ls_evals += m.evals;
+                        if (!m.have) {
+                            m.inner_done = true;
+                        } else {
+                            m.sigma = m.accepted;
+                            m.e_base = m.e_cand;
+                            std::swap(m.base, m.cand);
+                            if (p->tol_dal > 0.0 && std::fabs(m.phi_acc - m.phi0) < p->tol_dal * std::fabs(m.phi0))
+                                m.inner_done = true;
+                        }
+                    }
+                }
+                search.swap(next);
+            }
+        }
+        if (B.quad) {
+            for (int i : outer) {
+                B.im[i].S.outer_iters = 1;
+                B.im[i].outer_done = true;
+                B.im[i].finish_ms = now_ms();
+            }
+            break;
+        }
+        if ((rc = B.pd(outer, 1, true))) return rc;
+        const double t_now = now_ms();
+        for (int i : outer) {
+            BImg& m = B.im[i];
+            m.S.outer_iters = j + 1;
+            m.S.gap_rel = std::isnan(m.L_prev) ? NAN : std::fabs(m.E.L - m.L_prev) / std::fabs(m.L_prev);
+            m.L_prev = m.E.L;
+            if ((p->tol_alm > 0.0 && m.E.r_rel < p->tol_alm) || j + 1 == M) {
+                m.outer_done = true;
+                m.finish_ms = t_now;
+            }
+        }
+    }
+    // outputs
+    int status = ABC_OK;
+    std::vector<int> final_e;
+    for (int i = 0; i < n; ++i) {
+        BImg& m = B.im[i];
+        if (!m.outer_done) m.finish_ms = now_ms();
+        ABC_HIP(hipMemcpyAsync(m.c_out, m.traj[m.base] + (size_t)K * m.f, m.f * sizeof(float),
+                               hipMemcpyDeviceToDevice, B.st));
+        if (m.eps_user) {
+            std::vector<float> h((size_t)K * 2);
+            for (int q = 0; q < 2 * K; ++q) h[q] = (float)m.e_base[q];
+            ABC_HIP(hipMemcpyAsync(m.eps_user, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, B.st));
+            ABC_HIP(hipStreamSynchronize(B.st));
+        }
+        if (m.mu_user && !B.quad)
+            ABC_HIP(hipMemcpyAsync(m.mu_user, m.mu, 2 * m.f * sizeof(float), hipMemcpyDeviceToDevice, B.st));
+        if (B.quad || m.S.outer_iters == 0) final_e.push_back(i);
+    }
+    if (!final_e.empty()) {
+        // energies where no multiplier update ran: the pd kernel on zeroed scratch (spare trajectories)
+        for (int i : final_e) {
+            BImg& m = B.im[i];
+            float* sv = m.traj[m.trial];
+            float* sm = m.traj[m.cand];
+            if (B.quad || m.S.outer_iters == 0) {
+                ABC_HIP(hipMemsetAsync(sv, 0, 2 * m.f * sizeof(float), B.st));
+                ABC_HIP(hipMemcpyAsync(sm, m.mu, 2 * m.f * sizeof(float), hipMemcpyDeviceToDevice, B.st));
+                if (B.quad) ABC_HIP(hipMemsetAsync(sm, 0, 2 * m.f * sizeof(float), B.st));
+                std::swap(m.v, sv);
+                std::swap(m.mu, sm);
+            }
+        }
+        if ((rc = B.pd(final_e, 0, true))) return rc;
+        if (B.quad) {
+            std::vector<int> bslot;
+            for (int i : final_e) bslot.push_back(B.im[i].base);
+            // the quadratic objective is evaluated with v = mu = 0
+            for (int i : final_e) {
+                BImg& m = B.im[i];
+                ABC_HIP(hipMemsetAsync(m.v, 0, 2 * m.f * sizeof(float), B.st));
+                ABC_HIP(hipMemsetAsync(m.mu, 0, 2 * m.f * sizeof(float), B.st));
+            }
+            if ((rc = B.objective(final_e, bslot, false, phi))) return rc;
+            for (size_t a = 0; a < final_e.size(); ++a) {
+                BImg& m = B.im[final_e[a]];
+                m.E.L = m.E.Ltilde = phi[a];
+                m.E.r_rel = m.E.r_abs = 0.0;
+            }
+        }
+    }
+    ABC_HIP(hipStreamSynchronize(B.st));
+    for (int i = 0; i < n; ++i) {
+        BImg& m = B.im[i];
+        abc_stats S = m.S;
+        S.K = m.E.K;
+        S.TV = m.E.TV;
+        S.fid = m.E.fid;
+        S.L = m.E.L;
+        S.Ltilde = m.E.Ltilde;
+        S.r_rel = m.E.r_rel;
+        S.r_abs = m.E.r_abs;
+        S.status = (!B.quad && p->tol_alm > 0.0 && !(m.E.r_rel < p->tol_alm)) ? ABC_ENOCONV : ABC_OK;
+        if (S.status) status = ABC_ENOCONV;
+        if (st) st[i] = S;
+        if (finish_ms) finish_ms[i] = m.finish_ms;
+    }
+    return status;
 }
 
 }  // extern "C"

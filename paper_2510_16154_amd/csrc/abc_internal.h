@@ -15,6 +15,45 @@ struct Tile {
     int tx, ty;
 };
 
+// One image of a multi-image interaction launch.  The grid covers the tiles of
+// all jobs; `start` is the job's first global tile.  Forward step k reads trajectory
+// slot k and writes slot k+1; transposed step k reads slot k and ping-pongs
+// between pa and pb (p^{k+1} in pa when K-1-k is even), writing its control
+// partials to part + k * tiles * 2.
+struct StepJob {
+    float* traj;
+    const float* eps;
+    float* pa;
+    float* pb;
+    double* part;
+    int H, W, tiles_x, tiles, start;
+    float dts, dx2, dy2;
+};
+
+// One image of a multi-image per-pixel launch (256 pixels per block);
+// `start` is the job's first global block.
+struct PixJob {
+    const float* c;
+    const float* c0;
+    float* v;
+    float* mu;
+    float* pK;
+    float* part;
+    int H, W, start;
+    float area, inv2dx, inv2dy;
+};
+
+// One job of a multi-image reduction: rows x nblk partials (FP64 or FP32);
+// FP64 results are multiplied by `scale`.
+struct RedJob {
+    const double* part_d;
+    double* out_d;
+    const float* part_f;
+    float* out_f;
+    double scale;
+    int rows, nblk;
+};
+
 // Number of workgroups (= tiles) covering an H x W image.
 int tile_count(int H, int W, Tile t);
 
@@ -61,6 +100,19 @@ hipError_t launch_terminal(const float* c, const float* c0, const float* v, cons
 constexpr int kPdQuantities = 7;
 hipError_t launch_pd_step(const float* c, const float* c0, float* v, float* mu, int update_mu, int H,
                           int W, int C, float rho, float gamma, float* part, hipStream_t s);
+
+// Multi-image launches (jobs in device memory, sorted by start).
+hipError_t launch_forward_step_batched(const StepJob* jobs, int njobs, int total_tiles, int k, int C, int R, Tile t,
+                                       hipStream_t s);
+hipError_t launch_adjoint_step_batched(const StepJob* jobs, int njobs, int total_tiles, int k, int K, int C, int R,
+                                       Tile t, hipStream_t s);
+hipError_t launch_terminal_batched(const PixJob* jobs, int njobs, int total_blocks, int C, float rho, float alpha,
+                                   hipStream_t s);
+hipError_t launch_pd_step_batched(const PixJob* jobs, int njobs, int total_blocks, int update_mu, int C, float rho,
+                                  float gamma, hipStream_t s);
+// FP64: out_d[r*nq+q] = scale * sum over the job's row r; FP32: out_f[q] = sum (rows = 1).
+hipError_t launch_reduce_jobs_f64(const RedJob* jobs, int njobs, int max_rows, int nq, hipStream_t s);
+hipError_t launch_reduce_jobs(const RedJob* jobs, int njobs, int nq, hipStream_t s);
 
 // Sets *flag (device int) to nonzero when x[0..n) holds a NaN or an Inf.
 hipError_t launch_nonfinite(const float* x, size_t n, int* flag, hipStream_t s);

@@ -186,15 +186,13 @@ __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const
     }
 }
 
+// One interaction tile of a forward step: stage, then one thread per pixel.
 template <int CP, int RT>
-__global__ void __launch_bounds__(kMaxThreads)
-fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps,
-                int k, int H, int W, int C, int Rrt, int tiles_x, float dts, float dx2, float dy2) {
+__device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* __restrict__ cout, float exh,
+                                         float ech, int H, int W, int C, int R, int tile, int tiles_x, float dts,
+                                         float dx2, float dy2, float* lds) {
     constexpr int CS = Slot<CP>::CS;
-    extern __shared__ float lds[];
-    const int R = RT > 0 ? RT : Rrt;
     const int TX = blockDim.x, TY = blockDim.y;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
@@ -202,7 +200,6 @@ fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const f
     __syncthreads();
     const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
     if (gx >= W || gy >= H) return;
-    const float exh = 0.5f * eps[2 * k], ech = 0.5f * eps[2 * k + 1];
     const float* me = lds + ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
     float ci[CP], acc[CP], mi;
     load_px<CP>(me, ci, mi);
@@ -216,6 +213,46 @@ fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const f
 #pragma unroll
     for (int ch = 0; ch < CP; ++ch)
         if (ch < C) o[ch] = fmaf(dts, acc[ch], ci[ch]);
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxThreads)
+fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps,
+                int k, int H, int W, int C, int Rrt, int tiles_x, float dts, float dx2, float dy2) {
+    extern __shared__ float lds[];
+    const int R = RT > 0 ? RT : Rrt;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    fwd_tile<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, R, tile, tiles_x, dts, dx2, dy2,
+                     lds);
+}
+
+// Index of the last job whose first tile (or block) is <= g (jobs sorted by start).
+template <class J>
+__device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs, int g) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].start <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Forward step k of several images in one launch: the grid covers the tiles of
+// every job, jobs[j].start being the first global tile of job j.
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxThreads)
+fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C, int Rrt) {
+    extern __shared__ float lds[];
+    const int R = RT > 0 ? RT : Rrt;
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const StepJob& J = jobs[find_job(jobs, njobs, g)];
+    const size_t f = (size_t)J.H * J.W * C;
+    const float* e = J.eps + 2 * k;
+    fwd_tile<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H, J.W, C, R,
+                     g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
 }
 
 // ----------------------------------------------------------------------------
@@ -283,17 +320,15 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
     }
 }
 
+// One interaction tile of a transposed step; part[2*tile + {0,1}] receives the
+// workgroup's FP64 sums of the two control-gradient integrands.
 template <int CP, int RT>
-__global__ void __launch_bounds__(kMaxThreads)
-adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
-                const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, float dts,
-                float dx2, float dy2, double* __restrict__ part) {
+__device__ __forceinline__ void adj_tile(const float* __restrict__ c, const float* __restrict__ pin,
+                                         float* __restrict__ pout, float ex, float ec, int H, int W, int C, int R,
+                                         int tile, int tiles_x, float dts, float dx2, float dy2,
+                                         double* __restrict__ part, float* lds, double* red) {
     constexpr int CS = Slot<CP>::CS;
-    extern __shared__ float lds[];
-    __shared__ double red[16];
-    const int R = RT > 0 ? RT : Rrt;
     const int TX = blockDim.x, TY = blockDim.y;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
@@ -305,7 +340,6 @@ adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, floa
     const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
     float sx = 0.0f, sc = 0.0f;
     if (gx < W && gy < H) {
-        const float ex = eps[2 * k], ec = eps[2 * k + 1];
         const float exh = 0.5f * ex, ech = 0.5f * ec;
         const int off = ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
         const float* mc = ldc + off;
@@ -332,6 +366,37 @@ adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, floa
         part[2 * tile + 0] = bx;
         part[2 * tile + 1] = bc;
     }
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxThreads)
+adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
+                const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, float dts,
+                float dx2, float dy2, double* __restrict__ part) {
+    extern __shared__ float lds[];
+    __shared__ double red[16];
+    const int R = RT > 0 ? RT : Rrt;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    adj_tile<CP, RT>(c, pin, pout, eps[2 * k], eps[2 * k + 1], H, W, C, R, tile, tiles_x, dts, dx2, dy2, part, lds,
+                     red);
+}
+
+// Transposed step k of several images in one launch.  p^{k+1} is read from
+// pa when K-1-k is even, else from pb, and p^k goes to the other buffer;
+// part receives K x tiles x 2 partials per job.
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxThreads)
+adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C, int Rrt) {
+    extern __shared__ float lds[];
+    __shared__ double red[16];
+    const int R = RT > 0 ? RT : Rrt;
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const StepJob& J = jobs[find_job(jobs, njobs, g)];
+    const size_t f = (size_t)J.H * J.W * C;
+    const bool even = ((K - 1 - k) & 1) == 0;
+    const float* e = J.eps + 2 * k;
+    adj_tile<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W, C, R,
+                     g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds, red);
 }
 
 // ----------------------------------------------------------------------------
@@ -365,6 +430,35 @@ reduce_rows_f64_kernel(const double* __restrict__ part, int nblk, int nq, double
     }
 }
 
+// Per-job reductions of FP64 rows (grid: rows x jobs x nq) and FP32 rows
+// (grid: jobs x nq), each with the same per-thread strides and block tree as
+// the single-image kernels above, so that a job's sums equal the single-image
+// ones bit for bit.
+__global__ void __launch_bounds__(kMaxThreads)
+reduce_jobs_f64_kernel(const RedJob* __restrict__ jobs, int nq) {
+    __shared__ double red[16];
+    const RedJob& J = jobs[blockIdx.y];
+    const int r = blockIdx.x, q = blockIdx.z;
+    if (r >= J.rows) return;
+    const double* base = J.part_d + (size_t)r * J.nblk * nq + q;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < J.nblk; i += blockDim.x) s += base[(size_t)i * nq];
+    s = block_sum_f64(s, red);
+    if (threadIdx.x == 0) J.out_d[r * nq + q] = J.scale * s;
+}
+
+__global__ void __launch_bounds__(kMaxThreads)
+reduce_jobs_kernel(const RedJob* __restrict__ jobs, int nq) {
+    __shared__ float red[16];
+    const RedJob& J = jobs[blockIdx.x];
+    const int q = blockIdx.y;
+    const float* base = J.part_f + q;
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < J.nblk; i += blockDim.x) s += base[(size_t)i * nq];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) J.out_f[q] = s;
+}
+
 // ----------------------------------------------------------------------------
 // Per-pixel primal/dual kernels.  grad# is the central difference of Def. 3.1,
 // zero on the first/last column (row) by the reflective rule.
@@ -381,13 +475,12 @@ __device__ __forceinline__ float grad_y(const float* __restrict__ c, size_t i, i
 
 // gK = area [ div(mu + rho (v - grad c)) + alpha (c - c0) ], div = -grad#^T, and the
 // per-pixel objective rho/2 |v - g + mu/rho|^2 + |v| + alpha/2 |c - c0|^2.
-__global__ void __launch_bounds__(kMaxThreads)
-terminal_kernel(const float* __restrict__ c, const float* __restrict__ c0, const float* __restrict__ v,
-                const float* __restrict__ mu, int H, int W, int C, float rho, float alpha, float area,
-                float inv2dx, float inv2dy, float* __restrict__ pK, float* __restrict__ part) {
-    __shared__ float red[16];
+__device__ __forceinline__ void terminal_block(const float* __restrict__ c, const float* __restrict__ c0,
+                                               const float* __restrict__ v, const float* __restrict__ mu, int H, int W,
+                                               int C, float rho, float alpha, float area, float inv2dx, float inv2dy,
+                                               float* __restrict__ pK, float* __restrict__ part, int blk, float* red) {
     const size_t N = (size_t)H * W;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = (size_t)blk * blockDim.x + threadIdx.x;
     float obj = 0.0f;
     if (i < N) {
         const int r = (int)(i / W), q = (int)(i % W);
@@ -443,18 +536,36 @@ terminal_kernel(const float* __restrict__ c, const float* __restrict__ c0, const
         obj = fmaf(0.5f * rho, sh2, sqrtf(nv2)) + 0.5f * alpha * nf2;
     }
     obj = block_sum(obj, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = obj;
+    if (threadIdx.x == 0) part[blk] = obj;
+}
+
+__global__ void __launch_bounds__(kMaxThreads)
+terminal_kernel(const float* __restrict__ c, const float* __restrict__ c0, const float* __restrict__ v,
+                const float* __restrict__ mu, int H, int W, int C, float rho, float alpha, float area,
+                float inv2dx, float inv2dy, float* __restrict__ pK, float* __restrict__ part) {
+    __shared__ float red[16];
+    terminal_block(c, c0, v, mu, H, W, C, rho, alpha, area, inv2dx, inv2dy, pK, part, blockIdx.x, red);
+}
+
+// Terminal condition / objective of several images: jobs[j].start is the first
+// global block of job j (one block = 256 consecutive pixels of one image).
+__global__ void __launch_bounds__(kMaxThreads)
+terminal_batched_kernel(const PixJob* __restrict__ jobs, int njobs, int C, float rho, float alpha) {
+    __shared__ float red[16];
+    const int g = blockIdx.x;
+    const PixJob& J = jobs[find_job(jobs, njobs, g)];
+    terminal_block(J.c, J.c0, J.v, J.mu, J.H, J.W, C, rho, alpha, J.area, J.inv2dx, J.inv2dy, J.pK, J.part,
+                   g - J.start, red);
 }
 
 // v = shrink(grad c - mu/rho) jointly over the 2C components of each pixel;
 // mu += gamma (v - grad c) when update_mu.  Partial sums (kPdQuantities).
-__global__ void __launch_bounds__(kMaxThreads)
-pd_step_kernel(const float* __restrict__ c, const float* __restrict__ c0, float* __restrict__ v,
-               float* __restrict__ mu, int update_mu, int H, int W, int C, float rho, float gamma,
-               float inv2dx, float inv2dy, float* __restrict__ part) {
-    __shared__ float red[16];
+__device__ __forceinline__ void pd_block(const float* __restrict__ c, const float* __restrict__ c0,
+                                         float* __restrict__ v, float* __restrict__ mu, int update_mu, int H, int W,
+                                         int C, float rho, float gamma, float inv2dx, float inv2dy,
+                                         float* __restrict__ part, int blk, float* red) {
     const size_t N = (size_t)H * W;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = (size_t)blk * blockDim.x + threadIdx.x;
     float qv[kPdQuantities] = {0, 0, 0, 0, 0, 0, 0};
     if (i < N) {
         const int r = (int)(i / W), q = (int)(i % W);
@@ -500,8 +611,24 @@ pd_step_kernel(const float* __restrict__ c, const float* __restrict__ c0, float*
 #pragma unroll
     for (int m = 0; m < kPdQuantities; ++m) {
         const float s = block_sum(qv[m], red);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * kPdQuantities + m] = s;
+        if (threadIdx.x == 0) part[(size_t)blk * kPdQuantities + m] = s;
     }
+}
+
+__global__ void __launch_bounds__(kMaxThreads)
+pd_step_kernel(const float* __restrict__ c, const float* __restrict__ c0, float* __restrict__ v,
+               float* __restrict__ mu, int update_mu, int H, int W, int C, float rho, float gamma,
+               float inv2dx, float inv2dy, float* __restrict__ part) {
+    __shared__ float red[16];
+    pd_block(c, c0, v, mu, update_mu, H, W, C, rho, gamma, inv2dx, inv2dy, part, blockIdx.x, red);
+}
+
+__global__ void __launch_bounds__(kMaxThreads)
+pd_step_batched_kernel(const PixJob* __restrict__ jobs, int njobs, int update_mu, int C, float rho, float gamma) {
+    __shared__ float red[16];
+    const int g = blockIdx.x;
+    const PixJob& J = jobs[find_job(jobs, njobs, g)];
+    pd_block(J.c, J.c0, J.v, J.mu, update_mu, J.H, J.W, C, rho, gamma, J.inv2dx, J.inv2dy, J.part, g - J.start, red);
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
@@ -594,6 +721,62 @@ hipError_t adj_launch_r(const float* c, const float* pin, float* pout, const flo
     return adj_launch_t<CP, 0>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
 }
 
+template <int CP, int RT>
+hipError_t fwdb_launch_t(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t, hipStream_t s) {
+    const size_t lds = tile_lds_bytes(CP, R, t, 1);
+    auto fn = fwd_step_batched_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty), lds, s, jobs, njobs, k, C, R);
+    return hipGetLastError();
+}
+
+template <int CP, int RT>
+hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t,
+                         hipStream_t s) {
+    const size_t lds = tile_lds_bytes(CP, R, t, 2);
+    auto fn = adj_step_batched_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty), lds, s, jobs, njobs, k, K, C, R);
+    return hipGetLastError();
+}
+
+template <int CP>
+hipError_t fwdb_launch_r(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t, hipStream_t s) {
+    if constexpr (CP <= 4) {
+        switch (R) {
+            case 1: return fwdb_launch_t<CP, 1>(jobs, njobs, total, k, C, R, t, s);
+            case 2: return fwdb_launch_t<CP, 2>(jobs, njobs, total, k, C, R, t, s);
+            case 3: return fwdb_launch_t<CP, 3>(jobs, njobs, total, k, C, R, t, s);
+            case 4: return fwdb_launch_t<CP, 4>(jobs, njobs, total, k, C, R, t, s);
+            case 5: return fwdb_launch_t<CP, 5>(jobs, njobs, total, k, C, R, t, s);
+            default: break;
+        }
+    }
+    return fwdb_launch_t<CP, 0>(jobs, njobs, total, k, C, R, t, s);
+}
+
+template <int CP>
+hipError_t adjb_launch_r(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t,
+                         hipStream_t s) {
+    if constexpr (CP <= 4) {
+        switch (R) {
+            case 1: return adjb_launch_t<CP, 1>(jobs, njobs, total, k, K, C, R, t, s);
+            case 2: return adjb_launch_t<CP, 2>(jobs, njobs, total, k, K, C, R, t, s);
+            case 3: return adjb_launch_t<CP, 3>(jobs, njobs, total, k, K, C, R, t, s);
+            case 4: return adjb_launch_t<CP, 4>(jobs, njobs, total, k, K, C, R, t, s);
+            case 5: return adjb_launch_t<CP, 5>(jobs, njobs, total, k, K, C, R, t, s);
+            default: break;
+        }
+    }
+    return adjb_launch_t<CP, 0>(jobs, njobs, total, k, K, C, R, t, s);
+}
+
 }  // namespace
 
 int tile_count(int H, int W, Tile t) { return ((W + t.tx - 1) / t.tx) * ((H + t.ty - 1) / t.ty); }
@@ -663,6 +846,61 @@ hipError_t launch_reduce_rows_f64(const double* part, int nrows, int nblk, int n
                                   float* out_f, hipStream_t s) {
     hipLaunchKernelGGL(reduce_rows_f64_kernel, dim3(nrows, nq), dim3(kMaxThreads), 0, s, part, nblk, nq, scale, out,
                        out_f);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_step_batched(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t,
+                                       hipStream_t s) {
+    switch (padded_channels(C)) {
+        case 1: return fwdb_launch_r<1>(jobs, njobs, total, k, C, R, t, s);
+        case 2: return fwdb_launch_r<2>(jobs, njobs, total, k, C, R, t, s);
+        case 3: return fwdb_launch_r<3>(jobs, njobs, total, k, C, R, t, s);
+        case 4: return fwdb_launch_r<4>(jobs, njobs, total, k, C, R, t, s);
+        case 8: return fwdb_launch_r<8>(jobs, njobs, total, k, C, R, t, s);
+        case 16: return fwdb_launch_r<16>(jobs, njobs, total, k, C, R, t, s);
+        case 31: return fwdb_launch_r<31>(jobs, njobs, total, k, C, R, t, s);
+        case 32: return fwdb_launch_r<32>(jobs, njobs, total, k, C, R, t, s);
+        case 64: return fwdb_launch_r<64>(jobs, njobs, total, k, C, R, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adjoint_step_batched(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t,
+                                       hipStream_t s) {
+    switch (padded_channels(C)) {
+        case 1: return adjb_launch_r<1>(jobs, njobs, total, k, K, C, R, t, s);
+        case 2: return adjb_launch_r<2>(jobs, njobs, total, k, K, C, R, t, s);
+        case 3: return adjb_launch_r<3>(jobs, njobs, total, k, K, C, R, t, s);
+        case 4: return adjb_launch_r<4>(jobs, njobs, total, k, K, C, R, t, s);
+        case 8: return adjb_launch_r<8>(jobs, njobs, total, k, K, C, R, t, s);
+        case 16: return adjb_launch_r<16>(jobs, njobs, total, k, K, C, R, t, s);
+        case 31: return adjb_launch_r<31>(jobs, njobs, total, k, K, C, R, t, s);
+        case 32: return adjb_launch_r<32>(jobs, njobs, total, k, K, C, R, t, s);
+        case 64: return adjb_launch_r<64>(jobs, njobs, total, k, K, C, R, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_terminal_batched(const PixJob* jobs, int njobs, int total, int C, float rho, float alpha,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(terminal_batched_kernel, dim3(total), dim3(kMaxThreads), 0, s, jobs, njobs, C, rho, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_pd_step_batched(const PixJob* jobs, int njobs, int total, int update_mu, int C, float rho,
+                                  float gamma, hipStream_t s) {
+    hipLaunchKernelGGL(pd_step_batched_kernel, dim3(total), dim3(kMaxThreads), 0, s, jobs, njobs, update_mu, C, rho,
+                       gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_jobs_f64(const RedJob* jobs, int njobs, int max_rows, int nq, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_jobs_f64_kernel, dim3(max_rows, njobs, nq), dim3(kMaxThreads), 0, s, jobs, nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_jobs(const RedJob* jobs, int njobs, int nq, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_jobs_kernel, dim3(njobs, nq), dim3(kMaxThreads), 0, s, jobs, nq);
     return hipGetLastError();
 }
 
