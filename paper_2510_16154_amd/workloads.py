@@ -53,3 +53,33 @@ VORONOI512 = Workload("voronoi512_rgb_r5_k50", 512, 512, 3, 12, 0.08, 1002, grad
 HYPER2048 = Workload("hyperspectral2048_c31_r2_k100", 2048, 2048, 31, 24, 0.05, 1003, spectra=True, R=2, K=100)
 
 ALL = {w.name: w for w in (VORONOI32, VORONOI512, HYPER2048)}
+
+
+@dataclass(frozen=True)
+class BatchWorkload:
+    """64 RGB Voronoi images with uneven, non-square sides uniform in [128, 1024],
+    4-16 regions, noise sigma uniform in [0.02, 0.1]; the 512 x 512 dynamics
+    (R = 5, K = 50) and a fixed 5 x 10 multiplier / DAL schedule."""
+    name: str = "batch64_rgb_128to1024_r5_k50"
+    n: int = 64
+    seed: int = 1004
+    C: int = 3
+    R: int = 5
+    K: int = 50
+    max_outer: int = 5
+    max_inner: int = 10
+    alpha: float = 3000.0
+
+    def specs(self):
+        from .synth import batch_shapes
+        return batch_shapes(self.n, self.seed)
+
+    def images(self):
+        return [voronoi_image(H, W, self.C, reg, sig, s) for (H, W, reg, sig, s) in self.specs()]
+
+    def params(self, **kw) -> Params:
+        p = Params(K=self.K, R=self.R, max_outer=self.max_outer, max_inner=self.max_inner, alpha=self.alpha)
+        return p.replace(**kw) if kw else p
+
+
+BATCH64 = BatchWorkload()
