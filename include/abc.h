@@ -71,7 +71,12 @@ typedef struct abc_params {
     int32_t tile_x;      /* interaction tile width in pixels; 0 => library default  */
     int32_t tile_y;      /* interaction tile height in pixels; 0 => library default */
     int32_t cost;        /* ABC_COST_TV or ABC_COST_QUADRATIC (see abc_solve)         */
+    int32_t adj_tile_x;  /* adjoint tile width; 0 => tile_x (or library default)     */
+    int32_t adj_tile_y;  /* adjoint tile height; 0 => tile_y (or library default)    */
+    int32_t flags;       /* ABC_FLAG_* bits                                          */
 } abc_params;
+
+#define ABC_FLAG_NO_GRAPHS 1 /* launch every sweep step directly instead of replaying captured HIP graphs */
 
 #define ABC_COST_TV 0        /* TV + fidelity (eq. cost_TV), method of multipliers (Alg. 2)  */
 #define ABC_COST_QUADRATIC 1 /* quadratic J (Def. 3.2), direct-adjoint loop alone (Alg. 1) */
@@ -220,6 +225,20 @@ typedef struct abc_image {
     float* mu;       /* H x W x 2 x C multiplier in/out, or NULL (start at 0) */
     int32_t H, W;
 } abc_image;
+
+/* Tile autotuner.  Times the forward and adjoint interaction kernels for every
+ * admissible tile shape on the image c0 (H x W x C, device) under p's window
+ * radius and channel count, and writes the fastest shapes into p->tile_x/y
+ * (forward) and p->adj_tile_x/y (adjoint).  Results do not depend on the tile
+ * shape (each pixel sums its window in a fixed order), only the time does.
+ *   cache_path (host, may be NULL): JSON file of earlier results keyed by GPU
+ *     architecture, C, R, H and W; a hit skips the timing, a miss appends.
+ *   ws: ABC_WS_TUNE bytes.  best_us (host, may be NULL): the two best
+ *     per-launch times in microseconds (0 on a cache hit).
+ * Synchronises the stream. */
+#define ABC_WS_TUNE 4
+int abc_autotune(const float* c0, int H, int W, int C, abc_params* p, const char* cache_path, void* ws,
+                 size_t ws_bytes, void* stream, double* best_us);
 
 /* Bytes of device workspace abc_solve_batched needs for n images of sizes
  * H[i] x W[i] x C.  Host only. */

@@ -19,6 +19,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "abc.h")
 ABC_OK, ABC_EINVAL, ABC_EHIP, ABC_ENONFINITE, ABC_ENOCONV = 0, -1, -2, -3, 1
 ABC_WS_SOLVE, ABC_WS_FORWARD, ABC_WS_ADJOINT, ABC_WS_PD = 0, 1, 2, 3
 ABC_COST_TV, ABC_COST_QUADRATIC = 0, 1
+ABC_WS_TUNE = 4
+ABC_FLAG_NO_GRAPHS = 1
 
 
 class AbcParams(ct.Structure):
@@ -30,6 +32,7 @@ class AbcParams(ct.Structure):
         ("tol_alm", ct.c_double), ("tol_dal", ct.c_double),
         ("sigma0", ct.c_double), ("armijo_b", ct.c_double), ("armijo_c", ct.c_double),
         ("ckpt_every", ct.c_int32), ("tile_x", ct.c_int32), ("tile_y", ct.c_int32), ("cost", ct.c_int32),
+        ("adj_tile_x", ct.c_int32), ("adj_tile_y", ct.c_int32), ("flags", ct.c_int32),
     ]
 
 
@@ -75,6 +78,9 @@ class Params:
     tile_x: int = 0
     tile_y: int = 0
     cost: int = 0  # ABC_COST_TV (0) or ABC_COST_QUADRATIC (1)
+    adj_tile_x: int = 0
+    adj_tile_y: int = 0
+    flags: int = 0  # ABC_FLAG_NO_GRAPHS (1): direct launches instead of captured sweeps
 
     def to_c(self) -> AbcParams:
         p = AbcParams()
@@ -141,6 +147,8 @@ def lib():
                               ct.POINTER(AbcStats), _vp, ct.c_size_t, _vp]
     L.abc_solve.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp, _vp, _vp, _vp, _vp,
                             ct.c_size_t, _vp, ct.POINTER(AbcStats), ct.POINTER(AbcSolveLog)]
+    L.abc_autotune.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), ct.c_char_p, _vp,
+                               ct.c_size_t, _vp, ct.POINTER(ct.c_double)]
     L.abc_workspace_bytes_batched.argtypes = [ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.c_int, ct.c_int,
                                               ct.POINTER(AbcParams), ct.POINTER(ct.c_size_t)]
     L.abc_solve_batched.argtypes = [ct.POINTER(AbcImage), ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp,
@@ -359,3 +367,17 @@ def abc_solve_batched(images, params: Params, eps=None, mu=None, ws=None):
                                  fin.ctypes.data_as(ct.POINTER(ct.c_double)))
     _check(rc, allow=(ABC_OK, ABC_ENOCONV))
     return outs, [_stats_dict(s) for s in st], fin
+
+
+def abc_autotune(c0, params: Params, cache_path=None):
+    """Tile shapes tuned on c0 (see abc_autotune in abc.h).  Returns (tuned Params,
+    (forward us, adjoint us) -- zeros on a cache hit)."""
+    torch = _torch()
+    H, W, C = c0.shape
+    nb = abc_workspace_bytes(ABC_WS_TUNE, H, W, C, params)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=c0.device)
+    p = params.to_c()
+    us = (ct.c_double * 2)()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().abc_autotune(_ptr(c0), H, W, C, ct.byref(p), path, ct.c_void_p(ws.data_ptr()), nb, _stream(), us))
+    return Params.from_c(p), (us[0], us[1])

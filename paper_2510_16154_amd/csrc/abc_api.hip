@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -49,6 +51,49 @@ struct Carve {
     }
 };
 
+// Captured HIP graphs of sweep launches, keyed by the caller.  A sweep is
+// recorded once on a private capture stream and replayed on the caller's
+// stream; kernels read controls, job tables and buffers through pointers
+// that stay fixed, so one recording serves every replay.
+struct GraphCache {
+    hipStream_t cap = nullptr;
+    hipStream_t last = nullptr;
+    std::map<std::array<long, 4>, hipGraphExec_t> execs;
+    GraphCache() = default;
+    GraphCache(const GraphCache&) = delete;
+    GraphCache& operator=(const GraphCache&) = delete;
+    ~GraphCache() {
+        if (last) (void)hipStreamSynchronize(last);
+        for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+    template <class F>
+    int run(bool enabled, const std::array<long, 4>& key, hipStream_t st, F&& record) {
+        last = st;
+        if (!enabled) return record(st);
+        auto it = execs.find(key);
+        if (it == execs.end()) {
+            if (!cap) ABC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            ABC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            const int rc = record(cap);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(cap, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(ABC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e2 != hipSuccess) return fail(ABC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+            it = execs.emplace(key, ex).first;
+        }
+        ABC_HIP(hipGraphLaunch(it->second, st));
+        return ABC_OK;
+    }
+};
+
 struct Shape {
     int H, W, C;
     size_t npix() const { return (size_t)H * W; }
@@ -88,12 +133,18 @@ int check_params(const abc_params* p) {
         return fail(ABC_EINVAL, "Armijo parameters: sigma0 > 0, b and c in (0,1)");
     if (p->ckpt_every < 0) return fail(ABC_EINVAL, "ckpt_every must be >= 0");
     if (p->cost != ABC_COST_TV && p->cost != ABC_COST_QUADRATIC) return fail(ABC_EINVAL, "unknown cost");
+    if (p->flags & ~ABC_FLAG_NO_GRAPHS) return fail(ABC_EINVAL, "unknown flag bits");
     return ABC_OK;
 }
 
 int pick_tile(const abc_params* p, int C, int fields, abc::Tile* t) {
-    if (p->tile_x > 0 || p->tile_y > 0) {
-        abc::Tile u{p->tile_x, p->tile_y};
+    int tx = p->tile_x, ty = p->tile_y;
+    if (fields == 2 && (p->adj_tile_x > 0 || p->adj_tile_y > 0)) {
+        tx = p->adj_tile_x;
+        ty = p->adj_tile_y;
+    }
+    if (tx > 0 || ty > 0) {
+        abc::Tile u{tx, ty};
         if (!abc::tile_ok(C, p->R, u, fields))
             return fail(ABC_EINVAL, "tile_x * tile_y must be a multiple of 64 and <= 256, and fit in LDS");
         *t = u;
@@ -224,16 +275,6 @@ int adjoint_steps(const float* const* states, int k0, int k1, const float* eps, 
     return ABC_OK;
 }
 
-// Reduced control gradient: G[k][m] (FP64) = dl/deps^k_m / dt = -5 s * (raw sums).
-int fetch_gradient(const double* part, int K, int tiles, double* Gdev, float s_norm, hipStream_t st,
-                   std::vector<double>& G) {
-    ABC_HIP(abc::launch_reduce_rows_f64(part, K, tiles, 2, -5.0 * (double)s_norm, Gdev, nullptr, st));
-    G.resize((size_t)K * 2);
-    ABC_HIP(hipMemcpyAsync(G.data(), Gdev, G.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    ABC_HIP(hipStreamSynchronize(st));
-    return ABC_OK;
-}
-
 int objective(const float* cK, const float* c0, const float* v, const float* mu, float* pK, const Shape& s,
               const abc_params* p, const PdWs& w, hipStream_t st, double* phi) {
     ABC_HIP(abc::launch_terminal(cK, c0, v, mu, s.H, s.W, s.C, p->rho, p->alpha, (float)s.area(), pK, w.part, st));
@@ -283,6 +324,10 @@ int check_finite(const float* x, size_t n, const PdWs& w, hipStream_t st, const 
 
 }  // namespace
 
+namespace {
+size_t tune_ws_bytes(int H, int W, int C);
+}
+
 // ===========================================================================
 extern "C" {
 
@@ -329,7 +374,11 @@ int abc_workspace_bytes(int kind, int H, int W, int C, const abc_params* p, size
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
     if (!bytes) return fail(ABC_EINVAL, "bytes is NULL");
-    if (kind < ABC_WS_SOLVE || kind > ABC_WS_PD) return fail(ABC_EINVAL, "unknown workspace kind");
+    if (kind < ABC_WS_SOLVE || kind > ABC_WS_TUNE) return fail(ABC_EINVAL, "unknown workspace kind");
+    if (kind == ABC_WS_TUNE) {
+        *bytes = tune_ws_bytes(H, W, C);
+        return ABC_OK;
+    }
     abc::Tile tf{32, 8}, ta{32, 8};
     if ((rc = pick_tile(p, C, 1, &tf))) return rc;
     if ((rc = pick_tile(p, C, 2, &ta))) return rc;
@@ -524,12 +573,26 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     };
     const size_t traj_stride = (size_t)K * f;  // offset of c^K inside a trajectory
     int base = 0, cand = 1, trial = 2;
+    GraphCache graphs;
+    const bool use_graphs = !(p->flags & ABC_FLAG_NO_GRAPHS) && p->R > 0;
+    // slot 0 of every trajectory holds c0 for the whole solve
+    for (int b = 0; b < 3; ++b) ABC_HIP(hipMemcpyAsync(w.traj[b], c0, f * sizeof(float), hipMemcpyDeviceToDevice, st));
+    // K forward steps into trajectory buffer `idx` under the controls eps[idx]
+    auto sweep = [&](int idx) -> int {
+        if (p->R == 0) return forward_sweep_full(c0, w.traj[idx], w.eps[idx], s, p, dts, tf, st);
+        return graphs.run(use_graphs, {0, idx, 0, 0}, st, [&](hipStream_t s2) -> int {
+            for (int k = 0; k < K; ++k)
+                ABC_HIP(abc::launch_forward_step(w.traj[idx] + k * f, w.traj[idx] + (k + 1) * f, w.eps[idx], k, H, W, C,
+                                                 p->R, dts, tf, s2));
+            return ABC_OK;
+        });
+    };
     // Armijo trial into buffer `trial`: eps(tau), forward sweep, Phi(tau), test.
     auto run_trial = [&](const std::vector<double>& G, double tau, double phi0, double* phit, bool* ok) -> int {
         project(G, tau, e_try);
         int r2 = upload(e_try, w.eps[trial]);
         if (r2) return r2;
-        if ((r2 = forward_sweep_full(c0, w.traj[trial], w.eps[trial], s, p, dts, tf, st))) return r2;
+        if ((r2 = sweep(trial))) return r2;
         if ((r2 = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, phit))) return r2;
         double ip = 0.0;
         for (int i = 0; i < 2 * K; ++i) ip += G[i] * (e_try[i] - e_base[i]);
@@ -549,7 +612,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
 
     // Alg. 2: forward integration, v^(0) = argmin_v L(c^(0), v, mu^(0)).
     if ((rc = upload(e_base, w.eps[base]))) return rc;
-    if ((rc = forward_sweep_full(c0, w.traj[base], w.eps[base], s, p, dts, tf, st))) return rc;
+    if ((rc = sweep(base))) return rc;
     if (!quad && (rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 0, s, p, w.pd, st, nullptr))) return rc;
 
     double sigma = p->sigma0;
@@ -575,10 +638,20 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
             if (p->R > 0) {
                 std::vector<const float*> states(K);
                 for (int k = 0; k < K; ++k) states[k] = w.traj[base] + (size_t)k * f;
-                if ((rc = adjoint_steps(states.data(), 0, K, w.eps[base], s, p, dts, ta, cur, spare, w.adj.part,
-                                        tiles, st)))
-                    return rc;
-                if ((rc = fetch_gradient(w.adj.part, K, tiles, w.G, snorm, st, G))) return rc;
+                rc = graphs.run(use_graphs, {1, base, 0, 0}, st, [&](hipStream_t s2) -> int {
+                    float* c2 = cur;
+                    float* sp2 = spare;
+                    int r3 = adjoint_steps(states.data(), 0, K, w.eps[base], s, p, dts, ta, c2, sp2, w.adj.part, tiles,
+                                           s2);
+                    if (r3) return r3;
+                    ABC_HIP(abc::launch_reduce_rows_f64(w.adj.part, K, tiles, 2, -5.0 * (double)snorm, w.G, nullptr,
+                                                        s2));
+                    return ABC_OK;
+                });
+                if (rc) return rc;
+                G.resize((size_t)K * 2);
+                ABC_HIP(hipMemcpyAsync(G.data(), w.G, G.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+                ABC_HIP(hipStreamSynchronize(st));
             } else {
                 G.assign((size_t)K * 2, 0.0);
             }
@@ -597,7 +670,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                 if (eps_replay) {
                     e_try.assign(eps_replay + slot * 2 * K, eps_replay + (slot + 1) * 2 * K);
                     if ((rc = upload(e_try, w.eps[trial]))) return rc;
-                    if ((rc = forward_sweep_full(c0, w.traj[trial], w.eps[trial], s, p, dts, tf, st))) return rc;
+                    if ((rc = sweep(trial))) return rc;
                     if ((rc = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, &phi_acc)))
                         return rc;
                 } else if ((rc = run_trial(G, accepted, phi0, &phi_acc, &ok))) {
@@ -779,9 +852,11 @@ struct Batch {
     bool quad;
     abc::Tile tf, ta;
     hipStream_t st;
+    bool use_graphs = false;
     std::vector<BImg> im;
     BatchWs w;
     std::vector<float> eps_host;  // mirror of eps_all
+    GraphCache graphs;
 
     float* eps_dev(int i, int slot) const { return w.eps_all + ((size_t)i * 3 + slot) * K * 2; }
 
@@ -819,19 +894,22 @@ struct Batch {
         }
         ABC_HIP(hipMemcpyAsync(w.step_jobs, jobs.data(), jobs.size() * sizeof(abc::StepJob), hipMemcpyHostToDevice,
                                st));
-        for (int k = 0; k < K; ++k) {
-            if (p->R == 0) {
+        if (p->R == 0) {
+            for (int k = 0; k < K; ++k)
                 for (size_t j = 0; j < who.size(); ++j) {
                     const BImg& m = im[who[j]];
                     float* t = m.traj[slot[j]];
                     ABC_HIP(hipMemcpyAsync(t + (size_t)(k + 1) * m.f, t, m.f * sizeof(float), hipMemcpyDeviceToDevice,
                                            st));
                 }
-            } else {
-                ABC_HIP(abc::launch_forward_step_batched(w.step_jobs, (int)jobs.size(), total, k, C, p->R, tf, st));
-            }
+            return ABC_OK;
         }
-        return ABC_OK;
+        const int nj = (int)jobs.size();
+        return graphs.run(use_graphs, {0, total, nj, 0}, st, [&](hipStream_t s2) -> int {
+            for (int k = 0; k < K; ++k)
+                ABC_HIP(abc::launch_forward_step_batched(w.step_jobs, nj, total, k, C, p->R, tf, s2));
+            return ABC_OK;
+        });
     }
 
     // Terminal condition (into pa) and/or objective of trajectory `slot[j]`; fills phi[j].
@@ -911,9 +989,14 @@ struct Batch {
                                    hipMemcpyHostToDevice, st));
             ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice,
                                    st));
-            for (int k = K - 1; k >= 0; --k)
-                ABC_HIP(abc::launch_adjoint_step_batched(w.step_jobs, (int)jobs.size(), total, k, K, C, p->R, ta, st));
-            ABC_HIP(abc::launch_reduce_jobs_f64(w.red_jobs, (int)reds.size(), K, 2, st));
+            const int nj = (int)jobs.size();
+            int r2 = graphs.run(use_graphs, {1, total, nj, 0}, st, [&](hipStream_t s2) -> int {
+                for (int k = K - 1; k >= 0; --k)
+                    ABC_HIP(abc::launch_adjoint_step_batched(w.step_jobs, nj, total, k, K, C, p->R, ta, s2));
+                ABC_HIP(abc::launch_reduce_jobs_f64(w.red_jobs, nj, K, 2, s2));
+                return ABC_OK;
+            });
+            if (r2) return r2;
             std::vector<double> g(who.size() * K * 2);
             ABC_HIP(hipMemcpyAsync(g.data(), w.g_all, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
             ABC_HIP(hipStreamSynchronize(st));
@@ -1036,6 +1119,7 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
     const size_t need = batch_ws_bytes(Hs.data(), Ws.data(), n, C, p, B.ta);
     if (!ws || ws_bytes < need) return fail(ABC_EINVAL, "batched workspace too small");
     B.st = (hipStream_t)stream;
+    B.use_graphs = !(p->flags & ABC_FLAG_NO_GRAPHS) && p->R > 0;
     const int K = p->K;
     Carve cv(ws);
     carve_batch(cv, n, K, B.w);
@@ -1307,3 +1391,164 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Tile autotuner with a JSON cache.
+namespace {
+
+struct TuneEntry {
+    int ftx, fty, atx, aty;
+    double fus, aus;
+};
+
+std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
+    std::map<std::string, TuneEntry> out;
+    if (!path) return out;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), fp)) {
+        const char* q1 = std::strchr(line, '"');
+        if (!q1) continue;
+        const char* q2 = std::strchr(q1 + 1, '"');
+        if (!q2) continue;
+        TuneEntry e;
+        if (std::sscanf(q2 + 1, ": {\"fwd\": [%d, %d], \"adj\": [%d, %d], \"fwd_us\": %lf, \"adj_us\": %lf}", &e.ftx,
+                        &e.fty, &e.atx, &e.aty, &e.fus, &e.aus) == 6)
+            out[std::string(q1 + 1, q2)] = e;
+    }
+    std::fclose(fp);
+    return out;
+}
+
+bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return false;
+    std::fprintf(fp, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m) {
+        const TuneEntry& e = kv.second;
+        std::fprintf(fp, "  \"%s\": {\"fwd\": [%d, %d], \"adj\": [%d, %d], \"fwd_us\": %.3f, \"adj_us\": %.3f}%s\n",
+                     kv.first.c_str(), e.ftx, e.fty, e.atx, e.aty, e.fus, e.aus, (++i < m.size()) ? "," : "");
+    }
+    std::fprintf(fp, "}\n");
+    std::fclose(fp);
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+const abc::Tile kTuneCands[] = {{32, 8}, {16, 16}, {64, 4}, {128, 2}, {16, 8}, {32, 4}, {64, 2},
+                                {8, 16}, {8, 8},   {16, 4}, {32, 2}, {64, 1}};
+
+size_t tune_ws_bytes(int H, int W, int C) {
+    Carve cv(nullptr);
+    const size_t f = (size_t)H * W * C;
+    cv.take<float>(f);
+    cv.take<float>(f);
+    cv.take<float>(2);
+    int maxt = 0;
+    for (const abc::Tile& t : kTuneCands) maxt = std::max(maxt, abc::tile_count(H, W, t));
+    cv.take<double>((size_t)maxt * 2);
+    return cv.used;
+}
+
+}  // namespace
+
+extern "C" int abc_autotune(const float* c0, int H, int W, int C, abc_params* p, const char* cache_path, void* ws,
+                            size_t ws_bytes, void* stream, double* best_us) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if ((rc = check_shape(H, W, C))) return rc;
+    if (!c0) return fail(ABC_EINVAL, "c0 must be non-NULL");
+    if (best_us) best_us[0] = best_us[1] = 0.0;
+    if (p->R == 0) return ABC_OK;
+    int dev = 0;
+    ABC_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    ABC_HIP(hipGetDeviceProperties(&prop, dev));
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    char keybuf[160];
+    std::snprintf(keybuf, sizeof(keybuf), "%s|C=%d|R=%d|H=%d|W=%d", arch.c_str(), C, p->R, H, W);
+    const std::string key(keybuf);
+    std::map<std::string, TuneEntry> cache = read_tune_cache(cache_path);
+    auto hit = cache.find(key);
+    if (hit != cache.end() && abc::tile_ok(C, p->R, abc::Tile{hit->second.ftx, hit->second.fty}, 1) &&
+        abc::tile_ok(C, p->R, abc::Tile{hit->second.atx, hit->second.aty}, 2)) {
+        p->tile_x = hit->second.ftx;
+        p->tile_y = hit->second.fty;
+        p->adj_tile_x = hit->second.atx;
+        p->adj_tile_y = hit->second.aty;
+        return ABC_OK;
+    }
+    if (!ws || ws_bytes < tune_ws_bytes(H, W, C)) return fail(ABC_EINVAL, "autotune workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t f = (size_t)H * W * C;
+    Carve cv(ws);
+    float* out = cv.take<float>(f);
+    float* pout = cv.take<float>(f);
+    float* eps = cv.take<float>(2);
+    double* part = nullptr;
+    {
+        int maxt = 0;
+        for (const abc::Tile& t : kTuneCands) maxt = std::max(maxt, abc::tile_count(H, W, t));
+        part = cv.take<double>((size_t)maxt * 2);
+    }
+    const float e2[2] = {p->eps_init, p->eps_init};
+    ABC_HIP(hipMemcpyAsync(eps, e2, sizeof(e2), hipMemcpyHostToDevice, st));
+    const Shape s{H, W, C};
+    const float dts = p->dt * norm_factor(p, s);
+    hipEvent_t ev0, ev1;
+    ABC_HIP(hipEventCreate(&ev0));
+    ABC_HIP(hipEventCreate(&ev1));
+    TuneEntry best{0, 0, 0, 0, 1e30, 1e30};
+    constexpr int kReps = 5;
+    for (int kind = 0; kind < 2; ++kind) {
+        for (const abc::Tile& t : kTuneCands) {
+            if (!abc::tile_ok(C, p->R, t, kind + 1)) continue;
+            auto launch = [&]() -> hipError_t {
+                return kind == 0 ? abc::launch_forward_step(c0, out, eps, 0, H, W, C, p->R, dts, t, st)
+                                 : abc::launch_adjoint_step(c0, c0, pout, eps, 0, H, W, C, p->R, dts, t, part, st);
+            };
+            hipError_t e = launch();  // warm-up (also sets the LDS attribute)
+            if (e != hipSuccess) continue;
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                ABC_HIP(hipEventRecord(ev0, st));
+                for (int i = 0; i < kReps; ++i) ABC_HIP(launch());
+                ABC_HIP(hipEventRecord(ev1, st));
+                ABC_HIP(hipEventSynchronize(ev1));
+                float ms = 0.0f;
+                ABC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                ms_best = std::min(ms_best, ms);
+            }
+            const double us = 1e3 * (double)ms_best / kReps;
+            if (kind == 0 && us < best.fus) {
+                best.fus = us;
+                best.ftx = t.tx;
+                best.fty = t.ty;
+            }
+            if (kind == 1 && us < best.aus) {
+                best.aus = us;
+                best.atx = t.tx;
+                best.aty = t.ty;
+            }
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (best.ftx == 0 || best.atx == 0) return fail(ABC_EINVAL, "no admissible tile for this channel count and radius");
+    p->tile_x = best.ftx;
+    p->tile_y = best.fty;
+    p->adj_tile_x = best.atx;
+    p->adj_tile_y = best.aty;
+    if (best_us) {
+        best_us[0] = best.fus;
+        best_us[1] = best.aus;
+    }
+    if (cache_path) {
+        cache[key] = best;
+        if (!write_tune_cache(cache_path, cache)) return fail(ABC_EINVAL, std::string("cannot write ") + cache_path);
+    }
+    return ABC_OK;
+}
