@@ -74,6 +74,7 @@ typedef struct abc_params {
     int32_t adj_tile_x;  /* adjoint tile width; 0 => tile_x (or library default)     */
     int32_t adj_tile_y;  /* adjoint tile height; 0 => tile_y (or library default)    */
     int32_t flags;       /* ABC_FLAG_* bits                                          */
+    double stop_K;       /* > 0: also stop after a multiplier iteration once K <= stop_K */
 } abc_params;
 
 #define ABC_FLAG_NO_GRAPHS 1 /* launch every sweep step directly instead of replaying captured HIP graphs */
@@ -186,13 +187,16 @@ int abc_pd_step(const float* cK, const float* c0, int H, int W, int C, const abc
  *                  gradient is still computed and logged.
  *   grad_out:      [slots][K][2] control gradient G (FP64) of each DAL
  *                  iteration (dPhi/deps^k divided by dt).
- *   phi_out:       [slots][3] objective before the step, after it, trials. */
+ *   phi_out:       [slots][3] objective before the step, after it, trials.
+ *   outer_out:     [max_outer][4] after each multiplier iteration: K, L,
+ *                  r_rel and the elapsed milliseconds since the call began. */
 typedef struct abc_solve_log {
     const double* decisions_in;
     double* decisions_out;
     const double* eps_replay;
     double* grad_out;
     double* phi_out;
+    double* outer_out;
 } abc_solve_log;
 
 /* Full solve: method of multipliers (Alg. 2) whose control argmin is the

@@ -32,14 +32,14 @@ class AbcParams(ct.Structure):
         ("tol_alm", ct.c_double), ("tol_dal", ct.c_double),
         ("sigma0", ct.c_double), ("armijo_b", ct.c_double), ("armijo_c", ct.c_double),
         ("ckpt_every", ct.c_int32), ("tile_x", ct.c_int32), ("tile_y", ct.c_int32), ("cost", ct.c_int32),
-        ("adj_tile_x", ct.c_int32), ("adj_tile_y", ct.c_int32), ("flags", ct.c_int32),
+        ("adj_tile_x", ct.c_int32), ("adj_tile_y", ct.c_int32), ("flags", ct.c_int32), ("stop_K", ct.c_double),
     ]
 
 
 class AbcSolveLog(ct.Structure):
     _fields_ = [("decisions_in", ct.POINTER(ct.c_double)), ("decisions_out", ct.POINTER(ct.c_double)),
                 ("eps_replay", ct.POINTER(ct.c_double)), ("grad_out", ct.POINTER(ct.c_double)),
-                ("phi_out", ct.POINTER(ct.c_double))]
+                ("phi_out", ct.POINTER(ct.c_double)), ("outer_out", ct.POINTER(ct.c_double))]
 
 
 class AbcImage(ct.Structure):
@@ -81,6 +81,7 @@ class Params:
     adj_tile_x: int = 0
     adj_tile_y: int = 0
     flags: int = 0  # ABC_FLAG_NO_GRAPHS (1): direct launches instead of captured sweeps
+    stop_K: float = 0.0  # > 0: stop once the TV energy K reaches this value
 
     def to_c(self) -> AbcParams:
         p = AbcParams()
@@ -287,7 +288,8 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     """Full solve (see abc_solve in abc.h).  Returns a dict with the field ``c``,
     ``eps`` and ``mu`` (the tensors passed in, updated, when given), ``v``,
     ``stats``, and the logs (numpy): ``decisions`` (max_outer x max_inner),
-    ``grad_log`` (M x P x K x 2) and ``phi_log`` (M x P x 3).  ``decisions``
+    ``grad_log`` (M x P x K x 2), ``phi_log`` (M x P x 3) and ``outer_log``
+    (M x 4: K, L, r_rel, elapsed ms after each multiplier iteration).  ``decisions``
     and ``eps_replay`` (M x P x K x 2) replay a recorded control argmin."""
     import numpy as np
     torch = _torch()
@@ -304,6 +306,7 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     dec_out = np.zeros((M, P), dtype=np.float64)
     grad_log = np.zeros((M, P, K, 2), dtype=np.float64)
     phi_log = np.zeros((M, P, 3), dtype=np.float64)
+    outer_log = np.zeros((M, 4), dtype=np.float64)
     log = AbcSolveLog()
     keep = []
     if decisions is not None:
@@ -317,13 +320,14 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     log.decisions_out = dec_out.ctypes.data_as(dp)
     log.grad_out = grad_log.ctypes.data_as(dp)
     log.phi_out = phi_log.ctypes.data_as(dp)
+    log.outer_out = outer_log.ctypes.data_as(dp)
     st = AbcStats()
     p = params.to_c()
     rc = lib().abc_solve(_ptr(c0), H, W, C, ct.byref(p), _ptr(eps), _ptr(mu), _ptr(v), _ptr(c_out),
                          ct.c_void_p(ws.data_ptr()), nb, _stream(), ct.byref(st), ct.byref(log))
     _check(rc, allow=(ABC_OK, ABC_ENOCONV))
     return {"c": c_out, "eps": eps, "mu": mu, "v": v, "stats": _stats_dict(st), "decisions": dec_out,
-            "grad_log": grad_log, "phi_log": phi_log, "status": rc}
+            "grad_log": grad_log, "phi_log": phi_log, "outer_log": outer_log, "status": rc}
 
 
 def abc_workspace_bytes_batched(shapes, C: int, params: Params) -> int:

@@ -134,6 +134,7 @@ int check_params(const abc_params* p) {
     if (p->ckpt_every < 0) return fail(ABC_EINVAL, "ckpt_every must be >= 0");
     if (p->cost != ABC_COST_TV && p->cost != ABC_COST_QUADRATIC) return fail(ABC_EINVAL, "unknown cost");
     if (p->flags & ~ABC_FLAG_NO_GRAPHS) return fail(ABC_EINVAL, "unknown flag bits");
+    if (!(p->stop_K >= 0.0)) return fail(ABC_EINVAL, "stop_K must be >= 0");
     return ABC_OK;
 }
 
@@ -522,7 +523,9 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     const double* eps_replay = log ? log->eps_replay : nullptr;
     double* grad_out = log ? log->grad_out : nullptr;
     double* phi_out = log ? log->phi_out : nullptr;
+    double* outer_out = log ? log->outer_out : nullptr;
     if (eps_replay && !decisions_in) return fail(ABC_EINVAL, "eps_replay needs decisions_in");
+    const auto t_start = std::chrono::steady_clock::now();
     const Shape s{H, W, C};
     abc::Tile tf, ta;
     if ((rc = pick_tile(p, C, 1, &tf))) return rc;
@@ -609,6 +612,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     if (decisions_out) std::fill(decisions_out, decisions_out + nslots, 0.0);
     if (grad_out) std::fill(grad_out, grad_out + nslots * 2 * K, 0.0);
     if (phi_out) std::fill(phi_out, phi_out + nslots * 3, 0.0);
+    if (outer_out) std::fill(outer_out, outer_out + (size_t)M * 4, 0.0);
 
     // Alg. 2: forward integration, v^(0) = argmin_v L(c^(0), v, mu^(0)).
     if ((rc = upload(e_base, w.eps[base]))) return rc;
@@ -741,7 +745,15 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
         S.outer_iters = j + 1;
         S.gap_rel = std::isnan(L_prev) ? NAN : std::fabs(E.L - L_prev) / std::fabs(L_prev);
         L_prev = E.L;
+        if (outer_out) {
+            outer_out[4 * j + 0] = E.K;
+            outer_out[4 * j + 1] = E.L;
+            outer_out[4 * j + 2] = E.r_rel;
+            outer_out[4 * j + 3] =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        }
         if (p->tol_alm > 0.0 && E.r_rel < p->tol_alm) break;
+        if (p->stop_K > 0.0 && E.K <= p->stop_K) break;
     }
     if (quad) {
         // TV and fidelity of the final field from the pd kernel on scratch copies (v, mu stay 0);
@@ -1315,7 +1327,7 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
             m.S.outer_iters = j + 1;
             m.S.gap_rel = std::isnan(m.L_prev) ? NAN : std::fabs(m.E.L - m.L_prev) / std::fabs(m.L_prev);
             m.L_prev = m.E.L;
-            if ((p->tol_alm > 0.0 && m.E.r_rel < p->tol_alm) || j + 1 == M) {
+            if ((p->tol_alm > 0.0 && m.E.r_rel < p->tol_alm) || (p->stop_K > 0.0 && m.E.K <= p->stop_K) || j + 1 == M) {
                 m.outer_done = true;
                 m.finish_ms = t_now;
             }
