@@ -265,6 +265,44 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
 int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, void* ws, size_t ws_bytes,
                       void* stream, abc_stats* st, double* finish_ms);
 
+/* ---- Learned warm start ---------------------------------------------------
+ * A convolutional encoder-decoder predicting a starting multiplier field mu0
+ * (H x W x 2 x 3, inside the unit ball per pixel) and starting controls eps0
+ * (K x 2, inside E) from an RGB image, to start abc_solve (Alg. 2) closer to
+ * its end point.  Layers (3 x 3 convolutions, zero padding, ReLU):
+ *   3->16 (full res), 2x2 average pool, 16->32, 32->64 (half res),
+ *   2x nearest upsample concatenated with the first layer's output (80),
+ *   80->32, 32->6 (full res); mu0 = z / max(1, |z|);
+ *   eps0 = eps_min + (eps_max - eps_min) sigmoid(Wl mean(64-ch features) + bl).
+ * Weights are an FP32 blob (layout: per conv layer W[9 Cin][Cout] with row
+ * (kh*3 + kw)*Cin + ci, then b[Cout]; then Wl[64][2K], bl[2K]).  Convolutions
+ * run as BF16 x BF16 -> FP32 on the matrix cores (operands rounded to BF16).
+ * Images are B x H x W x 3 FP32 with H, W even. */
+
+/* Number of FP32 parameters for K control steps (K <= 128).  Host only. */
+int abc_wsnet_param_count(int K, size_t* n);
+
+/* Workspace bytes for a batch (train != 0: forward + backward).  Host only. */
+int abc_wsnet_workspace_bytes(int B, int H, int W, int K, int train, size_t* bytes);
+
+/* mu0 (B x H x W x 6) and eps0 (B x K x 2, in p's box E).  Synchronises. */
+int abc_wsnet_forward(const float* params, const float* x, int B, int H, int W, int K, const abc_params* p,
+                      float* mu0, float* eps0, void* ws, size_t ws_bytes, void* stream);
+
+/* Loss = mean_pixels |mu0 - mu_t|^2 + w_eps mean (e - e_t)^2 (e, e_t the controls
+ * mapped to [0,1] by E) and its gradient in the parameters (grad, same layout
+ * as params; overwritten).  loss (host) may be NULL; otherwise synchronises. */
+int abc_wsnet_loss_grad(const float* params, const float* x, const float* mu_t, const float* eps_t, int B, int H,
+                        int W, int K, const abc_params* p, float w_eps, float* grad, double* loss, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* One Adam step (bias-corrected, step t >= 1) on n parameters.  Asynchronous. */
+int abc_wsnet_adam(float* params, const float* grad, float* m, float* v, size_t n, int t, float lr, float b1,
+                   float b2, float eps, void* stream);
+
+/* Description of the calling thread's last warm-start failure. */
+const char* abc_wsnet_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -385,3 +385,74 @@ def abc_autotune(c0, params: Params, cache_path=None):
     path = cache_path.encode() if cache_path else None
     _check(lib().abc_autotune(_ptr(c0), H, W, C, ct.byref(p), path, ct.c_void_p(ws.data_ptr()), nb, _stream(), us))
     return Params.from_c(p), (us[0], us[1])
+
+
+# ------------------------------------------------------------------ learned warm start
+def _wsnet_lib():
+    L = lib()
+    if not getattr(L, "_wsnet_ready", False):
+        L.abc_wsnet_param_count.argtypes = [ct.c_int, ct.POINTER(ct.c_size_t)]
+        L.abc_wsnet_workspace_bytes.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                                ct.POINTER(ct.c_size_t)]
+        L.abc_wsnet_forward.argtypes = [_vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp,
+                                        _vp, _vp, ct.c_size_t, _vp]
+        L.abc_wsnet_loss_grad.argtypes = [_vp, _vp, _vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                          ct.POINTER(AbcParams), ct.c_float, _vp, ct.POINTER(ct.c_double), _vp,
+                                          ct.c_size_t, _vp]
+        L.abc_wsnet_adam.argtypes = [_vp, _vp, _vp, _vp, ct.c_size_t, ct.c_int, ct.c_float, ct.c_float, ct.c_float,
+                                     ct.c_float, _vp]
+        L.abc_wsnet_last_error.restype = ct.c_char_p
+        L._wsnet_ready = True
+    return L
+
+
+def _wcheck(rc):
+    if rc != ABC_OK:
+        raise AbcError(rc, _wsnet_lib().abc_wsnet_last_error().decode())
+
+
+def abc_wsnet_param_count(K: int) -> int:
+    n = ct.c_size_t(0)
+    _wcheck(_wsnet_lib().abc_wsnet_param_count(K, ct.byref(n)))
+    return n.value
+
+
+def abc_wsnet_forward(params, x, K: int, box: Params, ws=None):
+    """(mu0 B x H x W x 6, eps0 B x K x 2) predicted for the images x (B x H x W x 3)."""
+    torch = _torch()
+    B, H, W, _ = x.shape
+    L = _wsnet_lib()
+    nb_ = ct.c_size_t(0)
+    _wcheck(L.abc_wsnet_workspace_bytes(B, H, W, K, 0, ct.byref(nb_)))
+    if ws is None or ws.numel() < nb_.value:
+        ws = torch.empty(nb_.value, dtype=torch.uint8, device=x.device)
+    mu0 = torch.empty((B, H, W, 6), dtype=torch.float32, device=x.device)
+    eps0 = torch.empty((B, K, 2), dtype=torch.float32, device=x.device)
+    p = box.to_c()
+    _wcheck(L.abc_wsnet_forward(_ptr(params), _ptr(x), B, H, W, K, ct.byref(p), _ptr(mu0), _ptr(eps0),
+                                ct.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return mu0, eps0
+
+
+def abc_wsnet_loss_grad(params, x, mu_t, eps_t, K: int, box: Params, w_eps: float, grad=None, ws=None):
+    """(loss, gradient in the parameters) of the warm-start network on one batch."""
+    torch = _torch()
+    B, H, W, _ = x.shape
+    L = _wsnet_lib()
+    nb_ = ct.c_size_t(0)
+    _wcheck(L.abc_wsnet_workspace_bytes(B, H, W, K, 1, ct.byref(nb_)))
+    if ws is None or ws.numel() < nb_.value:
+        ws = torch.empty(nb_.value, dtype=torch.uint8, device=x.device)
+    if grad is None:
+        grad = torch.empty_like(params)
+    loss = ct.c_double(0.0)
+    p = box.to_c()
+    _wcheck(L.abc_wsnet_loss_grad(_ptr(params), _ptr(x), _ptr(mu_t), _ptr(eps_t), B, H, W, K, ct.byref(p),
+                                  float(w_eps), _ptr(grad), ct.byref(loss), ct.c_void_p(ws.data_ptr()), ws.numel(),
+                                  _stream()))
+    return loss.value, grad
+
+
+def abc_wsnet_adam(params, grad, m, v, t: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    _wcheck(_wsnet_lib().abc_wsnet_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(t),
+                                        float(lr), float(b1), float(b2), float(eps), _stream()))

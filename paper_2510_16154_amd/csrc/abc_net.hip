@@ -1,0 +1,712 @@
+// Learned warm start for the solver: a small convolutional encoder-decoder that
+// maps an image to a starting multiplier field mu0 and starting controls eps0.
+//
+// Network (NHWC activations in FP32, weights kept in FP32 and used as BF16 copies,
+// every convolution accumulates in FP32 on the matrix cores):
+//   a1 = relu(conv3x3(x; 3 -> 16))                 H   x W
+//   p1 = avgpool2(a1)                               H/2 x W/2
+//   a2 = relu(conv3x3(p1; 16 -> 32))                H/2 x W/2
+//   a3 = relu(conv3x3(a2; 32 -> 64))                H/2 x W/2
+//   cat = [upsample2(a3), a1]                       H   x W, 80 channels
+//   a4 = relu(conv3x3(cat; 80 -> 32))               H   x W
+//   z  = conv3x3(a4; 32 -> 6)                       H   x W
+//   mu0 = z / max(1, |z|)      (per pixel, the 6 = 2 x 3 components: inside the unit ball)
+//   e  = sigmoid(Wl mean(a3) + bl)                  per image, 2K values
+//   eps0 = eps_min + (eps_max - eps_min) e
+// Loss per batch: mean over pixels of |mu0 - mu*|^2 + w_eps * mean over (image, k, m) of (e - e*)^2,
+// e* = (eps* - eps_min) / (eps_max - eps_min).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: one wavefront owns a
+// 16 (pixels) x 16 (output channels) tile and walks K = 9 Cin in steps of 32, gathering
+// its operand fragments straight from the NHWC activations (zero outside the image).
+// The data gradient is the same kernel on the output gradient with the taps flipped
+// and the weight matrix transposed; the weight gradient contracts over pixels in
+// chunks whose partial sums are added in a fixed order by a second kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/abc.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;       // threads of the elementwise kernels
+constexpr int kChunk = 1024;  // pixels per weight-gradient partial
+
+thread_local std::string g_net_error;
+
+int nfail(int code, const std::string& m) {
+    g_net_error = m;
+    return code;
+}
+
+#define NET_HIP(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return nfail(ABC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernels.
+
+// Y[b, p, yoff + co] = act(bias[co] + sum_{t, ci} bf16(X[b, p + off(t), ci]) * Wb[t * Cin + ci][co]).
+// Grid (ceil(HW / 16), ceil(Cout / 16), B), one wavefront per workgroup.
+__global__ void __launch_bounds__(64) conv3x3_kernel(const float* __restrict__ X, int Cin, const __bf16* __restrict__ Wb,
+                                                     const float* __restrict__ bias, float* __restrict__ Y, int Cout,
+                                                     int ystride, int yoff, int H, int W, int relu) {
+    const int l = threadIdx.x;
+    const int b = blockIdx.z;
+    const int HW = H * W;
+    const int Ktot = 9 * Cin;
+    const float* Xb = X + (size_t)b * HW * Cin;
+    const int prow = blockIdx.x * 16 + (l & 15);
+    const int py = prow / W, px = prow - (prow / W) * W;
+    const int col = blockIdx.y * 16 + (l & 15);
+    const int kg = (l >> 4) * 8;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kc = 0; kc < Ktot; kc += 32) {
+        bf16x8 a, w;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc + kg + j;
+            float xv = 0.0f, wv = 0.0f;
+            if (k < Ktot) {
+                const int t = k / Cin, ci = k - t * Cin;
+                const int yy = py + t / 3 - 1, xx = px + t % 3 - 1;
+                if (prow < HW && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
+                    xv = Xb[((size_t)yy * W + xx) * Cin + ci];
+                if (col < Cout) wv = (float)Wb[(size_t)k * Cout + col];
+            }
+            a[j] = (__bf16)xv;
+            w[j] = (__bf16)wv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc, 0, 0, 0);
+    }
+    if (col >= Cout) return;
+    const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int p = blockIdx.x * 16 + (l >> 4) * 4 + i;
+        if (p < HW) {
+            float v = acc[i] + bv;
+            if (relu) v = fmaxf(v, 0.0f);
+            Y[((size_t)b * HW + p) * ystride + yoff + col] = v;
+        }
+    }
+}
+
+// part[c][k][co] = sum over pixels q of chunk c (flattened over the batch) of
+//   bf16(X[q + off(t), ci]) * bf16(dY[q, co]),  k = t * Cin + ci.
+// Grid (chunks, ceil(9 Cin / 16), ceil(Cout / 16)), one wavefront per workgroup.
+__global__ void __launch_bounds__(64) conv3x3_wgrad_kernel(const float* __restrict__ X, int Cin,
+                                                           const float* __restrict__ dY, int Cout, int H, int W, int B,
+                                                           float* __restrict__ part) {
+    const int l = threadIdx.x;
+    const int HW = H * W;
+    const int Ktot = 9 * Cin;
+    const int krow = blockIdx.y * 16 + (l & 15);
+    const int col = blockIdx.z * 16 + (l & 15);
+    const int t = krow / Cin, ci = krow - (krow / Cin) * Cin;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int kg = (l >> 4) * 8;
+    const int q_begin = blockIdx.x * kChunk;
+    const int q_end = min(q_begin + kChunk, B * HW);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int q0 = q_begin; q0 < q_end; q0 += 32) {
+        bf16x8 a, g;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int q = q0 + kg + j;
+            float xv = 0.0f, gv = 0.0f;
+            if (q < q_end) {
+                const int b = q / HW, p = q - (q / HW) * HW;
+                const int y = p / W, x = p - (p / W) * W;
+                const int yy = y + dy, xx = x + dx;
+                if (krow < Ktot && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
+                    xv = X[(((size_t)b * H + yy) * W + xx) * Cin + ci];
+                if (col < Cout) gv = dY[(size_t)q * Cout + col];
+            }
+            a[j] = (__bf16)xv;
+            g[j] = (__bf16)gv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, g, acc, 0, 0, 0);
+    }
+    if (col >= Cout) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = blockIdx.y * 16 + (l >> 4) * 4 + i;
+        if (k < Ktot) part[((size_t)blockIdx.x * Ktot + k) * Cout + col] = acc[i];
+    }
+}
+
+// out[i] = sum_c part[c * n + i] in chunk order.
+__global__ void __launch_bounds__(kT) sum_chunks_kernel(const float* __restrict__ part, int nchunks, int n,
+                                                        float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * n + i];
+    out[i] = s;
+}
+
+__device__ __forceinline__ float wsum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of v over a 256-thread block, valid in thread 0.
+__device__ __forceinline__ float bsum(float v, float* red) {
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float s = 0.0f;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kT / 64; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+// out[co] = sum over rows r of X[r * C + co]   (bias gradient; one block per channel).
+__global__ void __launch_bounds__(kT) colsum_kernel(const float* __restrict__ X, size_t rows, int C,
+                                                    float* __restrict__ out) {
+    __shared__ float red[4];
+    const int co = blockIdx.x;
+    float s = 0.0f;
+    for (size_t r = threadIdx.x; r < rows; r += kT) s += X[r * C + co];
+    s = bsum(s, red);
+    if (threadIdx.x == 0) out[co] = s;
+}
+
+// Out[b][t' * Cout + co][ci] = bf16(W[(8 - t') * Cin + ci][co]) and Wb = bf16(W).
+__global__ void __launch_bounds__(kT) weights_bf16_kernel(const float* __restrict__ Wt, int Cin, int Cout,
+                                                          __bf16* __restrict__ Wb, __bf16* __restrict__ Wf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = 9 * Cin * Cout;
+    if (i >= n) return;
+    const int co = i % Cout, k = i / Cout;
+    const int t = k / Cin, ci = k % Cin;
+    const __bf16 v = (__bf16)Wt[i];
+    Wb[i] = v;
+    Wf[((size_t)(8 - t) * Cout + co) * Cin + ci] = v;
+}
+
+__global__ void __launch_bounds__(kT) avgpool2_kernel(const float* __restrict__ A, int H, int W, int C, int B,
+                                                      float* __restrict__ P) {
+    const size_t n = (size_t)B * (H / 2) * (W / 2) * C;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = i % C;
+    size_t r = i / C;
+    const int x = r % (W / 2);
+    r /= (W / 2);
+    const int y = r % (H / 2);
+    const int b = (int)(r / (H / 2));
+    const float* a = A + (((size_t)b * H + 2 * y) * W + 2 * x) * C + c;
+    P[i] = 0.25f * (a[0] + a[C] + a[(size_t)W * C] + a[(size_t)W * C + C]);
+}
+
+// dA[b, y, x, c] = dcat[b, y, x, 64 + c] + 0.25 dP[b, y/2, x/2, c]   (a1 feeds the pool and the skip)
+__global__ void __launch_bounds__(kT) a1_grad_kernel(const float* __restrict__ dcat, const float* __restrict__ dP,
+                                                     int H, int W, int C, int Ccat, int coff, int B,
+                                                     float* __restrict__ dA) {
+    const size_t n = (size_t)B * H * W * C;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = i % C;
+    size_t r = i / C;
+    const int x = r % W;
+    r /= W;
+    const int y = r % H;
+    const int b = (int)(r / H);
+    const size_t pix = ((size_t)b * H + y) * W + x;
+    dA[i] = dcat[pix * Ccat + coff + c] + 0.25f * dP[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+}
+
+// cat[b, y, x, 0:C3] = a3[b, y/2, x/2, :], cat[b, y, x, C3:C3+C1] = a1[b, y, x, :]
+__global__ void __launch_bounds__(kT) up_concat_kernel(const float* __restrict__ a3, int C3, const float* __restrict__ a1,
+                                                       int C1, int H, int W, int B, float* __restrict__ cat) {
+    const int Cc = C3 + C1;
+    const size_t n = (size_t)B * H * W * Cc;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = i % Cc;
+    const size_t pix = i / Cc;
+    const int x = pix % W;
+    const int y = (pix / W) % H;
+    const int b = (int)(pix / ((size_t)W * H));
+    cat[i] = c < C3 ? a3[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C3 + c] : a1[pix * C1 + (c - C3)];
+}
+
+// da3[b, y2, x2, c] = sum of dcat over the 4 children (c < C3) + dg[b][c] / npix2
+__global__ void __launch_bounds__(kT) a3_grad_kernel(const float* __restrict__ dcat, int Cc, const float* __restrict__ dg,
+                                                     int H, int W, int C3, int B, float* __restrict__ da3) {
+    const int H2 = H / 2, W2 = W / 2;
+    const size_t n = (size_t)B * H2 * W2 * C3;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = i % C3;
+    size_t r = i / C3;
+    const int x = r % W2;
+    r /= W2;
+    const int y = r % H2;
+    const int b = (int)(r / H2);
+    const float* d = dcat + (((size_t)b * H + 2 * y) * W + 2 * x) * Cc + c;
+    const float s = (d[0] + d[Cc]) + (d[(size_t)W * Cc] + d[(size_t)W * Cc + Cc]);
+    da3[i] = s + dg[b * C3 + c] / (float)(H2 * W2);
+}
+
+__global__ void __launch_bounds__(kT) relu_grad_kernel(const float* __restrict__ A, float* __restrict__ dA, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(A[i] > 0.0f)) dA[i] = 0.0f;
+}
+
+// mu = z / max(1, |z|) per pixel (6 components); with a target: loss partials
+// |mu - mu*|^2 and dz = d(loss)/dz for loss = scale * sum |mu - mu*|^2.
+__global__ void __launch_bounds__(kT) mu_head_kernel(const float* __restrict__ z, const float* __restrict__ mt,
+                                                     size_t npix, float scale, float* __restrict__ mu,
+                                                     float* __restrict__ dz, float* __restrict__ part) {
+    __shared__ float red[4];
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float lsum = 0.0f;
+    if (i < npix) {
+        float v[6], n2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            v[c] = z[i * 6 + c];
+            n2 = fmaf(v[c], v[c], n2);
+        }
+        const float nz = sqrtf(n2);
+        const float inv = nz > 1.0f ? 1.0f / nz : 1.0f;
+        float m[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            m[c] = v[c] * inv;
+            if (mu) mu[i * 6 + c] = m[c];
+        }
+        if (mt) {
+            float dm[6], md = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const float e = m[c] - mt[i * 6 + c];
+                lsum = fmaf(e, e, lsum);
+                dm[c] = 2.0f * scale * e;
+                md = fmaf(m[c], dm[c], md);
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) dz[i * 6 + c] = nz > 1.0f ? (dm[c] - m[c] * md) * inv : dm[c];
+        }
+    }
+    if (!part) return;
+    lsum = bsum(lsum, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = lsum;
+}
+
+// g[b][c] = mean over the pixels of image b of A[., c]  (grid (B, C)).
+__global__ void __launch_bounds__(kT) gpool_kernel(const float* __restrict__ A, size_t npix, int C,
+                                                   float* __restrict__ g) {
+    __shared__ float red[4];
+    const int b = blockIdx.x, c = blockIdx.y;
+    const float* a = A + (size_t)b * npix * C + c;
+    float s = 0.0f;
+    for (size_t p = threadIdx.x; p < npix; p += kT) s += a[p * C];
+    s = bsum(s, red);
+    if (threadIdx.x == 0) g[b * C + c] = s / (float)npix;
+}
+
+// Control head of one image (one block per image, blockDim >= n_out):
+// e = sigmoid(bl + g Wl); with a target: loss partial, dWl / dbl per image, dg.
+__global__ void __launch_bounds__(kT) eps_head_kernel(const float* __restrict__ g, int C, const float* __restrict__ Wl,
+                                                      const float* __restrict__ bl, int n_out,
+                                                      const float* __restrict__ et, float scale, float* __restrict__ e_out,
+                                                      float* __restrict__ dWl_part, float* __restrict__ dbl_part,
+                                                      float* __restrict__ dg, float* __restrict__ part) {
+    __shared__ float gs[64];
+    __shared__ float dpre[kT];
+    __shared__ float red[4];
+    const int b = blockIdx.x, j = threadIdx.x;
+    if (j < C) gs[j] = g[b * C + j];
+    __syncthreads();
+    float lsum = 0.0f;
+    float d = 0.0f;
+    if (j < n_out) {
+        float pre = bl[j];
+        for (int c = 0; c < C; ++c) pre = fmaf(gs[c], Wl[c * n_out + j], pre);
+        const float e = 1.0f / (1.0f + expf(-pre));
+        if (e_out) e_out[b * n_out + j] = e;
+        if (et) {
+            const float r = e - et[b * n_out + j];
+            lsum = r * r;
+            d = 2.0f * scale * r * e * (1.0f - e);
+        }
+    }
+    dpre[j] = d;
+    __syncthreads();
+    if (!et) return;
+    if (j < n_out) {
+        dbl_part[b * n_out + j] = d;
+        for (int c = 0; c < C; ++c) dWl_part[((size_t)b * C + c) * n_out + j] = gs[c] * d;
+    }
+    if (j < C) {
+        float s = 0.0f;
+        for (int o = 0; o < n_out; ++o) s = fmaf(Wl[j * n_out + o], dpre[o], s);
+        dg[b * C + j] = s;
+    }
+    lsum = bsum(lsum, red);
+    if (threadIdx.x == 0) part[b] = lsum;
+}
+
+// Adam with bias correction; t >= 1.
+__global__ void __launch_bounds__(kT) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                  float* __restrict__ m, float* __restrict__ v, int n, float lr,
+                                                  float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Host driver.
+
+struct Layer {
+    int cin, cout;
+    size_t w, b;  // offsets of the FP32 weights [9 cin][cout] and bias [cout] in the parameter blob
+};
+
+struct NetShape {
+    Layer L[5];
+    size_t wl, bl;  // control head: Wl [64][2K], bl [2K]
+    size_t n;       // total parameters
+    int nout;       // 2K
+};
+
+NetShape net_shape(int K) {
+    NetShape s;
+    const int io[5][2] = {{3, 16}, {16, 32}, {32, 64}, {80, 32}, {32, 6}};
+    size_t off = 0;
+    for (int i = 0; i < 5; ++i) {
+        s.L[i].cin = io[i][0];
+        s.L[i].cout = io[i][1];
+        s.L[i].w = off;
+        off += (size_t)9 * io[i][0] * io[i][1];
+        s.L[i].b = off;
+        off += io[i][1];
+    }
+    s.nout = 2 * K;
+    s.wl = off;
+    off += (size_t)64 * s.nout;
+    s.bl = off;
+    off += s.nout;
+    s.n = off;
+    return s;
+}
+
+struct NetWs {
+    float *a1, *p1, *a2, *a3, *cat, *a4, *z, *g, *e;
+    float *d1, *dp1, *d2, *d3, *dcat, *d4, *dz, *dg, *dWl_part, *dbl_part, *wpart, *lpart, *lout;
+    __bf16 *wb, *wf;
+    size_t used;
+};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+NetWs carve_net(void* base, int B, int H, int W, const NetShape& s, bool train) {
+    NetWs w;
+    std::memset(&w, 0, sizeof(w));
+    char* p = (char*)base;
+    size_t u = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* r = p ? p + u : nullptr;
+        u += al(bytes);
+        return r;
+    };
+    const size_t P = (size_t)B * H * W, P2 = P / 4;
+    w.a1 = (float*)take(P * 16 * 4);
+    w.p1 = (float*)take(P2 * 16 * 4);
+    w.a2 = (float*)take(P2 * 32 * 4);
+    w.a3 = (float*)take(P2 * 64 * 4);
+    w.cat = (float*)take(P * 80 * 4);
+    w.a4 = (float*)take(P * 32 * 4);
+    w.z = (float*)take(P * 6 * 4);
+    w.g = (float*)take((size_t)B * 64 * 4);
+    w.e = (float*)take((size_t)B * s.nout * 4);
+    size_t nw = 0;
+    for (int i = 0; i < 5; ++i) nw += (size_t)9 * s.L[i].cin * s.L[i].cout;
+    w.wb = (__bf16*)take(nw * 2);
+    w.wf = (__bf16*)take(nw * 2);
+    w.lpart = (float*)take((P / kT + 2 + B) * 4);
+    w.lout = (float*)take(4 * 4);
+    if (train) {
+        w.d1 = (float*)take(P * 16 * 4);
+        w.dp1 = (float*)take(P2 * 16 * 4);
+        w.d2 = (float*)take(P2 * 32 * 4);
+        w.d3 = (float*)take(P2 * 64 * 4);
+        w.dcat = (float*)take(P * 80 * 4);
+        w.d4 = (float*)take(P * 32 * 4);
+        w.dz = (float*)take(P * 6 * 4);
+        w.dg = (float*)take((size_t)B * 64 * 4);
+        w.dWl_part = (float*)take((size_t)B * 64 * s.nout * 4);
+        w.dbl_part = (float*)take((size_t)B * s.nout * 4);
+        size_t maxw = 0;
+        for (int i = 0; i < 5; ++i) maxw = std::max(maxw, (size_t)9 * s.L[i].cin * s.L[i].cout);
+        const size_t chunks = (P + kChunk - 1) / kChunk;
+        w.wpart = (float*)take(chunks * maxw * 4);
+    }
+    w.used = u;
+    return w;
+}
+
+unsigned nb(size_t n) { return (unsigned)((n + kT - 1) / kT); }
+
+int check_net_args(int B, int H, int W, int K) {
+    if (B < 1 || H < 2 || W < 2 || (H % 2) || (W % 2)) return nfail(ABC_EINVAL, "B >= 1 and even H, W >= 2 required");
+    if (K < 1 || 2 * K > kT) return nfail(ABC_EINVAL, "K must be in [1, 128]");
+    if ((double)B * H * W > 2.0e9) return nfail(ABC_EINVAL, "batch too large");
+    return ABC_OK;
+}
+
+struct Net {
+    NetShape s;
+    NetWs w;
+    int B, H, W;
+    hipStream_t st;
+    const float* prm;
+
+    __bf16* wb(int i) const {
+        size_t off = 0;
+        for (int j = 0; j < i; ++j) off += (size_t)9 * s.L[j].cin * s.L[j].cout;
+        return w.wb + off;
+    }
+    __bf16* wf(int i) const {
+        size_t off = 0;
+        for (int j = 0; j < i; ++j) off += (size_t)9 * s.L[j].cin * s.L[j].cout;
+        return w.wf + off;
+    }
+
+    int conv(int i, const float* X, int h, int wd, float* Y, int ystride, int yoff, bool relu) {
+        const Layer& L = s.L[i];
+        dim3 grid((h * wd + 15) / 16, (L.cout + 15) / 16, B);
+        hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(64), 0, st, X, L.cin, wb(i), prm + L.b, Y, L.cout, ystride, yoff, h,
+                           wd, relu ? 1 : 0);
+        NET_HIP(hipGetLastError());
+        return ABC_OK;
+    }
+    // dX = conv^T(dY) for layer i (flipped, transposed weights, no bias)
+    int conv_t(int i, const float* dY, int h, int wd, float* dX) {
+        const Layer& L = s.L[i];
+        dim3 grid((h * wd + 15) / 16, (L.cin + 15) / 16, B);
+        hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(64), 0, st, dY, L.cout, wf(i), nullptr, dX, L.cin, L.cin, 0, h, wd,
+                           0);
+        NET_HIP(hipGetLastError());
+        return ABC_OK;
+    }
+    int wgrad(int i, const float* X, const float* dY, int h, int wd, float* grad) {
+        const Layer& L = s.L[i];
+        const size_t P = (size_t)B * h * wd;
+        const int chunks = (int)((P + kChunk - 1) / kChunk);
+        const int Kt = 9 * L.cin;
+        dim3 grid(chunks, (Kt + 15) / 16, (L.cout + 15) / 16);
+        hipLaunchKernelGGL(conv3x3_wgrad_kernel, grid, dim3(64), 0, st, X, L.cin, dY, L.cout, h, wd, B, w.wpart);
+        NET_HIP(hipGetLastError());
+        const int n = Kt * L.cout;
+        hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb(n)), dim3(kT), 0, st, w.wpart, chunks, n, grad + L.w);
+        NET_HIP(hipGetLastError());
+        hipLaunchKernelGGL(colsum_kernel, dim3(L.cout), dim3(kT), 0, st, dY, P, L.cout, grad + L.b);
+        NET_HIP(hipGetLastError());
+        return ABC_OK;
+    }
+
+    int prepare_weights() {
+        for (int i = 0; i < 5; ++i) {
+            const int n = 9 * s.L[i].cin * s.L[i].cout;
+            hipLaunchKernelGGL(weights_bf16_kernel, dim3(nb(n)), dim3(kT), 0, st, prm + s.L[i].w, s.L[i].cin, s.L[i].cout,
+                               wb(i), wf(i));
+            NET_HIP(hipGetLastError());
+        }
+        return ABC_OK;
+    }
+
+    int forward(const float* x) {
+        int rc;
+        const int h2 = H / 2, w2 = W / 2;
+        const size_t P = (size_t)B * H * W;
+        if ((rc = prepare_weights())) return rc;
+        if ((rc = conv(0, x, H, W, w.a1, 16, 0, true))) return rc;
+        hipLaunchKernelGGL(avgpool2_kernel, dim3(nb(P / 4 * 16)), dim3(kT), 0, st, w.a1, H, W, 16, B, w.p1);
+        NET_HIP(hipGetLastError());
+        if ((rc = conv(1, w.p1, h2, w2, w.a2, 32, 0, true))) return rc;
+        if ((rc = conv(2, w.a2, h2, w2, w.a3, 64, 0, true))) return rc;
+        hipLaunchKernelGGL(up_concat_kernel, dim3(nb(P * 80)), dim3(kT), 0, st, w.a3, 64, w.a1, 16, H, W, B, w.cat);
+        NET_HIP(hipGetLastError());
+        if ((rc = conv(3, w.cat, H, W, w.a4, 32, 0, true))) return rc;
+        if ((rc = conv(4, w.a4, H, W, w.z, 6, 0, false))) return rc;
+        hipLaunchKernelGGL(gpool_kernel, dim3(B, 64), dim3(kT), 0, st, w.a3, (size_t)h2 * w2, 64, w.g);
+        NET_HIP(hipGetLastError());
+        return ABC_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* abc_wsnet_last_error(void) { return g_net_error.c_str(); }
+
+int abc_wsnet_param_count(int K, size_t* n) {
+    if (!n || K < 1 || 2 * K > kT) return nfail(ABC_EINVAL, "K must be in [1, 128] and n non-NULL");
+    *n = net_shape(K).n;
+    return ABC_OK;
+}
+
+int abc_wsnet_workspace_bytes(int B, int H, int W, int K, int train, size_t* bytes) {
+    int rc = check_net_args(B, H, W, K);
+    if (rc) return rc;
+    if (!bytes) return nfail(ABC_EINVAL, "bytes is NULL");
+    *bytes = carve_net(nullptr, B, H, W, net_shape(K), train != 0).used;
+    return ABC_OK;
+}
+
+int abc_wsnet_forward(const float* params, const float* x, int B, int H, int W, int K, const abc_params* p, float* mu0,
+                      float* eps0, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_net_args(B, H, W, K);
+    if (rc) return rc;
+    if (!params || !x || !p || !mu0 || !eps0) return nfail(ABC_EINVAL, "params, x, p, mu0, eps0 must be non-NULL");
+    Net net;
+    net.s = net_shape(K);
+    if (!ws || ws_bytes < carve_net(nullptr, B, H, W, net.s, false).used)
+        return nfail(ABC_EINVAL, "wsnet workspace too small");
+    net.w = carve_net(ws, B, H, W, net.s, false);
+    net.B = B;
+    net.H = H;
+    net.W = W;
+    net.st = (hipStream_t)stream;
+    net.prm = params;
+    if ((rc = net.forward(x))) return rc;
+    const size_t P = (size_t)B * H * W;
+    hipLaunchKernelGGL(mu_head_kernel, dim3(nb(P)), dim3(kT), 0, net.st, net.w.z, nullptr, P, 0.0f, mu0, nullptr,
+                       nullptr);
+    NET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(eps_head_kernel, dim3(B), dim3(kT), 0, net.st, net.w.g, 64, params + net.s.wl, params + net.s.bl,
+                       net.s.nout, nullptr, 0.0f, net.w.e, nullptr, nullptr, nullptr, nullptr);
+    NET_HIP(hipGetLastError());
+    // eps0 = eps_min + (eps_max - eps_min) e, on the host side of the tiny array
+    std::vector<float> e((size_t)B * net.s.nout);
+    NET_HIP(hipMemcpyAsync(e.data(), net.w.e, e.size() * sizeof(float), hipMemcpyDeviceToHost, net.st));
+    NET_HIP(hipStreamSynchronize(net.st));
+    for (size_t i = 0; i < e.size(); ++i) {
+        const int m = (int)(i % 2);
+        e[i] = p->eps_min[m] + (p->eps_max[m] - p->eps_min[m]) * e[i];
+    }
+    NET_HIP(hipMemcpyAsync(eps0, e.data(), e.size() * sizeof(float), hipMemcpyHostToDevice, net.st));
+    NET_HIP(hipStreamSynchronize(net.st));
+    return ABC_OK;
+}
+
+int abc_wsnet_loss_grad(const float* params, const float* x, const float* mu_t, const float* eps_t, int B, int H,
+                        int W, int K, const abc_params* p, float w_eps, float* grad, double* loss, void* ws,
+                        size_t ws_bytes, void* stream) {
+    int rc = check_net_args(B, H, W, K);
+    if (rc) return rc;
+    if (!params || !x || !mu_t || !eps_t || !p || !grad) return nfail(ABC_EINVAL, "null argument");
+    Net net;
+    net.s = net_shape(K);
+    if (!ws || ws_bytes < carve_net(nullptr, B, H, W, net.s, true).used)
+        return nfail(ABC_EINVAL, "wsnet workspace too small");
+    net.w = carve_net(ws, B, H, W, net.s, true);
+    net.B = B;
+    net.H = H;
+    net.W = W;
+    hipStream_t st = (hipStream_t)stream;
+    net.st = st;
+    net.prm = params;
+    const NetWs& w = net.w;
+    const NetShape& s = net.s;
+    const int h2 = H / 2, w2 = W / 2;
+    const size_t P = (size_t)B * H * W, P2 = P / 4;
+    if ((rc = net.forward(x))) return rc;
+    // normalised control targets e* = (eps* - eps_min) / (eps_max - eps_min), staged through w.e's tail
+    std::vector<float> et((size_t)B * s.nout);
+    NET_HIP(hipMemcpyAsync(et.data(), eps_t, et.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    NET_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < et.size(); ++i) {
+        const int m = (int)(i % 2);
+        const float span = p->eps_max[m] - p->eps_min[m];
+        et[i] = span > 0.0f ? (et[i] - p->eps_min[m]) / span : 0.0f;
+    }
+    // heads with targets; the normalised control targets are staged in dcat, which stays
+    // free until the data gradient of layer 4 (stream order: the head reads them first)
+    const float mu_scale = 1.0f / (float)P;
+    const float e_scale = w_eps / (float)(B * s.nout);
+    float* lpart_mu = w.lpart;
+    float* lpart_e = w.lpart + nb(P) + 1;
+    NET_HIP(hipMemcpyAsync(w.dcat, et.data(), et.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(mu_head_kernel, dim3(nb(P)), dim3(kT), 0, st, w.z, mu_t, P, mu_scale, nullptr, w.dz, lpart_mu);
+    NET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(eps_head_kernel, dim3(B), dim3(kT), 0, st, w.g, 64, params + s.wl, params + s.bl, s.nout, w.dcat,
+                       e_scale, w.e, w.dWl_part, w.dbl_part, w.dg, lpart_e);
+    NET_HIP(hipGetLastError());
+    // control-head parameter gradients: sums over the batch (rows = B)
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb((size_t)64 * s.nout)), dim3(kT), 0, st, w.dWl_part, B, 64 * s.nout,
+                       grad + s.wl);
+    NET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb(s.nout)), dim3(kT), 0, st, w.dbl_part, B, s.nout, grad + s.bl);
+    NET_HIP(hipGetLastError());
+    // decoder
+    if ((rc = net.wgrad(4, w.a4, w.dz, H, W, grad))) return rc;
+    if ((rc = net.conv_t(4, w.dz, H, W, w.d4))) return rc;
+    hipLaunchKernelGGL(relu_grad_kernel, dim3(nb(P * 32)), dim3(kT), 0, st, w.a4, w.d4, P * 32);
+    NET_HIP(hipGetLastError());
+    if ((rc = net.wgrad(3, w.cat, w.d4, H, W, grad))) return rc;
+    if ((rc = net.conv_t(3, w.d4, H, W, w.dcat))) return rc;
+    hipLaunchKernelGGL(a3_grad_kernel, dim3(nb(P2 * 64)), dim3(kT), 0, st, w.dcat, 80, w.dg, H, W, 64, B, w.d3);
+    NET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(relu_grad_kernel, dim3(nb(P2 * 64)), dim3(kT), 0, st, w.a3, w.d3, P2 * 64);
+    NET_HIP(hipGetLastError());
+    // encoder
+    if ((rc = net.wgrad(2, w.a2, w.d3, h2, w2, grad))) return rc;
+    if ((rc = net.conv_t(2, w.d3, h2, w2, w.d2))) return rc;
+    hipLaunchKernelGGL(relu_grad_kernel, dim3(nb(P2 * 32)), dim3(kT), 0, st, w.a2, w.d2, P2 * 32);
+    NET_HIP(hipGetLastError());
+    if ((rc = net.wgrad(1, w.p1, w.d2, h2, w2, grad))) return rc;
+    if ((rc = net.conv_t(1, w.d2, h2, w2, w.dp1))) return rc;
+    hipLaunchKernelGGL(a1_grad_kernel, dim3(nb(P * 16)), dim3(kT), 0, st, w.dcat, w.dp1, H, W, 16, 80, 64, B, w.d1);
+    NET_HIP(hipGetLastError());
+    hipLaunchKernelGGL(relu_grad_kernel, dim3(nb(P * 16)), dim3(kT), 0, st, w.a1, w.d1, P * 16);
+    NET_HIP(hipGetLastError());
+    if ((rc = net.wgrad(0, x, w.d1, H, W, grad))) return rc;
+    if (loss) {
+        std::vector<float> lp(nb(P) + B);
+        NET_HIP(hipMemcpyAsync(lp.data(), lpart_mu, nb(P) * sizeof(float), hipMemcpyDeviceToHost, st));
+        NET_HIP(hipMemcpyAsync(lp.data() + nb(P), lpart_e, B * sizeof(float), hipMemcpyDeviceToHost, st));
+        NET_HIP(hipStreamSynchronize(st));
+        double lm = 0.0, le = 0.0;
+        for (unsigned i = 0; i < nb(P); ++i) lm += lp[i];
+        for (int i = 0; i < B; ++i) le += lp[nb(P) + i];
+        *loss = lm * (double)mu_scale + le * (double)e_scale;
+    }
+    return ABC_OK;
+}
+
+int abc_wsnet_adam(float* params, const float* grad, float* m, float* v, size_t n, int t, float lr, float b1, float b2,
+                   float eps, void* stream) {
+    if (!params || !grad || !m || !v || t < 1 || n == 0) return nfail(ABC_EINVAL, "bad Adam arguments");
+    const float c1 = 1.0f - std::pow(b1, (float)t), c2 = 1.0f - std::pow(b2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(nb(n)), dim3(kT), 0, (hipStream_t)stream, params, grad, m, v, (int)n, lr, b1,
+                       b2, eps, c1, c2);
+    NET_HIP(hipGetLastError());
+    return ABC_OK;
+}
+
+}  // extern "C"

@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["voronoi_image", "voronoi_labels", "batch_shapes"]
+__all__ = ["voronoi_image", "voronoi_labels", "batch_shapes", "wsnet_init"]
 
 
 def _nearest_site(H: int, W: int, sites: np.ndarray) -> np.ndarray:
@@ -105,3 +105,21 @@ def batch_shapes(n: int, seed: int, lo: int = 128, hi: int = 1024):
         sigma = float(rng.uniform(0.02, 0.1))
         out.append((H, W, regions, sigma, seed * 1000 + i))
     return out
+
+
+# Convolution shapes (input, output channels) of the warm-start network, in order.
+WSNET_CONVS = [(3, 16), (16, 32), (32, 64), (80, 32), (32, 6)]
+
+
+def wsnet_init(K: int, seed: int) -> np.ndarray:
+    """Seeded starting weights of the warm-start network, flat FP32: per 3 x 3
+    convolution He-normal weights (std sqrt(2 / (9 Cin))) then zero biases;
+    then the control head's 64 x 2K weights (std 1/8) and zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in WSNET_CONVS:
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / (9 * cin)), size=9 * cin * cout))
+        parts.append(np.zeros(cout))
+    parts.append(rng.normal(0.0, 0.125, size=64 * 2 * K))
+    parts.append(np.zeros(2 * K))
+    return np.concatenate(parts).astype(np.float32)

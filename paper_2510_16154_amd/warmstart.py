@@ -1,0 +1,122 @@
+"""Learned warm start for the solver (the network runs in the HIP library).
+
+The network maps an image to a starting multiplier field mu0 and starting
+controls eps0 for ``abc_solve``; it is trained on pairs (image, final mu and
+eps) produced by the plain method itself.  The plain cold-started solve stays
+the reference: a warm solve stops as soon as its TV energy reaches the cold
+solve's final energy within a relative tolerance, and falls back to the cold
+solve when it does not get there within the same iteration budget or produces
+a non-finite value.  Orchestration only; every arithmetic step is a library
+call.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import binding as B
+from .synth import voronoi_image, wsnet_init
+
+
+def make_dataset(n: int, size: int, seed0: int, params: B.Params, batch: int = 64, device="cuda"):
+    """n images of size x size (RGB Voronoi: 4-16 regions, sigma U[0.02, 0.1],
+    image i seeded seed0 + i), each solved by the plain method; returns device
+    tensors (x n x H x W x 3, mu n x H x W x 6, eps n x K x 2)."""
+    import torch
+    xs, mus, epss = [], [], []
+    for s0 in range(0, n, batch):
+        imgs, eps_l, mu_l = [], [], []
+        for i in range(s0, min(n, s0 + batch)):
+            r = np.random.default_rng(seed0 + i)
+            regions = int(r.integers(4, 17))
+            sigma = float(r.uniform(0.02, 0.1))
+            imgs.append(torch.as_tensor(voronoi_image(size, size, 3, regions, sigma, seed0 + i), device=device))
+            eps_l.append(torch.full((params.K, 2), params.eps_init, dtype=torch.float32, device=device))
+            mu_l.append(torch.zeros((size, size, 2, 3), dtype=torch.float32, device=device))
+        B.abc_solve_batched(imgs, params, eps=eps_l, mu=mu_l)
+        xs += imgs
+        mus += [m.reshape(size, size, 6) for m in mu_l]
+        epss += eps_l
+    return torch.stack(xs), torch.stack(mus), torch.stack(epss)
+
+
+@dataclass
+class TrainLog:
+    losses: list
+    seconds: float
+
+
+class WarmStart:
+    def __init__(self, K: int, box: B.Params, seed: int = 0, device="cuda"):
+        import torch
+        self.K, self.box = K, box
+        self.params = torch.as_tensor(wsnet_init(K, seed), device=device)
+        assert self.params.numel() == B.abc_wsnet_param_count(K)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+
+    def predict(self, x):
+        """(mu0 B x H x W x 2 x 3, eps0 B x K x 2) for images x (B x H x W x 3)."""
+        mu0, eps0 = B.abc_wsnet_forward(self.params, x.contiguous(), self.K, self.box)
+        return mu0.reshape(x.shape[0], x.shape[1], x.shape[2], 2, 3), eps0
+
+    def train(self, x, mu, eps, epochs: int, batch: int, lr: float, w_eps: float = 1.0, seed: int = 0,
+              lr_decay: float = 1.0) -> TrainLog:
+        import torch
+        n = x.shape[0]
+        rng = np.random.default_rng(seed)
+        grad = torch.empty_like(self.params)
+        losses = []
+        t0 = time.perf_counter()
+        for ep in range(epochs):
+            order = rng.permutation(n)
+            ep_loss = []
+            for s in range(0, n - batch + 1, batch):
+                idx = torch.as_tensor(order[s:s + batch], device=x.device)
+                loss, _ = B.abc_wsnet_loss_grad(self.params, x[idx].contiguous(), mu[idx].contiguous(),
+                                                eps[idx].contiguous(), self.K, self.box, w_eps, grad=grad)
+                self.t += 1
+                B.abc_wsnet_adam(self.params, grad, self.m, self.v, self.t, lr)
+                ep_loss.append(loss)
+            losses.append(float(np.mean(ep_loss)))
+            lr *= lr_decay
+        torch.cuda.synchronize()
+        return TrainLog(losses, time.perf_counter() - t0)
+
+    def solve(self, img, params: B.Params, target_K: float, cold=None):
+        """Warm solve of one image (H x W x 3) up to the energy target_K, with
+        the cold solve as fallback.  ``cold``: an earlier cold result
+        (dict from ``cold_solve``) to fall back to without recomputing."""
+        import torch
+        t0 = time.perf_counter()
+        mu0, eps0 = self.predict(img[None])
+        out = B.abc_solve(img, params.replace(stop_K=target_K), eps=eps0[0].contiguous(),
+                          mu=mu0[0].contiguous())
+        torch.cuda.synchronize()
+        t_warm = time.perf_counter() - t0
+        st = out["stats"]
+        ok = np.isfinite(st["K"]) and st["K"] <= target_K and bool(torch.isfinite(out["c"]).all())
+        res = {"reached": ok, "outer_iters": st["outer_iters"], "seconds": t_warm, "K": st["K"], "fallback": False}
+        if not ok:
+            c = cold if cold is not None else cold_solve(img, params)
+            res.update(fallback=True, seconds=t_warm + c["seconds"], K=c["K"],
+                       outer_iters=st["outer_iters"] + c["outer_iters"])
+        return res
+
+
+def cold_solve(img, params: B.Params, rel_tol: float = 1e-4):
+    """Plain solve from eps_init, mu = 0; also the outer iteration and time at
+    which it first came within rel_tol of its own final energy."""
+    import torch
+    t0 = time.perf_counter()
+    out = B.abc_solve(img, params)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    K = out["stats"]["K"]
+    log = out["outer_log"][:out["stats"]["outer_iters"]]
+    hit = int(np.argmax(log[:, 0] <= K * (1 + rel_tol)))
+    return {"K": K, "seconds": sec, "outer_iters": out["stats"]["outer_iters"], "iters_to_target": hit + 1,
+            "seconds_to_target": log[hit, 3] / 1e3, "target": K * (1 + rel_tol)}

@@ -1,0 +1,87 @@
+"""Warm-start network on the GPU: forward, loss and parameter gradient against
+the FP64 oracle (which rounds the same convolution operands to bfloat16), the
+Adam step against its formula, and a short training run that lowers the
+loss.  Tolerances: the GPU keeps activations in FP32 before rounding them to
+bfloat16 while the oracle rounds FP64 values, so an operand straddling a
+rounding boundary can differ by one bfloat16 step; the comparisons allow
+relative l2 errors of 1e-3."""
+import numpy as np
+import pytest
+
+import paper_2510_16154_amd as A
+from oracle import wsnet as O
+from paper_2510_16154_amd.synth import voronoi_image, wsnet_init
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BOX = ((2.0, 2.0), (1100.0, 1100.0))
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _batch(B, H, W, K, seed):
+    x = np.stack([voronoi_image(H, W, 3, 5, 0.05, seed + i) for i in range(B)])
+    rng = np.random.default_rng(seed)
+    mu_t = rng.normal(scale=0.4, size=(B, H, W, 6))
+    eps_t = rng.uniform(2, 1100, size=(B, K, 2))
+    params = wsnet_init(K, seed)
+    params = params + np.random.default_rng(seed + 1).normal(scale=0.02, size=params.size).astype(np.float32)
+    return x, mu_t, eps_t, params
+
+
+@pytest.mark.parametrize("B,H,W,K", [(2, 32, 48, 5), (1, 18, 22, 50)])
+def test_forward_and_gradient_match_oracle(B, H, W, K):
+    print(f"[case] wsnet B={B} H={H} W={W} K={K}", flush=True)
+    x, mu_t, eps_t, params = _batch(B, H, W, K, 11)
+    box = A.Params(K=K)
+    mu0, eps0 = A.binding.abc_wsnet_forward(T(params), T(x), K, box)
+    mu_o, eps_o, _ = O.forward(params.astype(np.float64), x, K, *BOX)
+    assert rel2(N(mu0), mu_o) < 1e-3
+    assert rel2(N(eps0), eps_o) < 1e-3
+    loss, g = A.binding.abc_wsnet_loss_grad(T(params), T(x), T(mu_t), T(eps_t), K, box, 0.5)
+    loss_o, g_o = O.loss_grad(params.astype(np.float64), x, mu_t, eps_t, K, *BOX, 0.5)
+    print(f"[wsnet] loss {loss:.6g} oracle {loss_o:.6g} grad rel2 {rel2(N(g), g_o):.2e}", flush=True)
+    assert abs(loss - loss_o) <= 1e-4 * abs(loss_o)
+    assert rel2(N(g), g_o) < 1e-3
+    offs, wl, bl, n = O.layout(K)
+    for a, b in offs:  # each layer's weight gradient on its own
+        assert rel2(N(g)[a:b], g_o[a:b]) < 2e-3
+
+
+def test_adam_step_matches_formula():
+    rng = np.random.default_rng(0)
+    p, g, m, v = (rng.normal(size=1000).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    pt, gt, mt, vt = T(p), T(g), T(m), T(v)
+    A.binding.abc_wsnet_adam(pt, gt, mt, vt, 3, 1e-3)
+    b1, b2, e = 0.9, 0.999, 1e-8
+    m2 = b1 * m + (1 - b1) * g
+    v2 = b2 * v + (1 - b2) * g * g
+    p2 = p - 1e-3 * (m2 / (1 - b1 ** 3)) / (np.sqrt(v2 / (1 - b2 ** 3)) + e)
+    assert np.allclose(N(pt), p2, rtol=1e-5, atol=1e-6)
+
+
+def test_training_lowers_the_loss():
+    from paper_2510_16154_amd.warmstart import WarmStart
+    K = 5
+    x, mu_t, eps_t, _ = _batch(8, 32, 32, K, 21)
+    mu_t = np.clip(mu_t, -0.3, 0.3)
+    ws = WarmStart(K, A.Params(K=K), seed=3)
+    log = ws.train(T(x), T(mu_t), T(eps_t), epochs=30, batch=4, lr=3e-3)
+    print(f"[train] losses {log.losses[0]:.4f} -> {log.losses[-1]:.4f}", flush=True)
+    assert log.losses[-1] < 0.8 * log.losses[0]
+    mu0, eps0 = ws.predict(T(x[:2]))
+    assert mu0.shape == (2, 32, 32, 2, 3) and eps0.shape == (2, K, 2)
+    assert bool(torch.all(torch.linalg.vector_norm(mu0.reshape(2, 32, 32, 6), dim=3) <= 1.0 + 1e-6))
