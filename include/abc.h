@@ -74,7 +74,11 @@ typedef struct abc_params {
     int32_t adj_tile_x;  /* adjoint tile width; 0 => tile_x (or library default)     */
     int32_t adj_tile_y;  /* adjoint tile height; 0 => tile_y (or library default)    */
     int32_t flags;       /* ABC_FLAG_* bits                                          */
-    double stop_K;       /* > 0: also stop after a multiplier iteration once K <= stop_K */
+    double stop_K;       /* > 0: also stop once K <= stop_K (checked after the starting
+                            forward sweep and after every accepted DAL step)        */
+    double tol_gap;      /* > 0: stop once |L_j - L_{j-1}| / |L_{j-1}| < tol_gap, the
+                            change of the Lagrangian between multiplier iterations
+                            (the ADMM stop of Sec. 4.1)                             */
 } abc_params;
 
 #define ABC_FLAG_NO_GRAPHS 1 /* launch every sweep step directly instead of replaying captured HIP graphs */
@@ -97,6 +101,8 @@ typedef struct abc_stats {
     double gap_rel;      /* |L_j - L_{j-1}| / |L_{j-1}| (NaN after one iteration)    */
     double phi_first;    /* inner objective at the first DAL iteration              */
     double phi_last;     /* inner objective at the last DAL iteration               */
+    double K_start;      /* TV energy after the starting forward sweep (NaN unless stop_K > 0) */
+    double ms_start;     /* milliseconds from the call to the end of that sweep     */
 } abc_stats;
 
 /* Workspace kinds for abc_workspace_bytes(). */
@@ -187,7 +193,8 @@ int abc_pd_step(const float* cK, const float* c0, int H, int W, int C, const abc
  *                  gradient is still computed and logged.
  *   grad_out:      [slots][K][2] control gradient G (FP64) of each DAL
  *                  iteration (dPhi/deps^k divided by dt).
- *   phi_out:       [slots][3] objective before the step, after it, trials.
+ *   phi_out:       [slots][5] objective before the step, after it, trials,
+ *                  TV energy K after the step, milliseconds since the call.
  *   outer_out:     [max_outer][4] after each multiplier iteration: K, L,
  *                  r_rel and the elapsed milliseconds since the call began. */
 typedef struct abc_solve_log {
@@ -256,6 +263,7 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
  * sweep, the next Armijo trial of every image that needs one, or the
  * multiplier update), so that small images share the GPU instead of running
  * one after another.  An image leaves the rounds when its own loops end.
+ * p->stop_K is checked after every multiplier iteration here.
  *   imgs: host array of n descriptors.  C: channels (shared).
  *   st: host array of n stats (may be NULL).
  *   finish_ms: host array of n completion times in ms after the call began

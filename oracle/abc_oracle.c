@@ -79,6 +79,7 @@ typedef struct {
     int literal_kernel;/* 1: use the printed (4r-1)(1-r)^4 (debug only)   */
     int cost;          /* 0: TV cost, method of multipliers (Alg. 2);
                           1: quadratic cost J (Def. 3.2), DAL alone (Alg. 1) */
+    double tol_gap;    /* stop when |L_j - L_{j-1}| / |L_{j-1}| < tol_gap (0: off) */
 } or_params;
 
 /* Results of one primal/dual update or energy evaluation. */
@@ -665,6 +666,8 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
         S.gap_rel = isnan(L_prev) ? NAN : fabs(E.L - L_prev) / fabs(L_prev);
         L_prev = E.L;
         if (P->tol_alm > 0.0 && E.r_rel < P->tol_alm) break;
+        /* stop once the Lagrangian's change between multiplier iterations is small (Sec. 4.1) */
+        if (P->tol_gap > 0.0 && !isnan(S.gap_rel) && S.gap_rel < P->tol_gap) break;
     }
     if (S.outer_iters == 0) or_energies_eval(base + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, &E);
     memcpy(cK, base + (size_t)K * n, n * sizeof(double));

@@ -30,7 +30,7 @@ class _Params(ct.Structure):
         ("max_outer", ct.c_int), ("max_inner", ct.c_int), ("max_ls", ct.c_int),
         ("tol_alm", ct.c_double), ("tol_dal", ct.c_double),
         ("sigma0", ct.c_double), ("armijo_b", ct.c_double), ("armijo_c", ct.c_double),
-        ("literal_kernel", ct.c_int), ("cost", ct.c_int),
+        ("literal_kernel", ct.c_int), ("cost", ct.c_int), ("tol_gap", ct.c_double),
     ]
 
 
@@ -69,6 +69,7 @@ class Params:
     armijo_c: float = 1e-4           # Sec. 3.2
     literal_kernel: int = 0
     cost: int = 0                    # 0: TV / method of multipliers, 1: quadratic J / DAL alone
+    tol_gap: float = 0.0             # stop when the relative change of L is below this
     extra: dict = field(default_factory=dict)
 
     def norm(self, H: int, W: int) -> float:
@@ -88,6 +89,7 @@ class Params:
         p.sigma0, p.armijo_b, p.armijo_c = self.sigma0, self.armijo_b, self.armijo_c
         p.literal_kernel = self.literal_kernel
         p.cost = self.cost
+        p.tol_gap = self.tol_gap
         return p
 
 

@@ -33,6 +33,7 @@ class AbcParams(ct.Structure):
         ("sigma0", ct.c_double), ("armijo_b", ct.c_double), ("armijo_c", ct.c_double),
         ("ckpt_every", ct.c_int32), ("tile_x", ct.c_int32), ("tile_y", ct.c_int32), ("cost", ct.c_int32),
         ("adj_tile_x", ct.c_int32), ("adj_tile_y", ct.c_int32), ("flags", ct.c_int32), ("stop_K", ct.c_double),
+        ("tol_gap", ct.c_double),
     ]
 
 
@@ -50,7 +51,8 @@ class AbcImage(ct.Structure):
 class AbcStats(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("outer_iters", ct.c_int32), ("inner_iters", ct.c_int32),
                 ("ls_evals", ct.c_int32)] + [(n, ct.c_double) for n in (
-                    "K", "TV", "fid", "L", "Ltilde", "r_rel", "r_abs", "gap_rel", "phi_first", "phi_last")]
+                    "K", "TV", "fid", "L", "Ltilde", "r_rel", "r_abs", "gap_rel", "phi_first", "phi_last",
+                    "K_start", "ms_start")]
 
 
 @dataclass
@@ -82,6 +84,7 @@ class Params:
     adj_tile_y: int = 0
     flags: int = 0  # ABC_FLAG_NO_GRAPHS (1): direct launches instead of captured sweeps
     stop_K: float = 0.0  # > 0: stop once the TV energy K reaches this value
+    tol_gap: float = 0.0  # > 0: stop once L changes by less than this (relative) between iterations
 
     def to_c(self) -> AbcParams:
         p = AbcParams()
@@ -288,7 +291,8 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     """Full solve (see abc_solve in abc.h).  Returns a dict with the field ``c``,
     ``eps`` and ``mu`` (the tensors passed in, updated, when given), ``v``,
     ``stats``, and the logs (numpy): ``decisions`` (max_outer x max_inner),
-    ``grad_log`` (M x P x K x 2), ``phi_log`` (M x P x 3) and ``outer_log``
+    ``grad_log`` (M x P x K x 2), ``phi_log`` (M x P x 5: objective before and
+    after the step, trials, K after the step, ms) and ``outer_log``
     (M x 4: K, L, r_rel, elapsed ms after each multiplier iteration).  ``decisions``
     and ``eps_replay`` (M x P x K x 2) replay a recorded control argmin."""
     import numpy as np
@@ -305,7 +309,7 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     dp = ct.POINTER(ct.c_double)
     dec_out = np.zeros((M, P), dtype=np.float64)
     grad_log = np.zeros((M, P, K, 2), dtype=np.float64)
-    phi_log = np.zeros((M, P, 3), dtype=np.float64)
+    phi_log = np.zeros((M, P, 5), dtype=np.float64)
     outer_log = np.zeros((M, 4), dtype=np.float64)
     log = AbcSolveLog()
     keep = []

@@ -94,6 +94,13 @@ struct GraphCache {
     }
 };
 
+// Columns of abc_solve_log.phi_out per DAL iteration.
+constexpr int kStepLog = 5;
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 struct Shape {
     int H, W, C;
     size_t npix() const { return (size_t)H * W; }
@@ -135,6 +142,7 @@ int check_params(const abc_params* p) {
     if (p->cost != ABC_COST_TV && p->cost != ABC_COST_QUADRATIC) return fail(ABC_EINVAL, "unknown cost");
     if (p->flags & ~ABC_FLAG_NO_GRAPHS) return fail(ABC_EINVAL, "unknown flag bits");
     if (!(p->stop_K >= 0.0)) return fail(ABC_EINVAL, "stop_K must be >= 0");
+    if (!(p->tol_gap >= 0.0)) return fail(ABC_EINVAL, "tol_gap must be >= 0");
     return ABC_OK;
 }
 
@@ -276,15 +284,22 @@ int adjoint_steps(const float* const* states, int k0, int k1, const float* eps, 
     return ABC_OK;
 }
 
+// Terminal condition (pK may be NULL) and, when phi is set, the objective L~ and
+// the TV energy K = TV + fidelity of cK (Kout, TVout, fidout may be NULL).
 int objective(const float* cK, const float* c0, const float* v, const float* mu, float* pK, const Shape& s,
-              const abc_params* p, const PdWs& w, hipStream_t st, double* phi) {
+              const abc_params* p, const PdWs& w, hipStream_t st, double* phi, double* Kout = nullptr,
+              double* TVout = nullptr, double* fidout = nullptr) {
     ABC_HIP(abc::launch_terminal(cK, c0, v, mu, s.H, s.W, s.C, p->rho, p->alpha, (float)s.area(), pK, w.part, st));
     if (!phi) return ABC_OK;
-    ABC_HIP(abc::launch_reduce_rows(w.part, 1, abc::pd_blocks(s.H, s.W), 1, w.out, 1.0f, st));
-    float h = 0.0f;
-    ABC_HIP(hipMemcpyAsync(&h, w.out, sizeof(float), hipMemcpyDeviceToHost, st));
+    ABC_HIP(abc::launch_reduce_rows(w.part, 1, abc::pd_blocks(s.H, s.W), abc::kTermQuantities, w.out, 1.0f, st));
+    float h[abc::kTermQuantities];
+    ABC_HIP(hipMemcpyAsync(h, w.out, sizeof(h), hipMemcpyDeviceToHost, st));
     ABC_HIP(hipStreamSynchronize(st));
-    *phi = s.area() * (double)h;
+    *phi = s.area() * (double)h[0];
+    const double tv = s.area() * (double)h[1], fid = s.area() * 0.5 * (double)p->alpha * (double)h[2];
+    if (Kout) *Kout = tv + fid;
+    if (TVout) *TVout = tv;
+    if (fidout) *fidout = fid;
     return ABC_OK;
 }
 
@@ -591,12 +606,14 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
         });
     };
     // Armijo trial into buffer `trial`: eps(tau), forward sweep, Phi(tau), test.
+    double K_try = 0.0;  // TV energy of the last trial's final field
     auto run_trial = [&](const std::vector<double>& G, double tau, double phi0, double* phit, bool* ok) -> int {
         project(G, tau, e_try);
         int r2 = upload(e_try, w.eps[trial]);
         if (r2) return r2;
         if ((r2 = sweep(trial))) return r2;
-        if ((r2 = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, phit))) return r2;
+        if ((r2 = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, phit, &K_try)))
+            return r2;
         double ip = 0.0;
         for (int i = 0; i < 2 * K; ++i) ip += G[i] * (e_try[i] - e_base[i]);
         ip *= (double)p->dt;
@@ -611,13 +628,20 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     const size_t nslots = (size_t)M * P;
     if (decisions_out) std::fill(decisions_out, decisions_out + nslots, 0.0);
     if (grad_out) std::fill(grad_out, grad_out + nslots * 2 * K, 0.0);
-    if (phi_out) std::fill(phi_out, phi_out + nslots * 3, 0.0);
+    if (phi_out) std::fill(phi_out, phi_out + nslots * kStepLog, 0.0);
     if (outer_out) std::fill(outer_out, outer_out + (size_t)M * 4, 0.0);
 
     // Alg. 2: forward integration, v^(0) = argmin_v L(c^(0), v, mu^(0)).
     if ((rc = upload(e_base, w.eps[base]))) return rc;
     if ((rc = sweep(base))) return rc;
-    if (!quad && (rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 0, s, p, w.pd, st, nullptr))) return rc;
+    abc_stats E0;
+    std::memset(&E0, 0, sizeof(E0));
+    const bool check0 = !quad && p->stop_K > 0.0;
+    if (!quad && (rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 0, s, p, w.pd, st, check0 ? &E0 : nullptr)))
+        return rc;
+    // energy target already met by the starting controls (e.g. a warm start): no iteration needed
+    const bool done0 = check0 && E0.K <= p->stop_K;
+    const double ms_start = ms_since(t_start);
 
     double sigma = p->sigma0;
     double L_prev = NAN;
@@ -625,7 +649,10 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     abc_stats E;
     std::memset(&E, 0, sizeof(E));
     std::vector<double> G;
-    const int n_outer = quad ? std::min(M, 1) : M;
+    double K_acc = 0.0;  // TV energy after the last accepted step
+    bool hit_K = false;
+    const int n_outer = quad ? std::min(M, 1) : (done0 ? 0 : M);
+    if (done0) E = E0;
     for (int j = 0; j < n_outer; ++j) {
         for (int it = 0; it < P; ++it) {
             const size_t slot = (size_t)j * P + it;
@@ -661,7 +688,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
             }
             S.inner_iters++;
             if (grad_out) std::copy(G.begin(), G.end(), grad_out + slot * 2 * K);
-            if (phi_out) phi_out[3 * slot] = phi0;
+            if (phi_out) phi_out[kStepLog * slot] = phi0;
             bool all_zero = true;
             for (double g : G) all_zero = all_zero && (g == 0.0);
             if (decisions_in && !(decisions_in[slot] > 0.0)) break;
@@ -675,15 +702,17 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                     e_try.assign(eps_replay + slot * 2 * K, eps_replay + (slot + 1) * 2 * K);
                     if ((rc = upload(e_try, w.eps[trial]))) return rc;
                     if ((rc = sweep(trial))) return rc;
-                    if ((rc = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, &phi_acc)))
+                    if ((rc = objective(w.traj[trial] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, &phi_acc,
+                                        &K_try)))
                         return rc;
                 } else if ((rc = run_trial(G, accepted, phi0, &phi_acc, &ok))) {
                     return rc;
                 }
                 std::swap(cand, trial);
                 e_cand = e_try;
+                K_acc = K_try;
                 S.ls_evals++;
-                if (phi_out) phi_out[3 * slot + 2] = 1;
+                if (phi_out) phi_out[kStepLog * slot + 2] = 1;
             } else {
                 double tau = sigma, phit = 0.0;
                 bool ok = false, have = false;
@@ -696,6 +725,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                     e_cand = e_try;
                     accepted = tau;
                     phi_acc = phit;
+                    K_acc = K_try;
                     have = true;
                     while (evals < p->max_ls) {
                         project(G, tau / p->armijo_b, e_next);
@@ -708,6 +738,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                         e_cand = e_try;
                         accepted = tau;
                         phi_acc = phit;
+                        K_acc = K_try;
                     }
                 } else {
                     // backtracking branch
@@ -720,21 +751,34 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                             e_cand = e_try;
                             accepted = tau;
                             phi_acc = phit;
+                            K_acc = K_try;
                             have = true;
                             break;
                         }
                     }
                 }
                 S.ls_evals += evals;
-                if (phi_out) phi_out[3 * slot + 2] = evals;
+                if (phi_out) phi_out[kStepLog * slot + 2] = evals;
                 if (!have) break;
                 sigma = accepted;
             }
             e_base = e_cand;
             std::swap(base, cand);
             if (decisions_out) decisions_out[slot] = accepted;
-            if (phi_out) phi_out[3 * slot + 1] = phi_acc;
+            if (phi_out) {
+                phi_out[kStepLog * slot + 1] = phi_acc;
+                phi_out[kStepLog * slot + 3] = K_acc;
+                phi_out[kStepLog * slot + 4] = ms_since(t_start);
+            }
+            if (!quad && p->stop_K > 0.0 && K_acc <= p->stop_K) {
+                hit_K = true;  // energy target met by this step: no further iteration
+                break;
+            }
             if (p->tol_dal > 0.0 && std::fabs(phi_acc - phi0) < p->tol_dal * std::fabs(phi0)) break;
+        }
+        if (hit_K) {
+            S.outer_iters = j + 1;
+            break;
         }
         if (quad) {
             S.outer_iters = 1;
@@ -749,11 +793,12 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
             outer_out[4 * j + 0] = E.K;
             outer_out[4 * j + 1] = E.L;
             outer_out[4 * j + 2] = E.r_rel;
-            outer_out[4 * j + 3] =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            outer_out[4 * j + 3] = ms_since(t_start);
         }
         if (p->tol_alm > 0.0 && E.r_rel < p->tol_alm) break;
         if (p->stop_K > 0.0 && E.K <= p->stop_K) break;
+        // the change of the Lagrangian between multiplier iterations is small (Sec. 4.1)
+        if (p->tol_gap > 0.0 && !std::isnan(S.gap_rel) && S.gap_rel < p->tol_gap) break;
     }
     if (quad) {
         // TV and fidelity of the final field from the pd kernel on scratch copies (v, mu stay 0);
@@ -768,7 +813,10 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
         if ((rc = objective(w.traj[base] + traj_stride, c0, vv, mm, nullptr, s, &pq, w.pd, st, &J))) return rc;
         E.L = E.Ltilde = J;
         E.r_rel = E.r_abs = 0.0;
-    } else if (S.outer_iters == 0) {
+    } else if (hit_K) {
+        // energies of the final field with its v-argmin (computed on a spare buffer; mu unchanged)
+        if ((rc = pd_update(w.traj[base] + traj_stride, c0, w.traj[trial], mm, 0, s, p, w.pd, st, &E))) return rc;
+    } else if (S.outer_iters == 0 && !done0) {
         // no multiplier step taken: energies at the initial state (v is unchanged by this call)
         if ((rc = pd_update(w.traj[base] + traj_stride, c0, vv, mm, 0, s, p, w.pd, st, &E))) return rc;
     }
@@ -787,6 +835,8 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     S.r_rel = E.r_rel;
     S.r_abs = E.r_abs;
     S.status = (!quad && p->tol_alm > 0.0 && !(E.r_rel < p->tol_alm)) ? ABC_ENOCONV : ABC_OK;
+    S.K_start = check0 ? E0.K : NAN;
+    S.ms_start = ms_start;
     if (stats) *stats = S;
     return S.status;
 }
@@ -957,7 +1007,7 @@ struct Batch {
         ABC_HIP(hipMemcpyAsync(w.pix_jobs, jobs.data(), jobs.size() * sizeof(abc::PixJob), hipMemcpyHostToDevice, st));
         ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice, st));
         ABC_HIP(abc::launch_terminal_batched(w.pix_jobs, (int)jobs.size(), total, C, pq.rho, pq.alpha, st));
-        ABC_HIP(abc::launch_reduce_jobs(w.red_jobs, (int)reds.size(), 1, st));
+        ABC_HIP(abc::launch_reduce_jobs(w.red_jobs, (int)reds.size(), abc::kTermQuantities, st));
         std::vector<float> q(who.size() * abc::kPdQuantities);
         ABC_HIP(hipMemcpyAsync(q.data(), w.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, st));
         ABC_HIP(hipStreamSynchronize(st));
@@ -1164,6 +1214,8 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
         std::memset(&m.S, 0, sizeof(m.S));
         std::memset(&m.E, 0, sizeof(m.E));
         m.S.gap_rel = NAN;
+        m.S.K_start = NAN;
+        m.S.ms_start = NAN;
         if (m.eps_user) {
             std::vector<float> h((size_t)K * 2);
             ABC_HIP(hipMemcpyAsync(h.data(), m.eps_user, h.size() * sizeof(float), hipMemcpyDeviceToHost, B.st));
@@ -1327,7 +1379,9 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
             m.S.outer_iters = j + 1;
             m.S.gap_rel = std::isnan(m.L_prev) ? NAN : std::fabs(m.E.L - m.L_prev) / std::fabs(m.L_prev);
             m.L_prev = m.E.L;
-            if ((p->tol_alm > 0.0 && m.E.r_rel < p->tol_alm) || (p->stop_K > 0.0 && m.E.K <= p->stop_K) || j + 1 == M) {
+            const bool gap_ok = p->tol_gap > 0.0 && !std::isnan(m.S.gap_rel) && m.S.gap_rel < p->tol_gap;
+            if ((p->tol_alm > 0.0 && m.E.r_rel < p->tol_alm) || (p->stop_K > 0.0 && m.E.K <= p->stop_K) || gap_ok ||
+                j + 1 == M) {
                 m.outer_done = true;
                 m.finish_ms = t_now;
             }

@@ -90,7 +90,9 @@ hipError_t launch_reduce_rows(const float* part, int nrows, int nblk, int nq, fl
 // Workgroups used by the per-pixel primal/dual kernels.
 int pd_blocks(int H, int W);
 
-// Terminal condition and objective partials (one float per workgroup in part).
+// Terminal condition and objective partials: kTermQuantities floats per workgroup in
+// part (objective, |grad c|, |c - c0|^2).
+constexpr int kTermQuantities = 3;
 hipError_t launch_terminal(const float* c, const float* c0, const float* v, const float* mu, int H,
                            int W, int C, float rho, float alpha, float area, float* pK, float* part,
                            hipStream_t s);

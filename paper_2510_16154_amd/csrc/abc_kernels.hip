@@ -474,18 +474,19 @@ __device__ __forceinline__ float grad_y(const float* __restrict__ c, size_t i, i
 }
 
 // gK = area [ div(mu + rho (v - grad c)) + alpha (c - c0) ], div = -grad#^T, and the
-// per-pixel objective rho/2 |v - g + mu/rho|^2 + |v| + alpha/2 |c - c0|^2.
+// workgroup sums of the per-pixel objective rho/2 |v - g + mu/rho|^2 + |v| + alpha/2 |c - c0|^2,
+// of |grad c| and of |c - c0|^2 (kTermQuantities values per workgroup).
 __device__ __forceinline__ void terminal_block(const float* __restrict__ c, const float* __restrict__ c0,
                                                const float* __restrict__ v, const float* __restrict__ mu, int H, int W,
                                                int C, float rho, float alpha, float area, float inv2dx, float inv2dy,
                                                float* __restrict__ pK, float* __restrict__ part, int blk, float* red) {
     const size_t N = (size_t)H * W;
     const size_t i = (size_t)blk * blockDim.x + threadIdx.x;
-    float obj = 0.0f;
+    float obj = 0.0f, tv = 0.0f, fid = 0.0f;
     if (i < N) {
         const int r = (int)(i / W), q = (int)(i % W);
         const float inv_rho = 1.0f / rho;
-        float sh2 = 0.0f, nv2 = 0.0f, nf2 = 0.0f;
+        float sh2 = 0.0f, nv2 = 0.0f, nf2 = 0.0f, ng2 = 0.0f;
         for (int ch = 0; ch < C; ++ch) {
             const float cc = c[i * C + ch];
             const float gx = grad_x(c, i, q, W, C, ch, inv2dx);
@@ -498,6 +499,7 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
             const float shy = fmaf(my, inv_rho, vy - gy);
             sh2 = fmaf(shx, shx, fmaf(shy, shy, sh2));
             nv2 = fmaf(vx, vx, fmaf(vy, vy, nv2));
+            ng2 = fmaf(gx, gx, fmaf(gy, gy, ng2));
             const float e = cc - c0[i * C + ch];
             nf2 = fmaf(e, e, nf2);
             if (pK) {
@@ -534,9 +536,17 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
             }
         }
         obj = fmaf(0.5f * rho, sh2, sqrtf(nv2)) + 0.5f * alpha * nf2;
+        tv = sqrtf(ng2);
+        fid = nf2;
     }
     obj = block_sum(obj, red);
-    if (threadIdx.x == 0) part[blk] = obj;
+    tv = block_sum(tv, red);
+    fid = block_sum(fid, red);
+    if (threadIdx.x == 0) {
+        part[(size_t)blk * kTermQuantities + 0] = obj;
+        part[(size_t)blk * kTermQuantities + 1] = tv;
+        part[(size_t)blk * kTermQuantities + 2] = fid;
+    }
 }
 
 __global__ void __launch_bounds__(kMaxThreads)

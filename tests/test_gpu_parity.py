@@ -44,7 +44,7 @@ def both_params(orc, H, W, **kw):
     gp = A.Params(**kw)
     op = orc.Params(K=gp.K, R=gp.R, s=gp.inv_norm, alpha=gp.alpha, rho=gp.rho, gamma=gp.gamma,
                     max_outer=gp.max_outer, max_inner=gp.max_inner, max_ls=gp.max_ls, tol_alm=gp.tol_alm,
-                    tol_dal=gp.tol_dal)
+                    tol_dal=gp.tol_dal, tol_gap=gp.tol_gap)
     return gp, op
 
 
@@ -298,3 +298,16 @@ def test_unwindowed_paper_sum_matches_oracle(orc, C):
     g0, geps = A.abc_adjoint_dynamics(traj, T(eps), gp, T(gK))
     p0, ge = orc.adjoint_sweep(want, op, gK, eps)
     assert relinf(N(g0), p0) < FIELD_TOL and rel2(N(geps), ge) < FIELD_TOL
+
+
+
+def test_gap_stop_matches_oracle(orc):
+    """The Lagrangian-gap stop (Sec. 4.1) ends the GPU solve at the same multiplier
+    iteration as the oracle's when the controls are replayed."""
+    c0 = voronoi_image(32, 32, 3, 4, 0.05, 1001)
+    gp, op = both_params(orc, 32, 32, K=20, R=2, alpha=3000.0, max_outer=8, max_inner=4, tol_gap=0.25)
+    ref = orc.solve(c0, op)
+    assert 1 < ref["stats"]["outer_iters"] < 8
+    out = A.abc_solve(T(c0), gp, decisions=ref["decisions"], eps_replay=ref["eps_log"])
+    assert out["stats"]["outer_iters"] == ref["stats"]["outer_iters"]
+    assert relinf(N(out["c"]), ref["c"]) < FIELD_TOL

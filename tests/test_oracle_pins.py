@@ -466,3 +466,22 @@ def test_quadratic_dal_equals_dense_bruteforce(orc):
     taken = res["decisions"][0] > 0
     assert np.all(tr[taken, 1] <= tr[taken, 0])
     assert res["stats"]["Ltilde"] == pytest.approx(tr[taken, 1][-1] if taken.any() else tr[0, 0], rel=1e-12)
+
+
+
+def test_lagrangian_gap_stop(orc):
+    """The multiplier loop stops at the first iteration whose relative change of
+    L falls below tol_gap (the ADMM stop of Sec. 4.1), and not before."""
+    c0 = voronoi_image(16, 16, 3, 4, 0.05, 201).astype(np.float64)
+    base = dict(K=6, R=2, alpha=20.0, max_outer=8, max_inner=3)
+    full = orc.solve(c0, _P(orc, **base))
+    # L after each iteration from a run that is cut after j iterations
+    Ls = [orc.solve(c0, _P(orc, **dict(base, max_outer=j)))["stats"]["L"] for j in range(1, 9)]
+    gaps = [abs(Ls[j] - Ls[j - 1]) / abs(Ls[j - 1]) for j in range(1, 8)]
+    tol = sorted(gaps)[len(gaps) // 2]
+    stop = 1 + next(j for j, g in enumerate(gaps, start=1) if g < tol)
+    res = orc.solve(c0, _P(orc, **dict(base, tol_gap=tol)))
+    assert res["stats"]["outer_iters"] == stop
+    assert res["stats"]["gap_rel"] < tol
+    assert np.array_equal(res["c"], orc.solve(c0, _P(orc, **dict(base, max_outer=stop)))["c"])
+    assert full["stats"]["outer_iters"] == 8
