@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the SHA-256 of
 # the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "89ab6d3e02e978e4bdf0b2c3b909925d8a71ea605a716737be164d6e4df140a2",
+    "kernel_sha256": "ec4de64fd4d3f0f99d13d2d80b6c9014f5b1307fbb0cbe11a6c94ce51acda0fc",
     "bytes_per_launch": 11.02e6,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")

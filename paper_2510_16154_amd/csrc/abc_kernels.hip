@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "abc_internal.h"
 
@@ -461,7 +462,11 @@ reduce_jobs_kernel(const RedJob* __restrict__ jobs, int nq) {
 
 // ----------------------------------------------------------------------------
 // Per-pixel primal/dual kernels.  grad# is the central difference of Def. 3.1,
-// zero on the first/last column (row) by the reflective rule.
+// zero on the first/last column (row) by the reflective rule.  One workgroup
+// covers 256 consecutive pixels (a contiguous range of every HWC field); the
+// ranges are handed to the XCDs in contiguous runs, so the rows above and
+// below a range are mostly in the same L2.  CP is the padded channel count:
+// the channel loops unroll and every load of a pixel is in flight at once.
 
 __device__ __forceinline__ float grad_x(const float* __restrict__ c, size_t i, int q, int W, int C, int ch,
                                         float inv2dx) {
@@ -476,6 +481,7 @@ __device__ __forceinline__ float grad_y(const float* __restrict__ c, size_t i, i
 // gK = area [ div(mu + rho (v - grad c)) + alpha (c - c0) ], div = -grad#^T, and the
 // workgroup sums of the per-pixel objective rho/2 |v - g + mu/rho|^2 + |v| + alpha/2 |c - c0|^2,
 // of |grad c| and of |c - c0|^2 (kTermQuantities values per workgroup).
+template <int CP>
 __device__ __forceinline__ void terminal_block(const float* __restrict__ c, const float* __restrict__ c0,
                                                const float* __restrict__ v, const float* __restrict__ mu, int H, int W,
                                                int C, float rho, float alpha, float area, float inv2dx, float inv2dy,
@@ -486,8 +492,11 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
     if (i < N) {
         const int r = (int)(i / W), q = (int)(i % W);
         const float inv_rho = 1.0f / rho;
+        const bool xl = q - 1 >= 1, xr = q + 1 <= W - 2, yu = r - 1 >= 1, yd = r + 1 <= H - 2;
         float sh2 = 0.0f, nv2 = 0.0f, nf2 = 0.0f, ng2 = 0.0f;
-        for (int ch = 0; ch < C; ++ch) {
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch) {
+            if (ch >= C) break;
             const float cc = c[i * C + ch];
             const float gx = grad_x(c, i, q, W, C, ch, inv2dx);
             const float gy = grad_y(c, i, r, H, W, C, ch, inv2dy);
@@ -504,28 +513,28 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
             nf2 = fmaf(e, e, nf2);
             if (pK) {
                 float dv = 0.0f;
-                if (q + 1 <= W - 2) {
+                if (xr) {
                     const size_t j = i + 1;
                     const float g = (c[(j + 1) * C + ch] - cc) * inv2dx;
                     const float vv = v ? v[(j * 2 + 0) * C + ch] : 0.0f;
                     const float mm = mu ? mu[(j * 2 + 0) * C + ch] : 0.0f;
                     dv = fmaf(fmaf(rho, vv - g, mm), inv2dx, dv);
                 }
-                if (q - 1 >= 1) {
+                if (xl) {
                     const size_t j = i - 1;
                     const float g = (cc - c[(j - 1) * C + ch]) * inv2dx;
                     const float vv = v ? v[(j * 2 + 0) * C + ch] : 0.0f;
                     const float mm = mu ? mu[(j * 2 + 0) * C + ch] : 0.0f;
                     dv = fmaf(-fmaf(rho, vv - g, mm), inv2dx, dv);
                 }
-                if (r + 1 <= H - 2) {
+                if (yd) {
                     const size_t j = i + W;
                     const float g = (c[(j + W) * C + ch] - cc) * inv2dy;
                     const float vv = v ? v[(j * 2 + 1) * C + ch] : 0.0f;
                     const float mm = mu ? mu[(j * 2 + 1) * C + ch] : 0.0f;
                     dv = fmaf(fmaf(rho, vv - g, mm), inv2dy, dv);
                 }
-                if (r - 1 >= 1) {
+                if (yu) {
                     const size_t j = i - W;
                     const float g = (cc - c[(j - W) * C + ch]) * inv2dy;
                     const float vv = v ? v[(j * 2 + 1) * C + ch] : 0.0f;
@@ -549,75 +558,95 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
     }
 }
 
+template <int CP>
 __global__ void __launch_bounds__(kMaxThreads)
 terminal_kernel(const float* __restrict__ c, const float* __restrict__ c0, const float* __restrict__ v,
                 const float* __restrict__ mu, int H, int W, int C, float rho, float alpha, float area,
                 float inv2dx, float inv2dy, float* __restrict__ pK, float* __restrict__ part) {
     __shared__ float red[16];
-    terminal_block(c, c0, v, mu, H, W, C, rho, alpha, area, inv2dx, inv2dy, pK, part, blockIdx.x, red);
+    terminal_block<CP>(c, c0, v, mu, H, W, C, rho, alpha, area, inv2dx, inv2dy, pK, part,
+                       xcd_tile(blockIdx.x, gridDim.x), red);
 }
 
 // Terminal condition / objective of several images: jobs[j].start is the first
 // global block of job j (one block = 256 consecutive pixels of one image).
+template <int CP>
 __global__ void __launch_bounds__(kMaxThreads)
 terminal_batched_kernel(const PixJob* __restrict__ jobs, int njobs, int C, float rho, float alpha) {
     __shared__ float red[16];
-    const int g = blockIdx.x;
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
     const PixJob& J = jobs[find_job(jobs, njobs, g)];
-    terminal_block(J.c, J.c0, J.v, J.mu, J.H, J.W, C, rho, alpha, J.area, J.inv2dx, J.inv2dy, J.pK, J.part,
-                   g - J.start, red);
+    terminal_block<CP>(J.c, J.c0, J.v, J.mu, J.H, J.W, C, rho, alpha, J.area, J.inv2dx, J.inv2dy, J.pK, J.part,
+                       g - J.start, red);
 }
 
 // v = shrink(grad c - mu/rho) jointly over the 2C components of each pixel;
 // mu += gamma (v - grad c) when update_mu.  Partial sums (kPdQuantities).
+// Two passes over the workgroup's pixel range: one thread per pixel finds the
+// shrink factor and the per-pixel norms, then one thread per v/mu entry
+// (consecutive threads on consecutive floats) writes v and mu.
+template <int CP>
 __device__ __forceinline__ void pd_block(const float* __restrict__ c, const float* __restrict__ c0,
                                          float* __restrict__ v, float* __restrict__ mu, int update_mu, int H, int W,
                                          int C, float rho, float gamma, float inv2dx, float inv2dy,
-                                         float* __restrict__ part, int blk, float* red) {
+                                         float* __restrict__ part, int blk, float* red, float* fac_s) {
     const size_t N = (size_t)H * W;
-    const size_t i = (size_t)blk * blockDim.x + threadIdx.x;
+    const size_t p0 = (size_t)blk * blockDim.x;
+    const size_t i = p0 + threadIdx.x;
+    const float inv_rho = 1.0f / rho;
     float qv[kPdQuantities] = {0, 0, 0, 0, 0, 0, 0};
     if (i < N) {
         const int r = (int)(i / W), q = (int)(i % W);
-        const float inv_rho = 1.0f / rho;
-        float na2 = 0.0f;
-        for (int ch = 0; ch < C; ++ch) {
-            const float ax = grad_x(c, i, q, W, C, ch, inv2dx) - mu[(i * 2 + 0) * C + ch] * inv_rho;
-            const float ay = grad_y(c, i, r, H, W, C, ch, inv2dy) - mu[(i * 2 + 1) * C + ch] * inv_rho;
+        float na2 = 0.0f, ng2 = 0.0f, sf = 0.0f;
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch) {
+            if (ch >= C) break;
+            const float gx = grad_x(c, i, q, W, C, ch, inv2dx);
+            const float gy = grad_y(c, i, r, H, W, C, ch, inv2dy);
+            const float ax = gx - mu[(i * 2 + 0) * C + ch] * inv_rho;
+            const float ay = gy - mu[(i * 2 + 1) * C + ch] * inv_rho;
             na2 = fmaf(ax, ax, fmaf(ay, ay, na2));
-        }
-        const float na = sqrtf(na2);
-        const float fac = na > inv_rho ? (na - inv_rho) / na : 0.0f;
-        float svg = 0, sg = 0, sv = 0, sf = 0, muvg = 0, sh2 = 0;
-        for (int ch = 0; ch < C; ++ch) {
-            for (int dim = 0; dim < 2; ++dim) {
-                const size_t o = (i * 2 + dim) * C + ch;
-                const float g = dim == 0 ? grad_x(c, i, q, W, C, ch, inv2dx) : grad_y(c, i, r, H, W, C, ch, inv2dy);
-                const float m = mu[o];
-                const float vn = fac * (g - m * inv_rho);
-                const float mn = update_mu ? fmaf(gamma, vn - g, m) : m;
-                v[o] = vn;
-                if (update_mu) mu[o] = mn;
-                const float vg = vn - g;
-                svg = fmaf(vg, vg, svg);
-                sg = fmaf(g, g, sg);
-                sv = fmaf(vn, vn, sv);
-                muvg = fmaf(mn, vg, muvg);
-                const float sh = fmaf(mn, inv_rho, vg);
-                sh2 = fmaf(sh, sh, sh2);
-            }
+            ng2 = fmaf(gx, gx, fmaf(gy, gy, ng2));
             const float e = c[i * C + ch] - c0[i * C + ch];
             sf = fmaf(e, e, sf);
         }
-        const float nv = sqrtf(sv);
-        qv[0] = svg;
-        qv[1] = sg;
-        qv[2] = sv;
-        qv[3] = sqrtf(sg);
+        const float na = sqrtf(na2);
+        const float fac = na > inv_rho ? (na - inv_rho) / na : 0.0f;
+        fac_s[threadIdx.x] = fac;
+        const float nv = fac * na;  // |v| of the pixel
+        qv[1] = ng2;
+        qv[2] = nv * nv;
+        qv[3] = sqrtf(ng2);
         qv[4] = sf;
-        qv[5] = nv + muvg;
-        qv[6] = fmaf(0.5f * rho, sh2, nv);
+        qv[5] = nv;
+        qv[6] = nv;
     }
+    __syncthreads();
+    const size_t n2c = 2 * (size_t)C;
+    const size_t pend = p0 + blockDim.x < N ? p0 + blockDim.x : N;
+    const size_t e0 = p0 * n2c, e1 = pend * n2c;
+    float svg = 0.0f, muvg = 0.0f, sh2 = 0.0f;
+    for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const size_t px = e / n2c;
+        const int rem = (int)(e - px * n2c);
+        const int dim = rem >= C;
+        const int ch = rem - dim * C;
+        const int r = (int)(px / W), q = (int)(px % W);
+        const float g = dim == 0 ? grad_x(c, px, q, W, C, ch, inv2dx) : grad_y(c, px, r, H, W, C, ch, inv2dy);
+        const float m = mu[e];
+        const float vn = fac_s[px - p0] * (g - m * inv_rho);
+        const float mn = update_mu ? fmaf(gamma, vn - g, m) : m;
+        v[e] = vn;
+        if (update_mu) mu[e] = mn;
+        const float vg = vn - g;
+        svg = fmaf(vg, vg, svg);
+        muvg = fmaf(mn, vg, muvg);
+        const float sh = fmaf(mn, inv_rho, vg);
+        sh2 = fmaf(sh, sh, sh2);
+    }
+    qv[0] = svg;
+    qv[5] += muvg;
+    qv[6] = fmaf(0.5f * rho, sh2, qv[6]);
 #pragma unroll
     for (int m = 0; m < kPdQuantities; ++m) {
         const float s = block_sum(qv[m], red);
@@ -625,20 +654,26 @@ __device__ __forceinline__ void pd_block(const float* __restrict__ c, const floa
     }
 }
 
+template <int CP>
 __global__ void __launch_bounds__(kMaxThreads)
 pd_step_kernel(const float* __restrict__ c, const float* __restrict__ c0, float* __restrict__ v,
                float* __restrict__ mu, int update_mu, int H, int W, int C, float rho, float gamma,
                float inv2dx, float inv2dy, float* __restrict__ part) {
     __shared__ float red[16];
-    pd_block(c, c0, v, mu, update_mu, H, W, C, rho, gamma, inv2dx, inv2dy, part, blockIdx.x, red);
+    __shared__ float fac_s[kMaxThreads];
+    pd_block<CP>(c, c0, v, mu, update_mu, H, W, C, rho, gamma, inv2dx, inv2dy, part,
+                 xcd_tile(blockIdx.x, gridDim.x), red, fac_s);
 }
 
+template <int CP>
 __global__ void __launch_bounds__(kMaxThreads)
 pd_step_batched_kernel(const PixJob* __restrict__ jobs, int njobs, int update_mu, int C, float rho, float gamma) {
     __shared__ float red[16];
-    const int g = blockIdx.x;
+    __shared__ float fac_s[kMaxThreads];
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
     const PixJob& J = jobs[find_job(jobs, njobs, g)];
-    pd_block(J.c, J.c0, J.v, J.mu, update_mu, J.H, J.W, C, rho, gamma, J.inv2dx, J.inv2dy, J.part, g - J.start, red);
+    pd_block<CP>(J.c, J.c0, J.v, J.mu, update_mu, J.H, J.W, C, rho, gamma, J.inv2dx, J.inv2dy, J.part,
+                 g - J.start, red, fac_s);
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
@@ -657,6 +692,23 @@ int padded_channels(int C) {
     for (int cp : kChannelSteps)
         if (C <= cp) return cp;
     return -1;
+}
+
+// Calls fn(std::integral_constant<int, CP>{}) for the padded channel count of C.
+template <class Fn>
+hipError_t by_channels(int C, Fn&& fn) {
+    switch (padded_channels(C)) {
+        case 1: return fn(std::integral_constant<int, 1>{});
+        case 2: return fn(std::integral_constant<int, 2>{});
+        case 3: return fn(std::integral_constant<int, 3>{});
+        case 4: return fn(std::integral_constant<int, 4>{});
+        case 8: return fn(std::integral_constant<int, 8>{});
+        case 16: return fn(std::integral_constant<int, 16>{});
+        case 31: return fn(std::integral_constant<int, 31>{});
+        case 32: return fn(std::integral_constant<int, 32>{});
+        case 64: return fn(std::integral_constant<int, 64>{});
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int CP, int RT>
@@ -893,15 +945,20 @@ hipError_t launch_adjoint_step_batched(const StepJob* jobs, int njobs, int total
 
 hipError_t launch_terminal_batched(const PixJob* jobs, int njobs, int total, int C, float rho, float alpha,
                                    hipStream_t s) {
-    hipLaunchKernelGGL(terminal_batched_kernel, dim3(total), dim3(kMaxThreads), 0, s, jobs, njobs, C, rho, alpha);
-    return hipGetLastError();
+    return by_channels(C, [&](auto cp) {
+        hipLaunchKernelGGL(terminal_batched_kernel<decltype(cp)::value>, dim3(total), dim3(kMaxThreads), 0, s, jobs,
+                           njobs, C, rho, alpha);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_pd_step_batched(const PixJob* jobs, int njobs, int total, int update_mu, int C, float rho,
                                   float gamma, hipStream_t s) {
-    hipLaunchKernelGGL(pd_step_batched_kernel, dim3(total), dim3(kMaxThreads), 0, s, jobs, njobs, update_mu, C, rho,
-                       gamma);
-    return hipGetLastError();
+    return by_channels(C, [&](auto cp) {
+        hipLaunchKernelGGL(pd_step_batched_kernel<decltype(cp)::value>, dim3(total), dim3(kMaxThreads), 0, s, jobs,
+                           njobs, update_mu, C, rho, gamma);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_reduce_jobs_f64(const RedJob* jobs, int njobs, int max_rows, int nq, hipStream_t s) {
@@ -919,17 +976,21 @@ int pd_blocks(int H, int W) { return (int)(((size_t)H * W + kMaxThreads - 1) / k
 hipError_t launch_terminal(const float* c, const float* c0, const float* v, const float* mu, int H, int W, int C,
                            float rho, float alpha, float area, float* pK, float* part, hipStream_t s) {
     const float inv2dx = 0.5f * (float)W, inv2dy = 0.5f * (float)H;
-    hipLaunchKernelGGL(terminal_kernel, dim3(pd_blocks(H, W)), dim3(kMaxThreads), 0, s, c, c0, v, mu, H, W, C, rho,
-                       alpha, area, inv2dx, inv2dy, pK, part);
-    return hipGetLastError();
+    return by_channels(C, [&](auto cp) {
+        hipLaunchKernelGGL(terminal_kernel<decltype(cp)::value>, dim3(pd_blocks(H, W)), dim3(kMaxThreads), 0, s, c,
+                           c0, v, mu, H, W, C, rho, alpha, area, inv2dx, inv2dy, pK, part);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_pd_step(const float* c, const float* c0, float* v, float* mu, int update_mu, int H, int W, int C,
                           float rho, float gamma, float* part, hipStream_t s) {
     const float inv2dx = 0.5f * (float)W, inv2dy = 0.5f * (float)H;
-    hipLaunchKernelGGL(pd_step_kernel, dim3(pd_blocks(H, W)), dim3(kMaxThreads), 0, s, c, c0, v, mu, update_mu, H,
-                       W, C, rho, gamma, inv2dx, inv2dy, part);
-    return hipGetLastError();
+    return by_channels(C, [&](auto cp) {
+        hipLaunchKernelGGL(pd_step_kernel<decltype(cp)::value>, dim3(pd_blocks(H, W)), dim3(kMaxThreads), 0, s, c,
+                           c0, v, mu, update_mu, H, W, C, rho, gamma, inv2dx, inv2dy, part);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_nonfinite(const float* x, size_t n, int* flag, hipStream_t s) {
