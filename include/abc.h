@@ -311,6 +311,54 @@ int abc_wsnet_adam(float* params, const float* grad, float* m, float* v, size_t 
 /* Description of the calling thread's last warm-start failure. */
 const char* abc_wsnet_last_error(void);
 
+/* ---- Segmentation scores (Sec. 4.4) ---------------------------------------
+ * The paper scores a processed image by labelling its segments with a
+ * watershed at threshold 0.02 and computing on those labels the intra-region
+ * variance IRV (over the original image), the inter-region contrast IRC (over
+ * the processed image) and the validity score VS = IRV / IRC:
+ *   IRV = (1/N) sum_j sum_{p in R_j} |c0_p - mean(c0 over R_j)|^2,
+ *   IRC = min_{i<j} |mean(c over R_i) - mean(c over R_j)|,
+ * with |.| the Euclidean norm over channels; labels without pixels are
+ * ignored and IRC = VS = NaN when fewer than two labels hold pixels.
+ *
+ * The watershed (the paper names no variant) is the marker-based one defined
+ * as a minimum spanning forest, whose result is unique:
+ *   relief g2(p) = sum_ch gx^2 + gy^2, gx = (c(q+1) - c(q-1)) / 2 and
+ *     gy = (c(r+1) - c(r-1)) / 2 (central differences of Def. 3.1 in pixel
+ *     units, zero on the first/last column and row), in FP32 with, per
+ *     channel in ascending order, g2 = fma(gx, gx, fma(gy, gy, g2));
+ *   markers: 4-connected components of {g2 < theta * theta (FP32)}; if none,
+ *     the pixel of least g2 (lowest index among ties);
+ *   edges: 4-neighbour pairs ordered by (max(g2 p, g2 q), index), index 2p
+ *     for (p, p+1) and 2p+1 for (p, p+W), p = r*W + q;
+ *   each pixel takes the marker component of its tree in the minimum
+ *     spanning forest relative to the markers; components are numbered
+ *     0..k-1 in order of their smallest pixel index.
+ * Cost: the pairwise IRC search is O(k^2) in the number of labels. */
+typedef struct abc_seg_stats {
+    int32_t k;        /* labels: watershed segments, or max(labels_in) + 1          */
+    int32_t nonempty; /* labels holding at least one pixel                          */
+    int32_t rounds;   /* flooding rounds of the forest construction (0 with labels_in) */
+    int32_t reserved;
+    double irv, irc, vs;
+} abc_seg_stats;
+
+/* Workspace bytes of abc_segment for an H x W x C image (H*W < 2^31).  Host only. */
+int abc_segment_workspace_bytes(int H, int W, int C, size_t* bytes);
+
+/* Labels and scores one image.
+ *   c: processed field, c0: original image, both H x W x C FP32 device, HWC.
+ *   theta: watershed threshold (the paper uses 0.02).
+ *   labels_in: device H x W int32 labels in [0, H*W) to score instead of the
+ *     watershed (theta and labels_out are then unused), or NULL.
+ *   labels_out: device H x W int32 watershed labels, or NULL.
+ *   stats: host output.
+ * Returns ABC_OK, ABC_EINVAL (bad argument, small workspace, label out of
+ * range) or ABC_EHIP.  Synchronises the stream (several times: the forest is
+ * built in rounds whose count is read back). */
+int abc_segment(const float* c, const float* c0, int H, int W, int C, float theta, const int32_t* labels_in,
+                int32_t* labels_out, abc_seg_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

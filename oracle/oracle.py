@@ -122,6 +122,13 @@ def lib():
         L.or_solve.argtypes = [_dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params), _dp, _dp, _dp, _dp,
                                _dp, _dp, _dp, _dp, _dp, ct.POINTER(_Stats)]
         L.or_solve.restype = ct.c_int
+        _fp = ct.POINTER(ct.c_float)
+        _ip = ct.POINTER(ct.c_int32)
+        L.seg_relief.argtypes = [_fp, ct.c_int, ct.c_int, ct.c_int, _fp]
+        L.seg_watershed.argtypes = [_fp, ct.c_int, ct.c_int, ct.c_int, ct.c_float, _ip]
+        L.seg_watershed.restype = ct.c_int
+        L.seg_metrics.argtypes = [_fp, _fp, _ip, ct.c_int, ct.c_int, ct.c_int, ct.c_int, _dp]
+        L.seg_metrics.restype = ct.c_int
         L.or_num_threads.restype = ct.c_int
         L.or_set_num_threads.argtypes = [ct.c_int]
         _lib = L
@@ -299,3 +306,55 @@ def solve(c0, P: Params, eps=None, mu=None, decisions=None):
     stats = {n: getattr(st, n) for n, _ in _Stats._fields_}
     return {"c": cK, "eps": e, "v": v, "mu": m, "decisions": dec_out, "trace": trace, "eps_log": eps_log,
             "grad_log": grad_log, "stats": stats}
+
+
+# ---------------------------------------------------------------------------
+# Segmentation metrics of Sec. 4.4 on a watershed labelling (seg_oracle.c).
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def seg_relief(c):
+    """FP32 relief g2 = |grad c|^2 (central differences in pixel units) of an (H, W, C) field."""
+    c = _f32(c)
+    H, W, C = c.shape
+    g2 = np.empty((H, W), dtype=np.float32)
+    lib().seg_relief(c.ctypes.data_as(ct.POINTER(ct.c_float)), H, W, C, g2.ctypes.data_as(ct.POINTER(ct.c_float)))
+    return g2
+
+
+def seg_watershed(c, theta: float = 0.02):
+    """Marker-based watershed of an (H, W, C) field at threshold theta (Sec. 4.4):
+    returns (labels (H, W) int32 in [0, k), k)."""
+    c = _f32(c)
+    H, W, C = c.shape
+    lab = np.empty((H, W), dtype=np.int32)
+    k = lib().seg_watershed(c.ctypes.data_as(ct.POINTER(ct.c_float)), H, W, C, ct.c_float(theta),
+                            lab.ctypes.data_as(ct.POINTER(ct.c_int32)))
+    if k < 1:
+        raise RuntimeError(f"seg_watershed failed ({k})")
+    return lab, k
+
+
+def seg_metrics(c, c0, labels, k: int | None = None) -> dict:
+    """IRV, IRC and VS (Sec. 4.4) of a labelling: c the processed field, c0 the original image."""
+    c, c0 = _f32(c), _f32(c0)
+    H, W, C = c.shape
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    if k is None:
+        k = int(labels.max()) + 1
+    out = np.empty(3)
+    rc = lib().seg_metrics(c.ctypes.data_as(ct.POINTER(ct.c_float)), c0.ctypes.data_as(ct.POINTER(ct.c_float)),
+                           labels.ctypes.data_as(ct.POINTER(ct.c_int32)), H, W, C, int(k), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"seg_metrics failed ({rc})")
+    return {"irv": float(out[0]), "irc": float(out[1]), "vs": float(out[2])}
+
+
+def segment(c, c0, theta: float = 0.02) -> dict:
+    """Watershed labels of c and their metrics against the original image c0."""
+    lab, k = seg_watershed(c, theta)
+    m = seg_metrics(c, c0, lab, k)
+    m.update(labels=lab, k=k)
+    return m

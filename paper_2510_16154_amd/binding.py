@@ -48,6 +48,11 @@ class AbcImage(ct.Structure):
                 ("H", ct.c_int32), ("W", ct.c_int32)]
 
 
+class AbcSegStats(ct.Structure):
+    _fields_ = [("k", ct.c_int32), ("nonempty", ct.c_int32), ("rounds", ct.c_int32), ("reserved", ct.c_int32),
+                ("irv", ct.c_double), ("irc", ct.c_double), ("vs", ct.c_double)]
+
+
 class AbcStats(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("outer_iters", ct.c_int32), ("inner_iters", ct.c_int32),
                 ("ls_evals", ct.c_int32)] + [(n, ct.c_double) for n in (
@@ -157,6 +162,9 @@ def lib():
                                               ct.POINTER(AbcParams), ct.POINTER(ct.c_size_t)]
     L.abc_solve_batched.argtypes = [ct.POINTER(AbcImage), ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp,
                                     ct.c_size_t, _vp, ct.POINTER(AbcStats), ct.POINTER(ct.c_double)]
+    L.abc_segment_workspace_bytes.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]
+    L.abc_segment.argtypes = [_vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.c_float, _vp, _vp, ct.POINTER(AbcSegStats),
+                              _vp, ct.c_size_t, _vp]
     for name in exported_names():
         if name not in ("abc_version", "abc_last_error"):
             getattr(L, name).restype = ct.c_int
@@ -193,6 +201,15 @@ def _ptr(t):
 
 def _stats_dict(s: AbcStats) -> dict:
     return {n: getattr(s, n) for n, _ in AbcStats._fields_}
+
+
+def _ptr_i32(t):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("labels must be a contiguous int32 tensor on the GPU")
+    return ct.c_void_p(t.data_ptr())
 
 
 # ------------------------------------------------------------------ host-only calls
@@ -460,3 +477,30 @@ def abc_wsnet_loss_grad(params, x, mu_t, eps_t, K: int, box: Params, w_eps: floa
 def abc_wsnet_adam(params, grad, m, v, t: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
     _wcheck(_wsnet_lib().abc_wsnet_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(t),
                                         float(lr), float(b1), float(b2), float(eps), _stream()))
+
+
+# ------------------------------------------------------------------ segmentation scores
+def abc_segment_workspace_bytes(H: int, W: int, C: int) -> int:
+    n = ct.c_size_t()
+    _check(lib().abc_segment_workspace_bytes(H, W, C, ct.byref(n)))
+    return n.value
+
+
+def abc_segment(c, c0, theta: float = 0.02, labels=None, want_labels=True, ws=None):
+    """Watershed labels of the processed field c (H x W x C) and the IRV / IRC / VS
+    scores of Sec. 4.4 against the original image c0; with ``labels`` (int32
+    H x W) those labels are scored instead.  Returns (labels or None, stats)."""
+    torch = _torch()
+    H, W, C = c.shape
+    if tuple(c0.shape) != (H, W, C):
+        raise ValueError("c and c0 must have the same shape")
+    if labels is not None and tuple(labels.shape) != (H, W):
+        raise ValueError("labels must be H x W")
+    nb = abc_segment_workspace_bytes(H, W, C)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=c.device)
+    out = torch.empty((H, W), dtype=torch.int32, device=c.device) if (labels is None and want_labels) else None
+    st = AbcSegStats()
+    _check(lib().abc_segment(_ptr(c), _ptr(c0), H, W, C, ct.c_float(theta), _ptr_i32(labels), _ptr_i32(out),
+                             ct.byref(st), ct.c_void_p(ws.data_ptr()), nb, _stream()))
+    return out, {n: getattr(st, n) for n, _ in AbcSegStats._fields_ if n != "reserved"}

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["abc_kernels.hip", "abc_api.hip", "abc_net.hip"]
+SOURCES = ["abc_kernels.hip", "abc_api.hip", "abc_net.hip", "abc_seg.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

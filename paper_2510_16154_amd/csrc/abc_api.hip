@@ -1618,3 +1618,7 @@ extern "C" int abc_autotune(const float* c0, int H, int W, int C, abc_params* p,
     }
     return ABC_OK;
 }
+
+namespace abc {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace abc

@@ -5,8 +5,12 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace abc {
+
+// Records the calling thread's last error (returned by abc_last_error).
+void set_last_error(const std::string& msg);
 
 // Tile of pixels handled by one workgroup of the windowed interaction kernels
 // (one thread per pixel; the workgroup stages the tile plus an R-pixel halo

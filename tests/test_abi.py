@@ -78,3 +78,20 @@ def test_null_pointers_are_rejected():
     assert L.abc_solve(None, 8, 8, 3, ct.byref(p), None, None, None, None, None, 0, None, None,
                        None) == A.ABC_EINVAL
     assert L.abc_pd_step(None, None, 8, 8, 3, ct.byref(p), None, None, 1, None, None, 0, None) == A.ABC_EINVAL
+
+
+def test_segment_entry_points_check_arguments_on_the_host():
+    L = B.lib()
+    assert B.abc_segment_workspace_bytes(64, 48, 3) >= 64 * 48 * (4 + 1 + 4 * 4 + 8 + 8 * (2 + 2 * 3))
+    n = ct.c_size_t()
+    assert L.abc_segment_workspace_bytes(0, 8, 3, ct.byref(n)) == A.ABC_EINVAL
+    assert L.abc_segment_workspace_bytes(8, 8, 65, ct.byref(n)) == A.ABC_EINVAL
+    st = B.AbcSegStats()
+    dummy = ct.c_void_p(16)
+    assert L.abc_segment(None, dummy, 8, 8, 3, ct.c_float(0.02), None, None, ct.byref(st), dummy, 1 << 30,
+                         None) == A.ABC_EINVAL
+    assert L.abc_segment(dummy, dummy, 8, 8, 3, ct.c_float(float("nan")), None, None, ct.byref(st), dummy,
+                         1 << 30, None) == A.ABC_EINVAL
+    need = B.abc_segment_workspace_bytes(8, 8, 3)
+    assert L.abc_segment(dummy, dummy, 8, 8, 3, ct.c_float(0.02), None, None, ct.byref(st), dummy, need - 1,
+                         None) == A.ABC_EINVAL
