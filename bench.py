@@ -68,9 +68,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
                     help="repeat the oracle's full forward+adjoint sweep until this much time has passed")
-    ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512"],
+    ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512", "hyper2048"],
                     help="voronoi512: the headline line (default); batch64: the batched form; segment512: "
-                         "watershed labels and IRV/IRC/VS scores of a solved 512 x 512 image")
+                         "watershed labels and IRV/IRC/VS scores of a solved 512 x 512 image; hyper2048: the "
+                         "differentiable form on 2048 x 2048 x 31 (checkpointed forward + backward)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit; used to calibrate "
                          "the HBM byte counters")
@@ -96,6 +97,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "segment512":
         return bench_segment(args)
+    if args.workload == "hyper2048":
+        return bench_hyper(args)
 
     import paper_2510_16154_amd as A
     from paper_2510_16154_amd.workloads import VORONOI512 as wl
@@ -228,6 +231,110 @@ def bench_batch(args) -> int:
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
            "sweeps_per_solve": evals,
            "agent_steps_per_s": npx * wb.K * evals / len(stats) / t}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_hyper(args) -> int:
+    """Differentiable form on the 2048 x 2048 x 31 smooth-spectrum image (R = 2, K = 100):
+    one step = the forward sweep keeping a checkpoint every 10 steps plus the backward of
+    l = <w, c^K> (adjoint sweep, each segment recomputed once).  value = H W K / step time.
+    Per-launch kernel times come from a 10-step sweep with the full trajectory."""
+    import torch
+
+    import paper_2510_16154_amd as A
+    from paper_2510_16154_amd.workloads import HYPER2048 as wl
+
+    dev = torch.device("cuda:0")
+    H, W, C, K, R = wl.H, wl.W, wl.C, wl.K, wl.R
+    c0n = wl.image()
+    c0 = torch.as_tensor(c0n, device=dev)
+    params = A.Params(K=K, R=R, ckpt_every=10)
+    eps = torch.full((K, 2), params.eps_init, dtype=torch.float32, device=dev)
+    w = torch.randn((H, W, C), generator=torch.Generator().manual_seed(2003)).to(dev)
+    ws_f = torch.empty(max(A.abc_workspace_bytes(A.ABC_WS_FORWARD, H, W, C, params), 1), dtype=torch.uint8,
+                       device=dev)
+    ws_a = torch.empty(A.abc_workspace_bytes(A.ABC_WS_ADJOINT, H, W, C, params), dtype=torch.uint8, device=dev)
+    traj = torch.empty((A.abc_traj_slots(params), H, W, C), dtype=torch.float32, device=dev)
+    g0 = torch.empty_like(c0)
+    geps = torch.empty((K, 2), dtype=torch.float32, device=dev)
+
+    def step():
+        A.abc_forward_dynamics(c0, eps, params, traj=traj, ws=ws_f)
+        A.abc_adjoint_dynamics(traj, eps, params, w, g0=g0, geps=geps, ws=ws_a)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    del traj, ws_f, ws_a
+
+    # per-launch times: a 10-step sweep with the full trajectory, HIP events on the kernels' stream
+    Ks = 10
+    ps = A.Params(K=Ks, R=R)
+    es = eps[:Ks].contiguous()
+    tr = torch.empty((Ks + 1, H, W, C), dtype=torch.float32, device=dev)
+    wf = torch.empty(max(A.abc_workspace_bytes(A.ABC_WS_FORWARD, H, W, C, ps), 1), dtype=torch.uint8, device=dev)
+    wa = torch.empty(A.abc_workspace_bytes(A.ABC_WS_ADJOINT, H, W, C, ps), dtype=torch.uint8, device=dev)
+    ge = torch.empty((Ks, 2), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd_ms, adj_ms = [], []
+    for _ in range(5):
+        ev[0].record(stream)
+        A.abc_forward_dynamics(c0, es, ps, traj=tr, ws=wf)
+        ev[1].record(stream)
+        A.abc_adjoint_dynamics(tr, es, ps, w, g0=g0, geps=ge, ws=wa)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        fwd_ms.append(ev[0].elapsed_time(ev[1]))
+        adj_ms.append(ev[1].elapsed_time(ev[2]))
+    t_fwd = float(np.median(fwd_ms)) * 1e-3 / Ks
+    t_adj = float(np.median(adj_ms)) * 1e-3 / Ks
+    pairs = window_pairs(H, W, R)
+    npx = H * W
+
+    def kernel(name, t, flops, nbytes):
+        return {"kernel": name, "launch_ms": t * 1e3, "tflops": flops / t / 1e12, "gbs": nbytes / t / 1e9,
+                "flops_per_launch": flops, "bytes_per_launch": nbytes,
+                "roof_ms": max(nbytes / (PEAK_HBM_GBS * 1e9), flops / (PEAK_FP32_VALU_TFLOPS * 1e12)) * 1e3}
+
+    kf = kernel(f"fwd_step_kernel<31,{R}>", t_fwd, pairs * flops_per_pair(C, "fwd"), 8 * C * npx)
+    ka = kernel(f"adj_step_kernel<31,{R}>", t_adj, pairs * flops_per_pair(C, "adj"), 12 * C * npx)
+    out = {"metric": "agent-steps/sec (fwd+adjoint), differentiable form", "value": npx * K / t_step,
+           "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic (seeded smooth-spectrum Voronoi image)",
+           "config": {"workload": wl.name, "H": H, "W": W, "C": C, "R": R, "K": K, "ckpt_every": 10,
+                      "step": "checkpointed forward sweep + backward (adjoint sweep with segment recompute)"},
+           "kernels": {"fwd": kf, "adj": ka},
+           "roofline": {"kernel": ka["kernel"], "bound": "alu", "achieved": ka["tflops"],
+                        "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ka["tflops"] / PEAK_FP32_VALU_TFLOPS, "traffic": None},
+           "hbm": {"kernel": kf["kernel"], "achieved_gbs": kf["gbs"], "peak_gbs": PEAK_HBM_GBS,
+                   "frac": kf["gbs"] / PEAK_HBM_GBS}}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        crop = np.ascontiguousarray(c0n[960:1088, 960:1088])
+        P = O.Params(K=K, R=R)
+        e = np.full((K, 2), 57.0)
+        pK = np.random.default_rng(0).normal(size=crop.shape)
+        reps, t1 = 0, time.perf_counter()
+        while True:
+            tr_o = O.forward_sweep(crop, P, e)
+            O.adjoint_sweep(tr_o, P, pK, e)
+            reps += 1
+            dt = time.perf_counter() - t1
+            if dt >= args.cpu_min_seconds:
+                break
+        out["cpu_baseline"] = {"value": crop.shape[0] * crop.shape[1] * K * reps / dt, "unit": "agent-steps/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"{reps} x (forward + adjoint sweep, {K} steps) of a 128x128x31 crop, "
+                                         f"R={R}, FP64, {dt:.1f} s"}
     print(json.dumps(out), flush=True)
     return 0
 

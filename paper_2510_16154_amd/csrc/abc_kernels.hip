@@ -91,14 +91,16 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
 }
 
-// LDS slot of one pixel: CP channels, then the inside mask, padded to whole
-// 16-byte vectors (8 bytes for one channel) so that a neighbour is read with
-// ds_read_b128 / b64: consecutive lanes then touch consecutive 16-byte slots
-// and the reads are free of bank conflicts.
+// LDS slot of one pixel: CP channels, then the inside mask, in whole 16-byte
+// vectors (8 bytes for one channel) so that a neighbour is read with
+// ds_read_b128 / b64.  The slot stride is an odd number of vectors: the
+// lanes of a read then fall on distinct bank groups (an even stride such as
+// 8 vectors for 31 channels would put every lane of a wave on the same banks).
 template <int CP>
 struct Slot {
-    static constexpr int NV = CP == 1 ? 1 : (CP + 1 + 3) / 4;  // vectors per pixel
-    static constexpr int CS = CP == 1 ? 2 : 4 * NV;             // floats per pixel
+    static constexpr int NV = CP == 1 ? 1 : (CP + 1 + 3) / 4;        // vectors holding data
+    static constexpr int NS = CP == 1 ? 1 : (NV % 2 ? NV : NV + 1);  // vectors per slot (stride)
+    static constexpr int CS = CP == 1 ? 2 : 4 * NS;                  // floats per slot
 };
 
 template <int CP>
@@ -846,7 +848,8 @@ int tile_count(int H, int W, Tile t) { return ((W + t.tx - 1) / t.tx) * ((H + t.
 size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     const int cp = padded_channels(C);
     if (cp < 0) return (size_t)-1;
-    const int cs = cp == 1 ? 2 : 4 * ((cp + 1 + 3) / 4);
+    const int nv = (cp + 1 + 3) / 4;
+    const int cs = cp == 1 ? 2 : 4 * (nv % 2 ? nv : nv + 1);
     return (size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)cs * sizeof(float);
 }
 
@@ -856,14 +859,38 @@ bool tile_ok(int C, int R, Tile t, int fields) {
     return tile_lds_bytes(C, R, t, fields) <= kMaxLds;
 }
 
+// Waves one CU can hold for a tile, limited by LDS and by 8 waves per SIMD.
+static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
+    const int wpb = (t.tx * t.ty + kWave - 1) / kWave;
+    const size_t lds = tile_lds_bytes(C, R, t, fields);
+    const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
+    return std::min(by_lds, 32 / wpb) * wpb;
+}
+
+// First candidate whose LDS fits in 64 KB (several workgroups per CU).  When
+// that leaves fewer than 8 waves per CU (wide pixels), the candidate with the
+// most waves per CU wins instead, then the one with the least halo.
 Tile default_tile(int C, int R, int fields) {
     static const Tile cands[] = {{32, 8}, {16, 16}, {64, 4}, {16, 8}, {32, 4}, {8, 16}, {8, 8}, {64, 1}};
     const size_t budget = 64 * 1024;
     for (const Tile& t : cands)
-        if (tile_ok(C, R, t, fields) && tile_lds_bytes(C, R, t, fields) <= budget) return t;
-    for (const Tile& t : cands)
-        if (tile_ok(C, R, t, fields)) return t;
-    return Tile{0, 0};
+        if (tile_ok(C, R, t, fields) && tile_lds_bytes(C, R, t, fields) <= budget &&
+            tile_waves_per_cu(C, R, t, fields) >= 8)
+            return t;
+    Tile best{0, 0};
+    int best_w = 0;
+    double best_eff = 0.0;
+    for (const Tile& t : cands) {
+        if (!tile_ok(C, R, t, fields)) continue;
+        const int w = tile_waves_per_cu(C, R, t, fields);
+        const double eff = (double)(t.tx * t.ty) / ((double)(t.tx + 2 * R) * (t.ty + 2 * R));
+        if (w > best_w || (w == best_w && eff > best_eff)) {
+            best = t;
+            best_w = w;
+            best_eff = eff;
+        }
+    }
+    return best;
 }
 
 hipError_t launch_forward_step(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
