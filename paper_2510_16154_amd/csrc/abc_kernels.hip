@@ -403,6 +403,301 @@ adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 }
 
 // ----------------------------------------------------------------------------
+// Wide pixels (16 to 64 channels) with a radius of 1 to 3: G = CP/8 lanes per
+// pixel, each lane owning 8 channels.  A pixel slot of 31 floats per field
+// would let only a few waves share a CU's LDS and keep each lane busy with
+// long per-channel chains; split over lanes, a 1024-thread workgroup covers
+// a 16 x 16 tile with 16 waves.  Per neighbour every lane forms its partial
+// |D|^2 (and D . dp), the G lanes of the pixel add them with DPP moves
+// (adjacent lanes, no LDS), all of them evaluate the kernel weight, and each
+// lane updates its own 8 channels.  The tile is staged as G channel planes of
+// 32-byte slots; plane g starts wide_shift(G, g) vectors into its region so
+// that the G x (16/G) lanes of every 16-lane read group hit distinct banks.
+// The order of every sum is fixed (channels within a lane, then the lane
+// pairs, then the window in the a, b order), so results do not depend on the
+// tile shape or on timing.
+constexpr int kMaxWideThreads = 1024;
+
+template <int CP>
+struct Wide {
+    static constexpr int G = (CP + 7) / 8;
+};
+
+__host__ __device__ constexpr int wide_shift(int G, int g) {
+    return G == 2 ? g : (G == 4 ? (g & 1) + 8 * (g >> 1) : (g & 1) + 4 * (g >> 1));
+}
+
+// Floats per channel plane: 32-byte slots, rounded to 256 bytes, plus room for the shift.
+__host__ __device__ constexpr int wide_plane_floats(int LW, int LH) {
+    return ((LW * LH * 32 + 255) / 256 * 256 + 256) / 4;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the G adjacent lanes of a pixel; every lane gets the same bits.
+template <int G>
+__device__ __forceinline__ float group_sum(float x) {
+    x = x + dpp_mov<0xB1>(x);                         // quad_perm [1,0,3,2]
+    if constexpr (G >= 4) x = x + dpp_mov<0x4E>(x);  // quad_perm [2,3,0,1]
+    if constexpr (G >= 8) x = x + dpp_mov<0x141>(x); // row_half_mirror
+    return x;
+}
+
+__device__ __forceinline__ void load8(const float* p, float (&v)[8]) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0];
+    const float4 b = reinterpret_cast<const float4*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+// Stage rows [y0-R, y0+TY+R) x cols [x0-R, x0+TX+R) of an HWC field as G
+// channel planes: thread (x, y) of the (TX G) x TY workgroup fills plane
+// x % G of cell x / G in every TY-th row, 8 channels as two 16-byte vectors
+// (the G lanes of a cell read one contiguous run of 4C bytes).  Cells
+// outside the image and channels >= C are 0.
+template <int G>
+__device__ __forceinline__ void stage_wide(float* dst, const float* __restrict__ src, int H, int W, int C, int x0,
+                                           int y0, int R, int LW, int LH, int pf) {
+    const int nx = LW * G;
+    for (int ly = threadIdx.y; ly < LH; ly += blockDim.y) {
+        const int gy = y0 - R + ly;
+        const bool row_in = (unsigned)gy < (unsigned)H;
+        for (int e = threadIdx.x; e < nx; e += blockDim.x) {
+            const int lx = e / G, g = e % G;
+            const int gx = x0 - R + lx;
+            float v[8];
+            if (row_in && (unsigned)gx < (unsigned)W) {
+                const float* p = src + ((size_t)gy * W + gx) * C + 8 * g;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = (8 * g + k < C) ? p[k] : 0.0f;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = 0.0f;
+            }
+            float4* d = reinterpret_cast<float4*>(dst + g * pf + wide_shift(G, g) * 4 + (ly * LW + lx) * 8);
+            d[0] = make_float4(v[0], v[1], v[2], v[3]);
+            d[1] = make_float4(v[4], v[5], v[6], v[7]);
+        }
+    }
+}
+
+template <int G, int RT, bool BORDER>
+__device__ __forceinline__ void fwd_window_wide(const float* me, int LW, const float (&ci)[8], float (&acc)[8],
+                                                float Ax, float Ay, float ech, int gx, int gy, int H, int W) {
+#pragma unroll 1
+    for (int a = -RT; a <= RT; ++a) {
+        const float om_row = fmaf(-Ay, (float)(a * a), 1.0f);
+        const bool row_in = (unsigned)(gy + a) < (unsigned)H;
+#pragma unroll
+        for (int b = -RT; b <= RT; ++b) {
+            if (a == 0 && b == 0) continue;
+            float cj[8];
+            load8(me + (a * LW + b) * 8, cj);
+            const float om = fmaf(-Ax, (float)(b * b), om_row);
+            float d[8];
+            float n2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                d[k] = cj[k] - ci[k];
+                n2 = fmaf(d[k], d[k], n2);
+            }
+            n2 = group_sum<G>(n2);
+            const float t = clamp01(fmaf(-ech, n2, om));
+            const float t2 = t * t;
+            float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
+            if (BORDER) w *= (row_in && (unsigned)(gx + b) < (unsigned)W) ? 1.0f : 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] = fmaf(w, d[k], acc[k]);
+        }
+    }
+}
+
+template <int CP, int RT>
+__device__ __forceinline__ void fwd_tile_wide(const float* __restrict__ cin, float* __restrict__ cout, float exh,
+                                              float ech, int H, int W, int C, int tile, int tiles_x, float dts,
+                                              float dx2, float dy2, float* lds) {
+    constexpr int G = Wide<CP>::G;
+    const int TX = blockDim.x / G, TY = blockDim.y;
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int LW = TX + 2 * RT, LH = TY + 2 * RT;
+    const int pf = wide_plane_floats(LW, LH);
+    const bool interior = x0 >= RT && y0 >= RT && x0 + TX + RT <= W && y0 + TY + RT <= H;
+    stage_wide<G>(lds, cin, H, W, C, x0, y0, RT, LW, LH, pf);
+    __syncthreads();
+    const int g = threadIdx.x % G, px = threadIdx.x / G;
+    const int gx = x0 + px, gy = y0 + threadIdx.y;
+    const float* me = lds + g * pf + wide_shift(G, g) * 4 + ((threadIdx.y + RT) * LW + px + RT) * 8;
+    float ci[8], acc[8];
+    load8(me, ci);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+    if (interior)
+        fwd_window_wide<G, RT, false>(me, LW, ci, acc, exh * dx2, exh * dy2, ech, gx, gy, H, W);
+    else
+        fwd_window_wide<G, RT, true>(me, LW, ci, acc, exh * dx2, exh * dy2, ech, gx, gy, H, W);
+    if (gx < W && gy < H) {
+        float* o = cout + ((size_t)gy * W + gx) * C + 8 * g;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (8 * g + k < C) o[k] = fmaf(dts, acc[k], ci[k]);
+    }
+}
+
+template <int G, int RT, bool BORDER>
+__device__ __forceinline__ void adj_window_wide(const float* mc, const float* mp, int LW, const float (&ci)[8],
+                                                const float (&pi)[8], float (&acc)[8], float& sx, float& sc, float Ax,
+                                                float Ay, float ech, float ec20, float dx2, float dy2, int gx, int gy,
+                                                int H, int W) {
+#pragma unroll 1
+    for (int a = -RT; a <= RT; ++a) {
+        const float om_row = fmaf(-Ay, (float)(a * a), 1.0f);
+        const float d2_row = dy2 * (float)(a * a);
+        const bool row_in = (unsigned)(gy + a) < (unsigned)H;
+#pragma unroll
+        for (int b = -RT; b <= RT; ++b) {
+            if (a == 0 && b == 0) continue;
+            float cj[8], pj[8];
+            load8(mc + (a * LW + b) * 8, cj);
+            load8(mp + (a * LW + b) * 8, pj);
+            const float om = fmaf(-Ax, (float)(b * b), om_row);
+            const float d2 = fmaf(dx2, (float)(b * b), d2_row);
+            float d[8], dp[8];
+            float n2 = 0.0f, ddp = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                d[k] = cj[k] - ci[k];
+                n2 = fmaf(d[k], d[k], n2);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                dp[k] = pj[k] - pi[k];
+                ddp = fmaf(d[k], dp[k], ddp);
+            }
+            n2 = group_sum<G>(n2);
+            ddp = group_sum<G>(ddp);
+            const float t = clamp01(fmaf(-ech, n2, om));
+            const float t2 = t * t;
+            const float t3 = t2 * t;
+            float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
+            float u = (t - 1.0f) * t3;
+            if (BORDER) {
+                const float m = (row_in && (unsigned)(gx + b) < (unsigned)W) ? 1.0f : 0.0f;
+                w *= m;
+                u *= m;
+            }
+            const float q = u * ddp;
+            const float coef = ec20 * q;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] = fmaf(coef, d[k], fmaf(w, dp[k], acc[k]));
+            sx = fmaf(d2, q, sx);
+            sc = fmaf(n2, q, sc);
+        }
+    }
+}
+
+template <int CP, int RT>
+__device__ __forceinline__ void adj_tile_wide(const float* __restrict__ c, const float* __restrict__ pin,
+                                              float* __restrict__ pout, float ex, float ec, int H, int W, int C,
+                                              int tile, int tiles_x, float dts, float dx2, float dy2,
+                                              double* __restrict__ part, float* lds, double* red) {
+    constexpr int G = Wide<CP>::G;
+    const int TX = blockDim.x / G, TY = blockDim.y;
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int LW = TX + 2 * RT, LH = TY + 2 * RT;
+    const int pf = wide_plane_floats(LW, LH);
+    const bool interior = x0 >= RT && y0 >= RT && x0 + TX + RT <= W && y0 + TY + RT <= H;
+    float* ldc = lds;
+    float* ldp = lds + G * pf;
+    stage_wide<G>(ldc, c, H, W, C, x0, y0, RT, LW, LH, pf);
+    stage_wide<G>(ldp, pin, H, W, C, x0, y0, RT, LW, LH, pf);
+    __syncthreads();
+    const int g = threadIdx.x % G, px = threadIdx.x / G;
+    const int gx = x0 + px, gy = y0 + threadIdx.y;
+    const int off = g * pf + wide_shift(G, g) * 4 + ((threadIdx.y + RT) * LW + px + RT) * 8;
+    const float* mc = ldc + off;
+    const float* mp = ldp + off;
+    float ci[8], pi[8], acc[8];
+    load8(mc, ci);
+    load8(mp, pi);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+    float sx = 0.0f, sc = 0.0f;
+    const float exh = 0.5f * ex, ech = 0.5f * ec;
+    if (interior)
+        adj_window_wide<G, RT, false>(mc, mp, LW, ci, pi, acc, sx, sc, exh * dx2, exh * dy2, ech, 20.0f * ec, dx2,
+                                      dy2, gx, gy, H, W);
+    else
+        adj_window_wide<G, RT, true>(mc, mp, LW, ci, pi, acc, sx, sc, exh * dx2, exh * dy2, ech, 20.0f * ec, dx2,
+                                     dy2, gx, gy, H, W);
+    const bool valid = gx < W && gy < H;
+    if (valid) {
+        float* o = pout + ((size_t)gy * W + gx) * C + 8 * g;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (8 * g + k < C) o[k] = fmaf(dts, acc[k], pi[k]);
+    }
+    // every lane of a pixel holds the same integrands; lane 0 contributes them
+    if (!valid || g != 0) sx = sc = 0.0f;
+    const double bx = block_sum_f64((double)sx, red);
+    const double bc = block_sum_f64((double)sc, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[2 * tile + 0] = bx;
+        part[2 * tile + 1] = bc;
+    }
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxWideThreads)
+fwd_step_wide_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps, int k,
+                     int H, int W, int C, int tiles_x, float dts, float dx2, float dy2) {
+    extern __shared__ float lds[];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    fwd_tile_wide<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, tile, tiles_x, dts, dx2, dy2,
+                          lds);
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxWideThreads)
+fwd_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C) {
+    extern __shared__ float lds[];
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const StepJob& J = jobs[find_job(jobs, njobs, g)];
+    const size_t f = (size_t)J.H * J.W * C;
+    const float* e = J.eps + 2 * k;
+    fwd_tile_wide<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H, J.W,
+                          C, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxWideThreads)
+adj_step_wide_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
+                     const float* __restrict__ eps, int k, int H, int W, int C, int tiles_x, float dts, float dx2,
+                     float dy2, double* __restrict__ part) {
+    extern __shared__ float lds[];
+    __shared__ double red[16];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    adj_tile_wide<CP, RT>(c, pin, pout, eps[2 * k], eps[2 * k + 1], H, W, C, tile, tiles_x, dts, dx2, dy2, part, lds,
+                          red);
+}
+
+template <int CP, int RT>
+__global__ void __launch_bounds__(kMaxWideThreads)
+adj_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C) {
+    extern __shared__ float lds[];
+    __shared__ double red[16];
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const StepJob& J = jobs[find_job(jobs, njobs, g)];
+    const size_t f = (size_t)J.H * J.W * C;
+    const bool even = ((K - 1 - k) & 1) == 0;
+    const float* e = J.eps + 2 * k;
+    adj_tile_wide<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W, C,
+                          g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds, red);
+}
+
+// ----------------------------------------------------------------------------
 // Reductions over workgroup partials: grid (nrows, nq); each workgroup sums one
 // column of one row with strided per-thread sums followed by the block tree.
 __global__ void __launch_bounds__(kMaxThreads)
@@ -747,6 +1042,69 @@ hipError_t adj_launch_t(const float* c, const float* pin, float* pout, const flo
     return hipGetLastError();
 }
 
+template <int CP, int RT>
+hipError_t fwd_wide_launch(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, float dts,
+                           Tile t, hipStream_t s) {
+    constexpr int G = Wide<CP>::G;
+    const int tiles_x = (W + t.tx - 1) / t.tx;
+    const int nb = tile_count(H, W, t);
+    const size_t lds = tile_lds_bytes(C, RT, t, 1);
+    auto fn = fwd_step_wide_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx * G, t.ty), lds, s, cin, cout, eps, k, H, W, C, tiles_x, dts, dx2,
+                       dy2);
+    return hipGetLastError();
+}
+
+template <int CP, int RT>
+hipError_t adj_wide_launch(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
+                           int C, float dts, Tile t, double* part, hipStream_t s) {
+    constexpr int G = Wide<CP>::G;
+    const int tiles_x = (W + t.tx - 1) / t.tx;
+    const int nb = tile_count(H, W, t);
+    const size_t lds = tile_lds_bytes(C, RT, t, 2);
+    auto fn = adj_step_wide_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx * G, t.ty), lds, s, c, pin, pout, eps, k, H, W, C, tiles_x, dts, dx2,
+                       dy2, part);
+    return hipGetLastError();
+}
+
+template <int CP, int RT>
+hipError_t fwdb_wide_launch(const StepJob* jobs, int njobs, int total, int k, int C, Tile t, hipStream_t s) {
+    constexpr int G = Wide<CP>::G;
+    const size_t lds = tile_lds_bytes(C, RT, t, 1);
+    auto fn = fwd_step_batched_wide_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx * G, t.ty), lds, s, jobs, njobs, k, C);
+    return hipGetLastError();
+}
+
+template <int CP, int RT>
+hipError_t adjb_wide_launch(const StepJob* jobs, int njobs, int total, int k, int K, int C, Tile t,
+                            hipStream_t s) {
+    constexpr int G = Wide<CP>::G;
+    const size_t lds = tile_lds_bytes(C, RT, t, 2);
+    auto fn = adj_step_batched_wide_kernel<CP, RT>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx * G, t.ty), lds, s, jobs, njobs, k, K, C);
+    return hipGetLastError();
+}
+
 // Compile-time radii for the small-channel kernels (full unroll of the window);
 // wider channel counts and other radii use the runtime-radius kernel.
 template <int CP>
@@ -761,8 +1119,13 @@ hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, 
             case 5: return fwd_launch_t<CP, 5>(cin, cout, eps, k, H, W, C, R, dts, t, s);
             default: break;
         }
-    } else if constexpr (CP == 31) {
-        if (R == 2) return fwd_launch_t<CP, 2>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+    } else if constexpr (CP >= 16) {
+        switch (R) {
+            case 1: return fwd_wide_launch<CP, 1>(cin, cout, eps, k, H, W, C, dts, t, s);
+            case 2: return fwd_wide_launch<CP, 2>(cin, cout, eps, k, H, W, C, dts, t, s);
+            case 3: return fwd_wide_launch<CP, 3>(cin, cout, eps, k, H, W, C, dts, t, s);
+            default: break;
+        }
     }
     return fwd_launch_t<CP, 0>(cin, cout, eps, k, H, W, C, R, dts, t, s);
 }
@@ -779,8 +1142,13 @@ hipError_t adj_launch_r(const float* c, const float* pin, float* pout, const flo
             case 5: return adj_launch_t<CP, 5>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
             default: break;
         }
-    } else if constexpr (CP == 31) {
-        if (R == 2) return adj_launch_t<CP, 2>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+    } else if constexpr (CP >= 16) {
+        switch (R) {
+            case 1: return adj_wide_launch<CP, 1>(c, pin, pout, eps, k, H, W, C, dts, t, part, s);
+            case 2: return adj_wide_launch<CP, 2>(c, pin, pout, eps, k, H, W, C, dts, t, part, s);
+            case 3: return adj_wide_launch<CP, 3>(c, pin, pout, eps, k, H, W, C, dts, t, part, s);
+            default: break;
+        }
     }
     return adj_launch_t<CP, 0>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
 }
@@ -821,6 +1189,13 @@ hipError_t fwdb_launch_r(const StepJob* jobs, int njobs, int total, int k, int C
             case 5: return fwdb_launch_t<CP, 5>(jobs, njobs, total, k, C, R, t, s);
             default: break;
         }
+    } else if constexpr (CP >= 16) {
+        switch (R) {
+            case 1: return fwdb_wide_launch<CP, 1>(jobs, njobs, total, k, C, t, s);
+            case 2: return fwdb_wide_launch<CP, 2>(jobs, njobs, total, k, C, t, s);
+            case 3: return fwdb_wide_launch<CP, 3>(jobs, njobs, total, k, C, t, s);
+            default: break;
+        }
     }
     return fwdb_launch_t<CP, 0>(jobs, njobs, total, k, C, R, t, s);
 }
@@ -837,6 +1212,13 @@ hipError_t adjb_launch_r(const StepJob* jobs, int njobs, int total, int k, int K
             case 5: return adjb_launch_t<CP, 5>(jobs, njobs, total, k, K, C, R, t, s);
             default: break;
         }
+    } else if constexpr (CP >= 16) {
+        switch (R) {
+            case 1: return adjb_wide_launch<CP, 1>(jobs, njobs, total, k, K, C, t, s);
+            case 2: return adjb_wide_launch<CP, 2>(jobs, njobs, total, k, K, C, t, s);
+            case 3: return adjb_wide_launch<CP, 3>(jobs, njobs, total, k, K, C, t, s);
+            default: break;
+        }
     }
     return adjb_launch_t<CP, 0>(jobs, njobs, total, k, K, C, R, t, s);
 }
@@ -845,23 +1227,33 @@ hipError_t adjb_launch_r(const StepJob* jobs, int njobs, int total, int k, int K
 
 int tile_count(int H, int W, Tile t) { return ((W + t.tx - 1) / t.tx) * ((H + t.ty - 1) / t.ty); }
 
+// Lanes per pixel: G = CP/8 for the wide kernels (16 to 64 channels, radius 1 to 3), else 1.
+int wide_lanes(int C, int R) {
+    const int cp = padded_channels(C);
+    return (cp >= 16 && R >= 1 && R <= 3) ? (cp + 7) / 8 : 1;
+}
+
 size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     const int cp = padded_channels(C);
     if (cp < 0) return (size_t)-1;
+    const int G = wide_lanes(C, R);
+    if (G > 1) return (size_t)fields * G * wide_plane_floats(t.tx + 2 * R, t.ty + 2 * R) * sizeof(float);
     const int nv = (cp + 1 + 3) / 4;
     const int cs = cp == 1 ? 2 : 4 * (nv % 2 ? nv : nv + 1);
     return (size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)cs * sizeof(float);
 }
 
 bool tile_ok(int C, int R, Tile t, int fields) {
-    if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > kMaxThreads) return false;
-    if ((t.tx * t.ty) % kWave != 0) return false;
+    const int G = wide_lanes(C, R);
+    const int threads = t.tx * t.ty * G;
+    if (t.tx < 1 || t.ty < 1 || threads > (G > 1 ? kMaxWideThreads : kMaxThreads)) return false;
+    if (threads % kWave != 0) return false;
     return tile_lds_bytes(C, R, t, fields) <= kMaxLds;
 }
 
 // Waves one CU can hold for a tile, limited by LDS and by 8 waves per SIMD.
 static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
-    const int wpb = (t.tx * t.ty + kWave - 1) / kWave;
+    const int wpb = (t.tx * t.ty * wide_lanes(C, R) + kWave - 1) / kWave;
     const size_t lds = tile_lds_bytes(C, R, t, fields);
     const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
     return std::min(by_lds, 32 / wpb) * wpb;

@@ -63,6 +63,13 @@ FWD_CASES = [
     (2, 2, 1, 1, 3, 11),
     (50, 45, 3, 0, 3, 12),
     (9, 12, 64, 2, 2, 13),
+    # 16 to 64 channels at radius 1-3 run on the lanes-per-pixel kernels
+    (37, 45, 16, 1, 3, 14),
+    (70, 33, 31, 3, 3, 15),
+    (45, 70, 32, 2, 3, 16),
+    (20, 21, 17, 2, 3, 17),
+    (33, 40, 40, 1, 2, 18),
+    (1, 50, 31, 2, 2, 19),
 ]
 
 
@@ -86,13 +93,18 @@ def test_forward_and_adjoint_match_oracle(orc, H, W, C, R, K, seed):
         assert np.all(N(geps) == 0)
 
 
-def test_tile_shape_does_not_change_a_single_bit(orc):
-    H, W, C, R, K = 45, 77, 3, 2, 4
+@pytest.mark.parametrize("C,R,tiles", [
+    (3, 2, [(32, 8), (16, 16), (64, 4), (8, 8), (64, 1), (16, 4)]),
+    (31, 2, [(32, 8), (16, 16), (16, 8), (8, 8), (64, 4)]),
+    (64, 1, [(16, 8), (8, 8), (8, 16), (32, 4)]),
+])
+def test_tile_shape_does_not_change_a_single_bit(orc, C, R, tiles):
+    H, W, K = 45, 77, 4
     c0 = voronoi_image(H, W, C, 4, 0.05, 21)
     eps = rand_eps(K, 21)
     gK = T(np.random.default_rng(22).normal(size=(H, W, C)))
     ref = None
-    for tx, ty in [(32, 8), (16, 16), (64, 4), (8, 8), (64, 1), (16, 4)]:
+    for tx, ty in tiles:
         gp = A.Params(K=K, R=R, tile_x=tx, tile_y=ty)
         traj = A.abc_forward_dynamics(T(c0), T(eps), gp)
         g0, _ = A.abc_adjoint_dynamics(traj, T(eps), gp, gK)
@@ -103,8 +115,9 @@ def test_tile_shape_does_not_change_a_single_bit(orc):
             assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1]), (tx, ty)
 
 
-def test_constant_image_is_a_bitwise_fixed_point():
-    c0 = np.full((40, 36, 3), 0.4375, dtype=np.float32)
+@pytest.mark.parametrize("C", [3, 31])
+def test_constant_image_is_a_bitwise_fixed_point(C):
+    c0 = np.full((40, 36, C), 0.4375, dtype=np.float32)
     gp = A.Params(K=5, R=3)
     traj = N(A.abc_forward_dynamics(T(c0), T(rand_eps(5, 1)), gp))
     assert np.all(traj == 0.4375)
