@@ -155,11 +155,26 @@ __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__
     }
 }
 
+// Offset constants of a window of radius RT, written by the threads of a
+// workgroup: om[a][b] = 1 - Ax b^2 - Ay a^2 (Ax = eps_x/2 dx^2, Ay = eps_x/2
+// dy^2), in the operation order of the window loop.  (In the transposed step
+// the same table measured slower than recomputing, so it is used only here.)
+__device__ __forceinline__ void offset_table(float* om, int RT, float Ax, float Ay) {
+    const int D = 2 * RT + 1;
+    for (int i = threadIdx.x + threadIdx.y * blockDim.x; i < D * D; i += blockDim.x * blockDim.y) {
+        const int a = i / D - RT, b = i % D - RT;
+        om[i] = fmaf(-Ax, (float)(b * b), fmaf(-Ay, (float)(a * a), 1.0f));
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Forward step.
+// With a compile-time radius the offset constants om_ab come from a table in
+// LDS (filled once per workgroup with the same expression), which takes one
+// VALU operation per neighbour off the inner loop.
 template <int CP, int RT, bool BORDER>
 __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const float (&ci)[CP],
-                                           float (&acc)[CP], float Ax, float Ay, float ech) {
+                                           float (&acc)[CP], float Ax, float Ay, float ech, const float* omt) {
     constexpr int CS = Slot<CP>::CS;
     const int RR = RT > 0 ? RT : R;
 #pragma unroll
@@ -171,7 +186,7 @@ __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const
             if (a == 0 && b == 0) continue;
             float cj[CP], mj;
             load_px<CP>(row + b * CS, cj, mj);
-            const float om = fmaf(-Ax, (float)(b * b), om_row);
+            const float om = RT > 0 ? omt[(a + RR) * (2 * RR + 1) + b + RR] : fmaf(-Ax, (float)(b * b), om_row);
             float d[CP];
             float n2 = 0.0f;
 #pragma unroll
@@ -199,6 +214,8 @@ __device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* _
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
+    float* omt = lds + LW * LH * CS;
+    if constexpr (RT > 0) offset_table(omt, RT, exh * dx2, exh * dy2);
     stage_tile<CP>(lds, cin, H, W, C, x0, y0, R, LW, LH);
     __syncthreads();
     const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
@@ -209,9 +226,9 @@ __device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* _
 #pragma unroll
     for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
     if (interior)
-        fwd_window<CP, RT, false>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech);
+        fwd_window<CP, RT, false>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech, omt);
     else
-        fwd_window<CP, RT, true>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech);
+        fwd_window<CP, RT, true>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech, omt);
     float* o = cout + ((size_t)gy * W + gx) * C;
 #pragma unroll
     for (int ch = 0; ch < CP; ++ch)
@@ -1240,7 +1257,9 @@ size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     if (G > 1) return (size_t)fields * G * wide_plane_floats(t.tx + 2 * R, t.ty + 2 * R) * sizeof(float);
     const int nv = (cp + 1 + 3) / 4;
     const int cs = cp == 1 ? 2 : 4 * (nv % 2 ? nv : nv + 1);
-    return (size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)cs * sizeof(float);
+    // plus the forward step's offset-constant table ((2R+1)^2 floats)
+    return ((size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)cs +
+            (size_t)(2 * R + 1) * (2 * R + 1)) * sizeof(float);
 }
 
 bool tile_ok(int C, int R, Tile t, int fields) {
