@@ -847,6 +847,11 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
 // Batched solve: lockstep rounds over many images of different sizes.
 namespace {
 
+// Where an image of a batched solve stands: it needs a gradient (objective
+// and adjoint sweep at its accepted controls), the next Armijo trial, its
+// multiplier update, or nothing more.
+constexpr int kPhGrad = 0, kPhSearch = 1, kPhPd = 2, kPhDone = 3;
+
 struct BImg {
     // geometry
     int H, W;
@@ -872,28 +877,40 @@ struct BImg {
     double sigma = 0, phi0 = 0, phi_acc = 0, accepted = 0, tau = 0, L_prev = NAN;
     int base = 0, cand = 1, trial = 2;
     int evals = 0, branch = 0;  // 0: first trial, 1: expanding, 2: backtracking
-    bool have = false, outer_done = false, inner_done = false, ls_done = false, phi_seen = false;
+    bool have = false, outer_done = false, ls_done = false, phi_seen = false;
+    int phase = 0;  // kPhGrad, kPhSearch, kPhPd or kPhDone
+    int j = 0;      // multiplier iteration in progress
+    int it = 0;     // gradient evaluations within it
     abc_stats S;
     abc_stats E;
     double finish_ms = 0;
 };
 
-struct BatchWs {
+// Job tables and reduction outputs of one launch stream.
+struct BatchLane {
     abc::StepJob* step_jobs;
     abc::PixJob* pix_jobs;
     abc::RedJob* red_jobs;
+    float* q_all;  // n x kPdQuantities
+    hipStream_t st;
+};
+
+struct BatchWs {
+    BatchLane a, b;    // a: gradients and multiplier updates, b: Armijo trials
     float* eps_all;    // n x 3 x K x 2
     double* g_all;     // n x K x 2
-    float* q_all;      // n x kPdQuantities
 };
 
 void carve_batch(Carve& cv, int n, int K, BatchWs& b) {
-    b.step_jobs = cv.take<abc::StepJob>(n);
-    b.pix_jobs = cv.take<abc::PixJob>(n);
-    b.red_jobs = cv.take<abc::RedJob>(n);
+    for (BatchLane* l : {&b.a, &b.b}) {
+        l->step_jobs = cv.take<abc::StepJob>(n);
+        l->pix_jobs = cv.take<abc::PixJob>(n);
+        l->red_jobs = cv.take<abc::RedJob>(n);
+        l->q_all = cv.take<float>((size_t)n * abc::kPdQuantities);
+        l->st = nullptr;
+    }
     b.eps_all = cv.take<float>((size_t)n * 3 * K * 2);
     b.g_all = cv.take<double>((size_t)n * K * 2);
-    b.q_all = cv.take<float>((size_t)n * abc::kPdQuantities);
 }
 
 void carve_bimg(Carve& cv, BImg& m, int K, int C) {
@@ -919,22 +936,35 @@ struct Batch {
     BatchWs w;
     std::vector<float> eps_host;  // mirror of eps_all
     GraphCache graphs;
+    hipStream_t own_b = nullptr;  // lane b's stream, created for the call
+
+    Batch() = default;
+    Batch(const Batch&) = delete;
+    Batch& operator=(const Batch&) = delete;
+    ~Batch() {
+        if (own_b) {
+            (void)hipStreamSynchronize(own_b);
+            (void)hipStreamDestroy(own_b);
+        }
+    }
 
     float* eps_dev(int i, int slot) const { return w.eps_all + ((size_t)i * 3 + slot) * K * 2; }
 
     int upload_eps(const std::vector<int>& who, const std::vector<int>& slot,
-                   const std::vector<const std::vector<double>*>& vals) {
+                   const std::vector<const std::vector<double>*>& vals, hipStream_t s) {
         for (size_t j = 0; j < who.size(); ++j) {
             float* h = eps_host.data() + ((size_t)who[j] * 3 + slot[j]) * K * 2;
             for (int q = 0; q < 2 * K; ++q) h[q] = (float)(*vals[j])[q];
         }
+        // the whole mirror: entries of images not listed are rewritten with the values they hold
         ABC_HIP(hipMemcpyAsync(w.eps_all, eps_host.data(), eps_host.size() * sizeof(float), hipMemcpyHostToDevice,
-                               st));
+                               s));
         return ABC_OK;
     }
 
     // K forward steps of every listed image into its trajectory `slot[j]`.
-    int forward(const std::vector<int>& who, const std::vector<int>& slot) {
+    int forward(const std::vector<int>& who, const std::vector<int>& slot, BatchLane& L) {
+        hipStream_t st = L.st;
         if (who.empty()) return ABC_OK;
         std::vector<abc::StepJob> jobs(who.size());
         int total = 0;
@@ -954,7 +984,7 @@ struct Batch {
             J.dy2 = 1.0f / ((float)m.H * (float)m.H);
             total += m.tiles_f;
         }
-        ABC_HIP(hipMemcpyAsync(w.step_jobs, jobs.data(), jobs.size() * sizeof(abc::StepJob), hipMemcpyHostToDevice,
+        ABC_HIP(hipMemcpyAsync(L.step_jobs, jobs.data(), jobs.size() * sizeof(abc::StepJob), hipMemcpyHostToDevice,
                                st));
         if (p->R == 0) {
             for (int k = 0; k < K; ++k)
@@ -967,17 +997,19 @@ struct Batch {
             return ABC_OK;
         }
         const int nj = (int)jobs.size();
-        return graphs.run(use_graphs, {0, total, nj, 0}, st, [&](hipStream_t s2) -> int {
+        // a recorded sweep reads the lane's own job table, so the lane is part of the key
+        const long lane = &L == &w.b ? 1 : 0;
+        return graphs.run(use_graphs, {0, total, nj, lane}, st, [&](hipStream_t s2) -> int {
             for (int k = 0; k < K; ++k)
-                ABC_HIP(abc::launch_forward_step_batched(w.step_jobs, nj, total, k, C, p->R, tf, s2));
+                ABC_HIP(abc::launch_forward_step_batched(L.step_jobs, nj, total, k, C, p->R, tf, s2));
             return ABC_OK;
         });
     }
 
-    // Terminal condition (into pa) and/or objective of trajectory `slot[j]`; fills phi[j].
-    int objective(const std::vector<int>& who, const std::vector<int>& slot, bool want_pK, std::vector<double>& phi) {
-        phi.assign(who.size(), 0.0);
+    // Terminal condition (into pa) and/or objective of trajectory `slot[j]`, queued on the lane.
+    int objective_launch(const std::vector<int>& who, const std::vector<int>& slot, bool want_pK, BatchLane& L) {
         if (who.empty()) return ABC_OK;
+        hipStream_t st = L.st;
         std::vector<abc::PixJob> jobs(who.size());
         std::vector<abc::RedJob> reds(who.size());
         int total = 0;
@@ -1000,24 +1032,39 @@ struct Batch {
             abc::RedJob& Rj = reds[j];
             std::memset(&Rj, 0, sizeof(Rj));
             Rj.part_f = m.pdpart;
-            Rj.out_f = w.q_all + (size_t)j * abc::kPdQuantities;
+            Rj.out_f = L.q_all + (size_t)j * abc::kPdQuantities;
             Rj.rows = 1;
             Rj.nblk = m.pdb;
         }
-        ABC_HIP(hipMemcpyAsync(w.pix_jobs, jobs.data(), jobs.size() * sizeof(abc::PixJob), hipMemcpyHostToDevice, st));
-        ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice, st));
-        ABC_HIP(abc::launch_terminal_batched(w.pix_jobs, (int)jobs.size(), total, C, pq.rho, pq.alpha, st));
-        ABC_HIP(abc::launch_reduce_jobs(w.red_jobs, (int)reds.size(), abc::kTermQuantities, st));
+        ABC_HIP(hipMemcpyAsync(L.pix_jobs, jobs.data(), jobs.size() * sizeof(abc::PixJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(hipMemcpyAsync(L.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(abc::launch_terminal_batched(L.pix_jobs, (int)jobs.size(), total, C, pq.rho, pq.alpha, st));
+        ABC_HIP(abc::launch_reduce_jobs(L.red_jobs, (int)reds.size(), abc::kTermQuantities, st));
+        return ABC_OK;
+    }
+
+    // Waits for the lane and reads the objectives queued by objective_launch into phi.
+    int objective_read(const std::vector<int>& who, BatchLane& L, std::vector<double>& phi) {
+        phi.assign(who.size(), 0.0);
+        if (who.empty()) return ABC_OK;
         std::vector<float> q(who.size() * abc::kPdQuantities);
-        ABC_HIP(hipMemcpyAsync(q.data(), w.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, st));
-        ABC_HIP(hipStreamSynchronize(st));
+        ABC_HIP(hipMemcpyAsync(q.data(), L.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, L.st));
+        ABC_HIP(hipStreamSynchronize(L.st));
         for (size_t j = 0; j < who.size(); ++j) phi[j] = im[who[j]].area * (double)q[j * abc::kPdQuantities];
         return ABC_OK;
+    }
+
+    int objective(const std::vector<int>& who, const std::vector<int>& slot, bool want_pK, std::vector<double>& phi,
+                  BatchLane& L) {
+        int rc = objective_launch(who, slot, want_pK, L);
+        return rc ? rc : objective_read(who, L, phi);
     }
 
     // Adjoint sweep from p^K (in pa) over each image's base trajectory; fills G.
     int adjoint(const std::vector<int>& who) {
         if (who.empty()) return ABC_OK;
+        BatchLane& L = w.a;
+        hipStream_t st = L.st;
         std::vector<abc::StepJob> jobs(who.size());
         std::vector<abc::RedJob> reds(who.size());
         int total = 0;
@@ -1047,15 +1094,15 @@ struct Batch {
             Rj.nblk = m.tiles_a;
         }
         if (p->R > 0) {
-            ABC_HIP(hipMemcpyAsync(w.step_jobs, jobs.data(), jobs.size() * sizeof(abc::StepJob),
+            ABC_HIP(hipMemcpyAsync(L.step_jobs, jobs.data(), jobs.size() * sizeof(abc::StepJob),
                                    hipMemcpyHostToDevice, st));
-            ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice,
+            ABC_HIP(hipMemcpyAsync(L.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice,
                                    st));
             const int nj = (int)jobs.size();
             int r2 = graphs.run(use_graphs, {1, total, nj, 0}, st, [&](hipStream_t s2) -> int {
                 for (int k = K - 1; k >= 0; --k)
-                    ABC_HIP(abc::launch_adjoint_step_batched(w.step_jobs, nj, total, k, K, C, p->R, ta, s2));
-                ABC_HIP(abc::launch_reduce_jobs_f64(w.red_jobs, nj, K, 2, s2));
+                    ABC_HIP(abc::launch_adjoint_step_batched(L.step_jobs, nj, total, k, K, C, p->R, ta, s2));
+                ABC_HIP(abc::launch_reduce_jobs_f64(L.red_jobs, nj, K, 2, s2));
                 return ABC_OK;
             });
             if (r2) return r2;
@@ -1073,6 +1120,8 @@ struct Batch {
     // Shrinkage / multiplier update of each listed image's final field; energies into E.
     int pd(const std::vector<int>& who, int update_mu, bool want) {
         if (who.empty()) return ABC_OK;
+        BatchLane& L = w.a;
+        hipStream_t st = L.st;
         std::vector<abc::PixJob> jobs(who.size());
         std::vector<abc::RedJob> reds(who.size());
         int total = 0;
@@ -1095,17 +1144,17 @@ struct Batch {
             abc::RedJob& Rj = reds[j];
             std::memset(&Rj, 0, sizeof(Rj));
             Rj.part_f = m.pdpart;
-            Rj.out_f = w.q_all + (size_t)j * abc::kPdQuantities;
+            Rj.out_f = L.q_all + (size_t)j * abc::kPdQuantities;
             Rj.rows = 1;
             Rj.nblk = m.pdb;
         }
-        ABC_HIP(hipMemcpyAsync(w.pix_jobs, jobs.data(), jobs.size() * sizeof(abc::PixJob), hipMemcpyHostToDevice, st));
-        ABC_HIP(hipMemcpyAsync(w.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice, st));
-        ABC_HIP(abc::launch_pd_step_batched(w.pix_jobs, (int)jobs.size(), total, update_mu, C, p->rho, p->gamma, st));
+        ABC_HIP(hipMemcpyAsync(L.pix_jobs, jobs.data(), jobs.size() * sizeof(abc::PixJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(hipMemcpyAsync(L.red_jobs, reds.data(), reds.size() * sizeof(abc::RedJob), hipMemcpyHostToDevice, st));
+        ABC_HIP(abc::launch_pd_step_batched(L.pix_jobs, (int)jobs.size(), total, update_mu, C, p->rho, p->gamma, st));
         if (!want) return ABC_OK;
-        ABC_HIP(abc::launch_reduce_jobs(w.red_jobs, (int)reds.size(), abc::kPdQuantities, st));
+        ABC_HIP(abc::launch_reduce_jobs(L.red_jobs, (int)reds.size(), abc::kPdQuantities, st));
         std::vector<float> q(who.size() * abc::kPdQuantities);
-        ABC_HIP(hipMemcpyAsync(q.data(), w.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        ABC_HIP(hipMemcpyAsync(q.data(), L.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, st));
         ABC_HIP(hipStreamSynchronize(st));
         for (size_t j = 0; j < who.size(); ++j) {
             Shape sh{im[who[j]].H, im[who[j]].W, C};
@@ -1185,6 +1234,9 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
     const int K = p->K;
     Carve cv(ws);
     carve_batch(cv, n, K, B.w);
+    B.w.a.st = B.st;
+    ABC_HIP(hipStreamCreateWithFlags(&B.own_b, hipStreamNonBlocking));
+    B.w.b.st = B.own_b;
     B.im.resize(n);
     B.eps_host.assign((size_t)n * 3 * K * 2, 0.0f);
     const auto t_start = std::chrono::steady_clock::now();
@@ -1240,31 +1292,56 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
         std::vector<int> s0(n, 0);
         std::vector<const std::vector<double>*> vals(n);
         for (int i = 0; i < n; ++i) vals[i] = &B.im[i].e_base;
-        if ((rc = B.upload_eps(all, s0, vals))) return rc;
-        if ((rc = B.forward(all, s0))) return rc;
+        if ((rc = B.upload_eps(all, s0, vals, B.st))) return rc;
+        if ((rc = B.forward(all, s0, B.w.a))) return rc;
         if (!B.quad && (rc = B.pd(all, 0, false))) return rc;
     }
     const int M = B.quad ? std::min(p->max_outer, 1) : p->max_outer;
     const int P = p->max_inner;
     std::vector<double> phi;
-    for (int j = 0; j < M; ++j) {
-        std::vector<int> outer;
+    // Each image runs its own loops (Alg. 2 around Alg. 1).  A round gives
+    // every image one step of its own: a gradient, one Armijo trial, or a
+    // multiplier update; the images in each phase share one launch per Euler
+    // step, and the trial sweeps run on a second stream while the gradient
+    // sweeps run on the caller's.  Images never wait for each other at a
+    // multiplier iteration, so a small image finishes early.  Every use of an
+    // image's buffers on one stream follows a host wait on the other.
+    auto end_inner = [&](BImg& m) { m.phase = kPhPd; };
+    for (int i = 0; i < n; ++i) B.im[i].phase = M > 0 ? kPhGrad : kPhDone;
+    for (int i = 0; i < n; ++i)
+        if (M > 0 && P == 0) end_inner(B.im[i]);
+    auto in_phase = [&](int ph) {
+        std::vector<int> v;
         for (int i = 0; i < n; ++i)
-            if (!B.im[i].outer_done) {
-                outer.push_back(i);
-                B.im[i].inner_done = false;
+            if (B.im[i].phase == ph) v.push_back(i);
+        return v;
+    };
+    std::vector<double> phi_s;
+    for (;;) {
+        std::vector<int> act = in_phase(kPhGrad);
+        std::vector<int> search = in_phase(kPhSearch);
+        std::vector<int> pdset = in_phase(kPhPd);
+        if (act.empty() && search.empty() && pdset.empty()) break;
+        // queue one Armijo trial for every image in a search (lane b)
+        if (!search.empty()) {
+            std::vector<int> tslot;
+            std::vector<const std::vector<double>*> vals;
+            for (int i : search) {
+                BImg& m = B.im[i];
+                B.project(m, m.tau, m.e_try);
+                tslot.push_back(m.trial);
+                vals.push_back(&m.e_try);
             }
-        if (outer.empty()) break;
-        for (int it = 0; it < P; ++it) {
-            std::vector<int> act;
-            for (int i : outer)
-                if (!B.im[i].inner_done) act.push_back(i);
-            if (act.empty()) break;
+            if ((rc = B.upload_eps(search, tslot, vals, B.w.b.st))) return rc;
+            if ((rc = B.forward(search, tslot, B.w.b))) return rc;
+            if ((rc = B.objective_launch(search, tslot, false, B.w.b))) return rc;
+        }
+        // gradients (lane a)
+        if (!act.empty()) {
             std::vector<int> bslot;
             for (int i : act) bslot.push_back(B.im[i].base);
-            if ((rc = B.objective(act, bslot, true, phi))) return rc;
+            if ((rc = B.objective(act, bslot, true, phi, B.w.a))) return rc;
             if ((rc = B.adjoint(act))) return rc;
-            std::vector<int> search;
             for (size_t a = 0; a < act.size(); ++a) {
                 BImg& m = B.im[act[a]];
                 m.phi0 = phi[a];
@@ -1274,10 +1351,11 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
                 }
                 m.S.phi_last = m.phi0;
                 m.S.inner_iters++;
+                m.it++;
                 bool all_zero = true;
                 for (double g : m.G) all_zero = all_zero && (g == 0.0);
                 if (all_zero) {
-                    m.inner_done = true;
+                    end_inner(m);
                     continue;
                 }
                 m.tau = m.sigma;
@@ -1287,103 +1365,100 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
                 m.ls_done = false;
                 m.accepted = 0.0;
                 m.phi_acc = m.phi0;
-                search.push_back(act[a]);
+                m.phase = kPhSearch;
             }
-            // Armijo rounds: every image that needs a trial gets one per round
-            while (!search.empty()) {
-                std::vector<int> tslot;
-                std::vector<const std::vector<double>*> vals;
-                for (int i : search) {
-                    BImg& m = B.im[i];
-                    B.project(m, m.tau, m.e_try);
-                    tslot.push_back(m.trial);
-                    vals.push_back(&m.e_try);
-                }
-                if ((rc = B.upload_eps(search, tslot, vals))) return rc;
-                if ((rc = B.forward(search, tslot))) return rc;
-                if ((rc = B.objective(search, tslot, false, phi))) return rc;
-                std::vector<int> next;
-                for (size_t a = 0; a < search.size(); ++a) {
-                    BImg& m = B.im[search[a]];
-                    m.evals++;
-                    double ip = 0.0;
-                    for (int q = 0; q < 2 * K; ++q) ip += m.G[q] * (m.e_try[q] - m.e_base[q]);
-                    ip *= (double)p->dt;
-                    const bool ok = phi[a] <= m.phi0 + p->armijo_c * ip;
-                    auto keep = [&]() {
-                        std::swap(m.cand, m.trial);
-                        m.e_cand = m.e_try;
-                        m.accepted = m.tau;
-                        m.phi_acc = phi[a];
-                        m.have = true;
-                    };
-                    bool more = false;
-                    if (m.branch == 0) {
-                        if (ok) {
-                            keep();
-                            m.branch = 1;
-                        } else {
-                            m.branch = 2;
-                        }
-                    } else if (m.branch == 1) {
-                        if (ok) keep();
-                        else m.ls_done = true;
+        }
+        // Armijo decisions of the trials
+        if (!search.empty()) {
+            if ((rc = B.objective_read(search, B.w.b, phi_s))) return rc;
+            for (size_t a = 0; a < search.size(); ++a) {
+                BImg& m = B.im[search[a]];
+                m.evals++;
+                double ip = 0.0;
+                for (int q = 0; q < 2 * K; ++q) ip += m.G[q] * (m.e_try[q] - m.e_base[q]);
+                ip *= (double)p->dt;
+                const bool ok = phi_s[a] <= m.phi0 + p->armijo_c * ip;
+                auto keep = [&]() {
+                    std::swap(m.cand, m.trial);
+                    m.e_cand = m.e_try;
+                    m.accepted = m.tau;
+                    m.phi_acc = phi_s[a];
+                    m.have = true;
+                };
+                bool more = false;
+                if (m.branch == 0) {
+                    if (ok) {
+                        keep();
+                        m.branch = 1;
                     } else {
-                        if (ok) {
-                            keep();
-                            m.ls_done = true;
-                        }
+                        m.branch = 2;
                     }
-                    if (!m.ls_done && m.evals < p->max_ls) {
-                        if (m.branch == 1) {
-                            B.project(m, m.tau / p->armijo_b, m.e_next);
-                            if (m.e_next != m.e_cand) {
-                                m.tau /= p->armijo_b;
-                                more = true;
-                            }
-                        } else {
-                            m.tau *= p->armijo_b;
+                } else if (m.branch == 1) {
+                    if (ok) keep();
+                    else m.ls_done = true;
+                } else {
+                    if (ok) {
+                        keep();
+                        m.ls_done = true;
+                    }
+                }
+                if (!m.ls_done && m.evals < p->max_ls) {
+                    if (m.branch == 1) {
+                        B.project(m, m.tau / p->armijo_b, m.e_next);
+                        if (m.e_next != m.e_cand) {
+                            m.tau /= p->armijo_b;
                             more = true;
                         }
-                    }
-                    if (more) {
-                        next.push_back(search[a]);
                     } else {
-                        m.S.ls_evals += m.evals;
-                        if (!m.have) {
-                            m.inner_done = true;
-                        } else {
-                            m.sigma = m.accepted;
-                            m.e_base = m.e_cand;
-                            std::swap(m.base, m.cand);
-                            if (p->tol_dal > 0.0 && std::fabs(m.phi_acc - m.phi0) < p->tol_dal * std::fabs(m.phi0))
-                                m.inner_done = true;
-                        }
+                        m.tau *= p->armijo_b;
+                        more = true;
                     }
                 }
-                search.swap(next);
+                if (more) continue;
+                m.S.ls_evals += m.evals;
+                if (!m.have) {
+                    end_inner(m);
+                    continue;
+                }
+                m.sigma = m.accepted;
+                m.e_base = m.e_cand;
+                std::swap(m.base, m.cand);
+                if ((p->tol_dal > 0.0 && std::fabs(m.phi_acc - m.phi0) < p->tol_dal * std::fabs(m.phi0)) ||
+                    m.it >= P)
+                    end_inner(m);
+                else
+                    m.phase = kPhGrad;
             }
         }
+        // multiplier updates
+        pdset = in_phase(kPhPd);
+        if (pdset.empty()) continue;
         if (B.quad) {
-            for (int i : outer) {
+            for (int i : pdset) {
                 B.im[i].S.outer_iters = 1;
                 B.im[i].outer_done = true;
+                B.im[i].phase = kPhDone;
                 B.im[i].finish_ms = now_ms();
             }
-            break;
+            continue;
         }
-        if ((rc = B.pd(outer, 1, true))) return rc;
+        if ((rc = B.pd(pdset, 1, true))) return rc;
         const double t_now = now_ms();
-        for (int i : outer) {
+        for (int i : pdset) {
             BImg& m = B.im[i];
-            m.S.outer_iters = j + 1;
+            m.S.outer_iters = m.j + 1;
             m.S.gap_rel = std::isnan(m.L_prev) ? NAN : std::fabs(m.E.L - m.L_prev) / std::fabs(m.L_prev);
             m.L_prev = m.E.L;
             const bool gap_ok = p->tol_gap > 0.0 && !std::isnan(m.S.gap_rel) && m.S.gap_rel < p->tol_gap;
             if ((p->tol_alm > 0.0 && m.E.r_rel < p->tol_alm) || (p->stop_K > 0.0 && m.E.K <= p->stop_K) || gap_ok ||
-                j + 1 == M) {
+                m.j + 1 == M) {
                 m.outer_done = true;
+                m.phase = kPhDone;
                 m.finish_ms = t_now;
+            } else {
+                m.j++;
+                m.it = 0;
+                m.phase = P > 0 ? kPhGrad : kPhPd;
             }
         }
     }
@@ -1429,7 +1504,7 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
                 ABC_HIP(hipMemsetAsync(m.v, 0, 2 * m.f * sizeof(float), B.st));
                 ABC_HIP(hipMemsetAsync(m.mu, 0, 2 * m.f * sizeof(float), B.st));
             }
-            if ((rc = B.objective(final_e, bslot, false, phi))) return rc;
+            if ((rc = B.objective(final_e, bslot, false, phi, B.w.a))) return rc;
             for (size_t a = 0; a < final_e.size(); ++a) {
                 BImg& m = B.im[final_e[a]];
                 m.E.L = m.E.Ltilde = phi[a];

@@ -11,6 +11,7 @@ call.
 """
 from __future__ import annotations
 
+import os
 import time
 from dataclasses import dataclass
 
@@ -42,6 +43,10 @@ def make_dataset(n: int, size: int, seed0: int, params: B.Params, batch: int = 6
     return torch.stack(xs), torch.stack(mus), torch.stack(epss)
 
 
+# Weights trained by train_warmstart.py for K = 50 (provenance in wsnet_k50.json).
+TRAINED_K50 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wsnet_k50.npy")
+
+
 @dataclass
 class TrainLog:
     losses: list
@@ -57,6 +62,17 @@ class WarmStart:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.t = 0
+
+    @classmethod
+    def load(cls, path: str, K: int, box: B.Params, device="cuda"):
+        """A network with the FP32 weights stored at path (a flat .npy)."""
+        import torch
+        ws = cls(K, box, device=device)
+        w = np.load(path, allow_pickle=False)
+        if w.shape != tuple(ws.params.shape):
+            raise ValueError(f"{path}: {w.shape[0]} parameters, the network for K={K} has {ws.params.numel()}")
+        ws.params.copy_(torch.as_tensor(w, device=device))
+        return ws
 
     def predict(self, x):
         """(mu0 B x H x W x 2 x 3, eps0 B x K x 2) for images x (B x H x W x 3)."""
