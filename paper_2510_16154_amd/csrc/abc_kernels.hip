@@ -277,7 +277,7 @@ fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 
 // ----------------------------------------------------------------------------
 // Adjoint step.  With q = (phi'/20)(D . dp), dp = p_j - p_i:
-//   acc += phi dp + 20 eps_c q D,
+//   acc += phi dp,  accq += q D   (the step adds acc + 20 eps_c accq),
 //   sx  += d^2 q,  sc += |D|^2 q.
 // The control gradient uses the symmetric-window identity
 //   sum_i sum_j phi' w (p_i . D_ij) = -1/2 sum_i sum_j phi' w (D_ij . (p_j - p_i))
@@ -289,7 +289,7 @@ fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 template <int CP, int RT, bool BORDER>
 __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int LW, int R,
                                            const float (&ci)[CP], const float (&pi)[CP], float (&acc)[CP],
-                                           float& sx, float& sc, float Ax, float Ay, float ech, float ec20,
+                                           float (&accq)[CP], float& sx, float& sc, float Ax, float Ay, float ech,
                                            float dx2, float dy2) {
     constexpr int CS = Slot<CP>::CS;
     const int RR = RT > 0 ? RT : R;
@@ -315,10 +315,10 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
                 n2 = fmaf(d[ch], d[ch], n2);
             }
             const float t = clamp01(fmaf(-ech, n2, om));
-            const float t2 = t * t;
-            const float t3 = t2 * t;
-            float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
-            float u = (t - 1.0f) * t3;
+            const float t3 = (t * t) * t;
+            const float t4 = t3 * t;
+            float w = fmaf(-4.0f, t, 5.0f) * t4;
+            float u = t4 - t3;
             if (BORDER) {
                 w *= mj;
                 u *= mj;
@@ -331,9 +331,11 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
                 ddp = fmaf(d[ch], dp[ch], ddp);
             }
             const float q = u * ddp;
-            const float coef = ec20 * q;
 #pragma unroll
-            for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(coef, d[ch], fmaf(w, dp[ch], acc[ch]));
+            for (int ch = 0; ch < CP; ++ch) {
+                acc[ch] = fmaf(w, dp[ch], acc[ch]);
+                accq[ch] = fmaf(q, d[ch], accq[ch]);
+            }
             sx = fmaf(d2, q, sx);
             sc = fmaf(n2, q, sc);
         }
@@ -364,21 +366,22 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
         const int off = ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
         const float* mc = ldc + off;
         const float* mp = ldp + off;
-        float ci[CP], pi[CP], acc[CP], mi;
+        float ci[CP], pi[CP], acc[CP], accq[CP], mi;
         load_px<CP>(mc, ci, mi);
         load_px<CP>(mp, pi, mi);
 #pragma unroll
-        for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
+        for (int ch = 0; ch < CP; ++ch) acc[ch] = accq[ch] = 0.0f;
         if (interior)
-            adj_window<CP, RT, false>(mc, mp, LW, R, ci, pi, acc, sx, sc, exh * dx2, exh * dy2, ech, 20.0f * ec,
-                                      dx2, dy2);
+            adj_window<CP, RT, false>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
+                                      dy2);
         else
-            adj_window<CP, RT, true>(mc, mp, LW, R, ci, pi, acc, sx, sc, exh * dx2, exh * dy2, ech, 20.0f * ec,
-                                     dx2, dy2);
+            adj_window<CP, RT, true>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
+                                     dy2);
+        const float ec20 = 20.0f * ec;
         float* o = pout + ((size_t)gy * W + gx) * C;
 #pragma unroll
         for (int ch = 0; ch < CP; ++ch)
-            if (ch < C) o[ch] = fmaf(dts, acc[ch], pi[ch]);
+            if (ch < C) o[ch] = fmaf(dts, fmaf(ec20, accq[ch], acc[ch]), pi[ch]);
     }
     const double bx = block_sum_f64((double)sx, red);
     const double bc = block_sum_f64((double)sc, red);
