@@ -51,6 +51,26 @@ struct Carve {
     }
 };
 
+// Pinned host array owned for the duration of a call; copies from it are
+// queued on `st`, which is drained before the array is freed.
+template <class T>
+struct PinnedHost {
+    T* ptr = nullptr;
+    hipStream_t st = nullptr;
+    PinnedHost() = default;
+    PinnedHost(const PinnedHost&) = delete;
+    PinnedHost& operator=(const PinnedHost&) = delete;
+    ~PinnedHost() {
+        if (!ptr) return;
+        (void)hipStreamSynchronize(st);
+        (void)hipHostFree(ptr);
+    }
+    int alloc(size_t n) {
+        ABC_HIP(hipHostMalloc((void**)&ptr, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault));
+        return ABC_OK;
+    }
+};
+
 // Captured HIP graphs of sweep launches, keyed by the caller.  A sweep is
 // recorded once on a private capture stream and replayed on the caller's
 // stream; kernels read controls, job tables and buffers through pointers
@@ -575,11 +595,15 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     if (!mu || quad) ABC_HIP(hipMemsetAsync(mm, 0, 2 * f * sizeof(float), st));
     if (quad) ABC_HIP(hipMemsetAsync(vv, 0, 2 * f * sizeof(float), st));
 
+    // Controls go up through a pinned staging array: the copy is queued without
+    // a host wait, and every later upload comes after a host wait (the
+    // objective read of the trial), so the array is free again by then.
+    PinnedHost<float> stage;
+    stage.st = st;
+    if ((rc = stage.alloc((size_t)K * 2))) return rc;
     auto upload = [&](const std::vector<double>& e, float* dev) -> int {
-        std::vector<float> h(e.size());
-        for (size_t i = 0; i < e.size(); ++i) h[i] = (float)e[i];
-        ABC_HIP(hipMemcpyAsync(dev, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, st));
-        ABC_HIP(hipStreamSynchronize(st));
+        for (size_t i = 0; i < e.size(); ++i) stage.ptr[i] = (float)e[i];
+        ABC_HIP(hipMemcpyAsync(dev, stage.ptr, e.size() * sizeof(float), hipMemcpyHostToDevice, st));
         return ABC_OK;
     };
     auto project = [&](const std::vector<double>& G, double tau, std::vector<double>& out) {
@@ -656,13 +680,13 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     for (int j = 0; j < n_outer; ++j) {
         for (int it = 0; it < P; ++it) {
             const size_t slot = (size_t)j * P + it;
+            // terminal condition and objective at the accepted controls, queued; read
+            // together with the control gradient after the adjoint sweep
             double phi0 = 0.0;
-            if ((rc = objective(w.traj[base] + traj_stride, c0, vv, mm, w.adj.pa, s, &pq, w.pd, st, &phi0))) return rc;
-            if (!phi_seen) {
-                S.phi_first = phi0;
-                phi_seen = true;
-            }
-            S.phi_last = phi0;
+            ABC_HIP(abc::launch_terminal(w.traj[base] + traj_stride, c0, vv, mm, H, W, C, pq.rho, pq.alpha,
+                                         (float)s.area(), w.adj.pa, w.pd.part, st));
+            ABC_HIP(abc::launch_reduce_rows(w.pd.part, 1, abc::pd_blocks(H, W), abc::kTermQuantities, w.pd.out, 1.0f,
+                                            st));
             // adjoint sweep from p^K = dL~/dc, then the control gradient
             float* cur = w.adj.pa;
             float* spare = w.adj.pb;
@@ -682,10 +706,20 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                 if (rc) return rc;
                 G.resize((size_t)K * 2);
                 ABC_HIP(hipMemcpyAsync(G.data(), w.G, G.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-                ABC_HIP(hipStreamSynchronize(st));
             } else {
                 G.assign((size_t)K * 2, 0.0);
             }
+            {
+                float h[abc::kTermQuantities];
+                ABC_HIP(hipMemcpyAsync(h, w.pd.out, sizeof(h), hipMemcpyDeviceToHost, st));
+                ABC_HIP(hipStreamSynchronize(st));
+                phi0 = s.area() * (double)h[0];
+            }
+            if (!phi_seen) {
+                S.phi_first = phi0;
+                phi_seen = true;
+            }
+            S.phi_last = phi0;
             S.inner_iters++;
             if (grad_out) std::copy(G.begin(), G.end(), grad_out + slot * 2 * K);
             if (phi_out) phi_out[kStepLog * slot] = phi0;
