@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "2e15fed72a568b66cc049d0513c843dcb7a444a0d1ebfa93f73ef7eb7e678d6c",
-    "adj_step_kernel<3,5>": 11.02e6,
+    "kernel_sha256": "963ee6d0898f54d39f86d8315e026a0422a5dc4d427a47a480107fe9abbf4f00",
+    "adj_step_kernel<3,5>": 11.01e6,
     "adj_step_wide_kernel<31,2>": 2078.93e6,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")
