@@ -73,12 +73,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
                     help="repeat the oracle's full forward+adjoint sweep until this much time has passed")
-    ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512", "hyper2048", "warmstart1024"],
+    ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512", "hyper2048", "warmstart1024", "converge512"],
                     help="voronoi512: the headline line (default); batch64: the batched form; segment512: "
                          "watershed labels and IRV/IRC/VS scores of a solved 512 x 512 image; hyper2048: the "
                          "differentiable form on 2048 x 2048 x 31 (checkpointed forward + backward); warmstart1024: "
                          "time to a converged solve of held-out 1024 x 1024 images, plain against the packaged "
-                         "learned warm start")
+                         "learned warm start; converge512: time to solve the 512 x 512 image to ALM residual 1e-5")
     ap.add_argument("--images", type=int, default=4, help="warmstart1024: held-out images to solve")
     ap.add_argument("--no-graphs", action="store_true",
                     help="batch64: launch every sweep step directly instead of replaying captured graphs")
@@ -111,6 +111,8 @@ def main() -> int:
         return bench_hyper(args)
     if args.workload == "warmstart1024":
         return bench_warmstart(args)
+    if args.workload == "converge512":
+        return bench_converge(args)
 
     import paper_2510_16154_amd as A
     from paper_2510_16154_amd.workloads import VORONOI512 as wl
@@ -348,6 +350,38 @@ def bench_hyper(args) -> int:
                                "sample": f"{reps} x (forward + adjoint sweep, {K} steps) of a 128x128x31 crop, "
                                          f"R={R}, FP64, {dt:.1f} s"}
     print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_converge(args) -> int:
+    """Time to a converged solve of the 512 x 512 x 3 bench image: the method of
+    multipliers until r_rel < 1e-5 (at most 200 iterations of at most 50 DAL
+    steps each), from the cold start.  One timed call of abc_solve per step."""
+    import torch
+
+    import paper_2510_16154_amd as A
+    from paper_2510_16154_amd.workloads import VORONOI512 as wl
+
+    c0 = torch.as_tensor(wl.image(), device="cuda")
+    params = wl.params()
+    for _ in range(args.warmup):
+        A.abc_solve(c0, params.replace(max_outer=2))
+    torch.cuda.synchronize()
+    times, st = [], None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        out = A.abc_solve(c0, params)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        st = out["stats"]
+    t = float(np.median(times))
+    res = {"metric": "time-to-converged solve (r_rel < 1e-5)", "value": t, "unit": "s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded Voronoi image)",
+           "config": {"workload": wl.name, "H": wl.H, "W": wl.W, "C": wl.C, "R": wl.R, "K": wl.K,
+                      "stop": "r_rel < 1e-5, M <= 200, P = 50"},
+           "stats": {k: st[k] for k in ("status", "outer_iters", "inner_iters", "ls_evals", "K", "r_rel", "gap_rel")}}
+    print(json.dumps(res), flush=True)
     return 0
 
 

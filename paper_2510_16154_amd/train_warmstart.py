@@ -37,6 +37,13 @@ def main(argv=None):
     ap.add_argument("--weights", default=None, help="skip data and training: evaluate these weights (.npy)")
     ap.add_argument("--eval-outer", type=int, default=20, help="multiplier iteration cap of the evaluated solves")
     ap.add_argument("--tol-gap", type=float, default=1e-2, help="Lagrangian-gap stop of the evaluated solves")
+    ap.add_argument("--eval-tol-alm", type=float, default=0.0,
+                    help="ALM residual stop of the evaluated solves (0: off, the gap stop decides)")
+    ap.add_argument("--target-outer", type=int, default=5, help="multiplier iterations of the target solves")
+    ap.add_argument("--target-inner", type=int, default=10, help="DAL iterations per multiplier iteration")
+    ap.add_argument("--target-tol-alm", type=float, default=0.0,
+                    help="ALM residual stop of the target solves (0: run --target-outer iterations)")
+    ap.add_argument("--chunk", type=int, default=256, help="images solved per data chunk (one progress line each)")
     args = ap.parse_args(argv)
 
     import torch
@@ -47,7 +54,8 @@ def main(argv=None):
     from .workloads import VORONOI512
 
     os.makedirs(args.out, exist_ok=True)
-    params = B.Params(K=VORONOI512.K, R=VORONOI512.R, max_outer=5, max_inner=10, alpha=VORONOI512.alpha)
+    params = B.Params(K=VORONOI512.K, R=VORONOI512.R, max_outer=args.target_outer, max_inner=args.target_inner,
+                      alpha=VORONOI512.alpha, tol_alm=args.target_tol_alm)
     ws = WarmStart(params.K, params, seed=7)
     logs, t_data = [], 0.0
     if args.weights:
@@ -55,7 +63,7 @@ def main(argv=None):
         args.n_train = 0
     t0 = time.perf_counter()
     xs, mus, epss = [], [], []
-    chunk = 256
+    chunk = args.chunk
     for s in range(0, args.n_train, chunk):
         x, mu, eps = make_dataset(min(chunk, args.n_train - s), args.size, args.train_seed + s, params)
         xs.append(x)
@@ -81,7 +89,8 @@ def main(argv=None):
         regions = int(r.integers(4, 17))
         sigma = float(r.uniform(0.02, 0.1))
         img = torch.as_tensor(voronoi_image(args.eval_size, args.eval_size, 3, regions, sigma, seed), device="cuda")
-        pe = params.replace(max_outer=args.eval_outer, tol_gap=args.tol_gap)
+        pe = params.replace(max_outer=args.eval_outer, max_inner=10, tol_gap=args.tol_gap,
+                            tol_alm=args.eval_tol_alm)
         cold = cold_solve(img, pe, keep_state=True)
         warm = ws.solve(img, pe, cold=cold)
         ideal = ideal_warm_solve(img, pe, cold)

@@ -47,3 +47,21 @@ def test_batched_handles_one_image_and_early_inner_exit():
     outs, stats, _ = A.abc_solve_batched([T(c0), T(other)], gp)
     assert torch.all(outs[0] == 0.5)
     assert stats[0]["ls_evals"] == 0 and stats[1]["ls_evals"] > 0
+
+
+def test_batched_wide_channels_equal_individual_solves_and_graphs():
+    """31 channels at radius 2 run on the lanes-per-pixel kernels, batched and single."""
+    print("[case] batched vs individual, C=31", flush=True)
+    shapes = [(40, 57), (33, 33), (16, 90)]
+    imgs = [voronoi_image(h, w, 31, 4, 0.05, 700 + i, spectra=True) for i, (h, w) in enumerate(shapes)]
+    gp = A.Params(K=6, R=2, alpha=20.0, max_outer=2, max_inner=3, tile_x=16, tile_y=16)
+    outs, stats, _ = A.abc_solve_batched([T(x) for x in imgs], gp)
+    torch.cuda.synchronize()
+    for i, x in enumerate(imgs):
+        ref = A.abc_solve(T(x), gp)
+        assert torch.equal(outs[i], ref["c"]), i
+        for key in ("K", "L", "inner_iters", "ls_evals", "outer_iters"):
+            assert stats[i][key] == ref["stats"][key], (i, key)
+    direct, _, _ = A.abc_solve_batched([T(x) for x in imgs], gp.replace(flags=A.ABC_FLAG_NO_GRAPHS))
+    for x, y in zip(outs, direct):
+        assert torch.equal(x, y)

@@ -66,3 +66,20 @@ def test_autotuner_picks_admissible_tiles_and_caches(tmp_path):
     g_ref, _ = A.abc_adjoint_dynamics(ref, eps, p, gK)
     g_got, _ = A.abc_adjoint_dynamics(got, eps, tuned, gK)
     assert torch.equal(g_ref, g_got)
+
+
+def test_autotuner_with_wide_channels():
+    c0 = T(voronoi_image(96, 130, 31, 6, 0.05, 6, spectra=True))
+    p = A.Params(K=4, R=2)
+    tuned, us = A.abc_autotune(c0, p)
+    print(f"[tune C=31] fwd {tuned.tile_x}x{tuned.tile_y} {us[0]:.1f} us, adj {tuned.adj_tile_x}x{tuned.adj_tile_y} "
+          f"{us[1]:.1f} us", flush=True)
+    assert us[0] > 0 and us[1] > 0
+    eps = T(np.random.default_rng(3).uniform(20, 300, size=(4, 2)))
+    ref = A.abc_forward_dynamics(c0, eps, p)
+    got = A.abc_forward_dynamics(c0, eps, tuned)
+    assert torch.equal(ref, got)
+    gK = T(np.random.default_rng(4).normal(size=(96, 130, 31)))
+    g_ref, e_ref = A.abc_adjoint_dynamics(ref, eps, p, gK)
+    g_got, e_got = A.abc_adjoint_dynamics(got, eps, tuned, gK)
+    assert torch.equal(g_ref, g_got)
