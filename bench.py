@@ -73,12 +73,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
                     help="repeat the oracle's full forward+adjoint sweep until this much time has passed")
-    ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512", "hyper2048", "warmstart1024", "converge512"],
+    ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512", "hyper2048", "warmstart1024", "converge512",
+                             "transfer1024"],
                     help="voronoi512: the headline line (default); batch64: the batched form; segment512: "
                          "watershed labels and IRV/IRC/VS scores of a solved 512 x 512 image; hyper2048: the "
                          "differentiable form on 2048 x 2048 x 31 (checkpointed forward + backward); warmstart1024: "
                          "time to a converged solve of held-out 1024 x 1024 images, plain against the packaged "
-                         "learned warm start; converge512: time to solve the 512 x 512 image to ALM residual 1e-5")
+                         "learned warm start; converge512: time to solve the 512 x 512 image to ALM residual 1e-5; "
+                         "transfer1024: controls of the 512 x 512 solve applied to its 2x finer version")
     ap.add_argument("--images", type=int, default=4, help="warmstart1024: held-out images to solve")
     ap.add_argument("--no-graphs", action="store_true",
                     help="batch64: launch every sweep step directly instead of replaying captured graphs")
@@ -113,6 +115,8 @@ def main() -> int:
         return bench_warmstart(args)
     if args.workload == "converge512":
         return bench_converge(args)
+    if args.workload == "transfer1024":
+        return bench_transfer(args)
 
     import paper_2510_16154_amd as A
     from paper_2510_16154_amd.workloads import VORONOI512 as wl
@@ -349,6 +353,51 @@ def bench_hyper(args) -> int:
                                "cores": O.num_threads(), "kind": "oracle",
                                "sample": f"{reps} x (forward + adjoint sweep, {K} steps) of a 128x128x31 crop, "
                                          f"R={R}, FP64, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_transfer(args) -> int:
+    """Sec. 4.3 control transfer: controls solved on the 512 x 512 x 3 bench image (3 x 5
+    iterations) drive one forward sweep of its 2x nearest-neighbour upsampled version
+    (1024 x 1024, window 2R = 10, normalisation s/4).  One step = that sweep."""
+    import torch
+
+    import paper_2510_16154_amd as A
+    from paper_2510_16154_amd.transfer import transfer_params
+    from paper_2510_16154_amd.workloads import VORONOI512 as wl
+
+    c_lo = torch.as_tensor(wl.image(), device="cuda")
+    p_lo = wl.params(max_outer=3, max_inner=5, tol_alm=0.0)
+    eps = torch.full((wl.K, 2), p_lo.eps_init, dtype=torch.float32, device="cuda")
+    A.abc_solve(c_lo, p_lo, eps=eps)
+    c_hi = c_lo.repeat_interleave(2, dim=0).repeat_interleave(2, dim=1).contiguous()
+    ph = transfer_params(p_lo, wl.H, wl.W, 2)
+    H, W, C = c_hi.shape
+    ws = torch.empty(max(A.abc_workspace_bytes(A.ABC_WS_FORWARD, H, W, C, ph), 1), dtype=torch.uint8, device="cuda")
+    traj = torch.empty((A.abc_traj_slots(ph), H, W, C), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        A.abc_forward_dynamics(c_hi, eps, ph, traj=traj, ws=ws)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(args.steps):
+        ev[0].record(stream)
+        A.abc_forward_dynamics(c_hi, eps, ph, traj=traj, ws=ws)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    t = float(np.median(ms)) * 1e-3
+    pairs = window_pairs(H, W, ph.R)
+    tflops = pairs * flops_per_pair(C, "fwd") * wl.K / t / 1e12
+    out = {"metric": "agent-steps/sec (forward sweep, transferred controls)", "value": H * W * wl.K / t,
+           "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded Voronoi image, 2x upsampled)",
+           "config": {"workload": "transfer1024_rgb_r10_k50", "H": H, "W": W, "C": C, "R": ph.R, "K": wl.K},
+           "roofline": {"kernel": f"fwd_step_kernel<3,{ph.R if ph.R <= 5 else 0}>", "bound": "alu",
+                        "achieved": tflops, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tflops / PEAK_FP32_VALU_TFLOPS, "traffic": None}}
     print(json.dumps(out), flush=True)
     return 0
 
