@@ -175,7 +175,9 @@ int pick_tile(const abc_params* p, int C, int fields, abc::Tile* t) {
     if (tx > 0 || ty > 0) {
         abc::Tile u{tx, ty};
         if (!abc::tile_ok(C, p->R, u, fields))
-            return fail(ABC_EINVAL, "tile_x * tile_y must be a multiple of 64 and <= 256, and fit in LDS");
+            return fail(ABC_EINVAL, "tile: tile_y must be a multiple of the pixels per thread (" +
+                                        std::to_string(abc::rows_per_thread(C, p->R)) +
+                                        "), tile_x * tile_y / that a multiple of 64 and <= 256, and fit in LDS");
         *t = u;
         return ABC_OK;
     }
@@ -1612,8 +1614,8 @@ bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& 
     return std::rename(tmp.c_str(), path) == 0;
 }
 
-const abc::Tile kTuneCands[] = {{32, 8}, {16, 16}, {64, 4}, {128, 2}, {16, 8}, {32, 4}, {64, 2},
-                                {8, 16}, {8, 8},   {16, 4}, {32, 2}, {64, 1}};
+const abc::Tile kTuneCands[] = {{32, 16}, {64, 8}, {16, 32}, {128, 4}, {32, 8}, {16, 16}, {64, 4}, {128, 2},
+                                {16, 8},  {32, 4}, {64, 2},  {8, 16},  {8, 8},  {16, 4},  {32, 2}, {64, 1}};
 
 size_t tune_ws_bytes(int H, int W, int C) {
     Carve cv(nullptr);

@@ -13,8 +13,8 @@ namespace abc {
 void set_last_error(const std::string& msg);
 
 // Tile of pixels handled by one workgroup of the windowed interaction kernels
-// (one thread per pixel; the workgroup stages the tile plus an R-pixel halo
-// in LDS).
+// (one or two pixels per thread, see rows_per_thread; the workgroup stages the
+// tile plus an R-pixel halo in LDS).
 struct Tile {
     int tx, ty;
 };
@@ -67,7 +67,15 @@ size_t tile_lds_bytes(int C, int R, Tile t, int fields);
 // Default tile for (C, R) and kernel kind (fields = 1 forward, 2 adjoint).
 Tile default_tile(int C, int R, int fields);
 
-// True when the (C, R, tile) combination fits the hardware limits.
+// Pixels each thread of the interaction kernels computes (vertically adjacent):
+// 2 for 1 to 4 channels with a radius of 1 to 5, else 1.  A tile of tx x ty
+// pixels runs as tx x ty / rows_per_thread threads (times the lanes per pixel
+// of the wide kernels).
+int rows_per_thread(int C, int R);
+
+// True when the (C, R, tile) combination fits the hardware limits: ty a
+// multiple of rows_per_thread, a whole number of 64-lane waves, at most 256
+// threads (1024 for the wide kernels) and the LDS budget.
 bool tile_ok(int C, int R, Tile t, int fields);
 
 // One explicit Euler step of the agent dynamics: cout = cin + dts * F(cin, eps^k).

@@ -1,7 +1,8 @@
 // gfx950 kernels of the agent-based optimal-control solver.
 //
 // Windowed interaction (forward Euler step of eq. MAsystem and its transpose,
-// Sec. 3.1): one thread per pixel, one workgroup per tile.  The workgroup
+// Sec. 3.1): one workgroup per tile, one or two vertically adjacent pixels
+// per thread (two with a compile-time radius).  The workgroup
 // stages its tile plus an R-pixel halo in LDS (channel-interleaved 16-byte
 // slots with one extra value per pixel that is 1 inside the image and 0 for
 // halo cells beyond the border), then every thread sums its (2R+1)^2 window in
@@ -103,6 +104,13 @@ struct Slot {
     static constexpr int CS = CP == 1 ? 2 : 4 * NS;                  // floats per slot
 };
 
+// Pixels per thread of the one-lane interaction kernels: two vertically
+// adjacent pixels with a compile-time radius, one with the runtime radius.
+template <int RT>
+struct RowsPerThread {
+    static constexpr int value = RT > 0 ? 2 : 1;
+};
+
 template <int CP>
 __device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m) {
     if constexpr (CP == 1) {
@@ -171,46 +179,58 @@ __device__ __forceinline__ void offset_table(float* om, int RT, float Ax, float 
 // Forward step.
 // With a compile-time radius the offset constants om_ab come from a table in
 // LDS (filled once per workgroup with the same expression), which takes one
-// VALU operation per neighbour off the inner loop.
-template <int CP, int RT, bool BORDER>
-__device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const float (&ci)[CP],
-                                           float (&acc)[CP], float Ax, float Ay, float ech, const float* omt) {
+// VALU operation per neighbour off the inner loop, and each thread computes
+// NP = 2 vertically adjacent pixels: a neighbour read from LDS serves every
+// pixel of the thread whose window holds it (the windows of rows y and y+1
+// share 2R of their 2R+1 rows).  Each pixel still sums its own window in the
+// (a, b) order, so the result is the same bit for bit as with one pixel per
+// thread.
+template <int CP, int RT, int NP, bool BORDER>
+__device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const float (&ci)[NP][CP],
+                                           float (&acc)[NP][CP], float Ax, float Ay, float ech, const float* omt) {
     constexpr int CS = Slot<CP>::CS;
     const int RR = RT > 0 ? RT : R;
+    // r: row of the neighbour relative to the thread's first pixel; pixel m sees it at a = r - m
 #pragma unroll
-    for (int a = -RR; a <= RR; ++a) {
-        const float* row = me + a * LW * CS;
-        const float om_row = fmaf(-Ay, (float)(a * a), 1.0f);
+    for (int r = -RR; r <= RR + NP - 1; ++r) {
+        const float* row = me + r * LW * CS;
 #pragma unroll
         for (int b = -RR; b <= RR; ++b) {
-            if (a == 0 && b == 0) continue;
             float cj[CP], mj;
             load_px<CP>(row + b * CS, cj, mj);
-            const float om = RT > 0 ? omt[(a + RR) * (2 * RR + 1) + b + RR] : fmaf(-Ax, (float)(b * b), om_row);
-            float d[CP];
-            float n2 = 0.0f;
 #pragma unroll
-            for (int ch = 0; ch < CP; ++ch) {
-                d[ch] = cj[ch] - ci[ch];
-                n2 = fmaf(d[ch], d[ch], n2);
+            for (int m = 0; m < NP; ++m) {
+                const int a = r - m;
+                if (a < -RR || a > RR || (a == 0 && b == 0)) continue;
+                const float om = RT > 0 ? omt[(a + RR) * (2 * RR + 1) + b + RR]
+                                        : fmaf(-Ax, (float)(b * b), fmaf(-Ay, (float)(a * a), 1.0f));
+                float d[CP];
+                float n2 = 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    d[ch] = cj[ch] - ci[m][ch];
+                    n2 = fmaf(d[ch], d[ch], n2);
+                }
+                const float t = clamp01(fmaf(-ech, n2, om));
+                const float t2 = t * t;
+                float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
+                if (BORDER) w *= mj;
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) acc[m][ch] = fmaf(w, d[ch], acc[m][ch]);
             }
-            const float t = clamp01(fmaf(-ech, n2, om));
-            const float t2 = t * t;
-            float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
-            if (BORDER) w *= mj;
-#pragma unroll
-            for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(w, d[ch], acc[ch]);
         }
     }
 }
 
-// One interaction tile of a forward step: stage, then one thread per pixel.
+// One interaction tile of a forward step: stage, then NP pixels per thread
+// (the workgroup is TX x TY/NP threads for a TX x TY tile).
 template <int CP, int RT>
 __device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* __restrict__ cout, float exh,
                                          float ech, int H, int W, int C, int R, int tile, int tiles_x, float dts,
                                          float dx2, float dy2, float* lds) {
     constexpr int CS = Slot<CP>::CS;
-    const int TX = blockDim.x, TY = blockDim.y;
+    constexpr int NP = RowsPerThread<RT>::value;
+    const int TX = blockDim.x, TY = NP * blockDim.y;
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
@@ -218,21 +238,28 @@ __device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* _
     if constexpr (RT > 0) offset_table(omt, RT, exh * dx2, exh * dy2);
     stage_tile<CP>(lds, cin, H, W, C, x0, y0, R, LW, LH);
     __syncthreads();
-    const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
+    const int gx = x0 + threadIdx.x, gy = y0 + NP * threadIdx.y;
     if (gx >= W || gy >= H) return;
-    const float* me = lds + ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
-    float ci[CP], acc[CP], mi;
-    load_px<CP>(me, ci, mi);
+    const float* me = lds + ((NP * threadIdx.y + R) * LW + threadIdx.x + R) * CS;
+    float ci[NP][CP], acc[NP][CP], mi;
 #pragma unroll
-    for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
+    for (int m = 0; m < NP; ++m) {
+        load_px<CP>(me + m * LW * CS, ci[m], mi);
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch) acc[m][ch] = 0.0f;
+    }
     if (interior)
-        fwd_window<CP, RT, false>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech, omt);
+        fwd_window<CP, RT, NP, false>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech, omt);
     else
-        fwd_window<CP, RT, true>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech, omt);
-    float* o = cout + ((size_t)gy * W + gx) * C;
+        fwd_window<CP, RT, NP, true>(me, LW, R, ci, acc, exh * dx2, exh * dy2, ech, omt);
 #pragma unroll
-    for (int ch = 0; ch < CP; ++ch)
-        if (ch < C) o[ch] = fmaf(dts, acc[ch], ci[ch]);
+    for (int m = 0; m < NP; ++m) {
+        if (gy + m >= H) break;
+        float* o = cout + ((size_t)(gy + m) * W + gx) * C;
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch)
+            if (ch < C) o[ch] = fmaf(dts, acc[m][ch], ci[m][ch]);
+    }
 }
 
 template <int CP, int RT>
@@ -286,71 +313,76 @@ fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 // over pixels is carried in FP64 (the solver's projected steps can reach
 // 1e13 or more, which amplifies rounding in this sum directly into the
 // controls).
-template <int CP, int RT, bool BORDER>
+template <int CP, int RT, int NP, bool BORDER>
 __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int LW, int R,
-                                           const float (&ci)[CP], const float (&pi)[CP], float (&acc)[CP],
-                                           float (&accq)[CP], float& sx, float& sc, float Ax, float Ay, float ech,
-                                           float dx2, float dy2) {
+                                           const float (&ci)[NP][CP], const float (&pi)[NP][CP],
+                                           float (&acc)[NP][CP], float (&accq)[NP][CP], float (&sx)[NP],
+                                           float (&sc)[NP], float Ax, float Ay, float ech, float dx2, float dy2) {
     constexpr int CS = Slot<CP>::CS;
     const int RR = RT > 0 ? RT : R;
+    // r: row of the neighbour relative to the thread's first pixel; pixel m sees it at a = r - m
 #pragma unroll
-    for (int a = -RR; a <= RR; ++a) {
-        const float* rowc = mc + a * LW * CS;
-        const float* rowp = mp + a * LW * CS;
-        const float om_row = fmaf(-Ay, (float)(a * a), 1.0f);
-        const float d2_row = dy2 * (float)(a * a);
+    for (int r = -RR; r <= RR + NP - 1; ++r) {
+        const float* rowc = mc + r * LW * CS;
+        const float* rowp = mp + r * LW * CS;
 #pragma unroll
         for (int b = -RR; b <= RR; ++b) {
-            if (a == 0 && b == 0) continue;
             float cj[CP], pj[CP], mj, unused;
             load_px<CP>(rowc + b * CS, cj, mj);
             load_px<CP>(rowp + b * CS, pj, unused);
-            const float om = fmaf(-Ax, (float)(b * b), om_row);
-            const float d2 = fmaf(dx2, (float)(b * b), d2_row);
-            float d[CP];
-            float n2 = 0.0f;
 #pragma unroll
-            for (int ch = 0; ch < CP; ++ch) {
-                d[ch] = cj[ch] - ci[ch];
-                n2 = fmaf(d[ch], d[ch], n2);
-            }
-            const float t = clamp01(fmaf(-ech, n2, om));
-            const float t3 = (t * t) * t;
-            const float t4 = t3 * t;
-            float w = fmaf(-4.0f, t, 5.0f) * t4;
-            float u = t4 - t3;
-            if (BORDER) {
-                w *= mj;
-                u *= mj;
-            }
-            float dp[CP];
-            float ddp = 0.0f;
+            for (int m = 0; m < NP; ++m) {
+                const int a = r - m;
+                if (a < -RR || a > RR || (a == 0 && b == 0)) continue;
+                const float om = fmaf(-Ax, (float)(b * b), fmaf(-Ay, (float)(a * a), 1.0f));
+                const float d2 = fmaf(dx2, (float)(b * b), dy2 * (float)(a * a));
+                float d[CP];
+                float n2 = 0.0f;
 #pragma unroll
-            for (int ch = 0; ch < CP; ++ch) {
-                dp[ch] = pj[ch] - pi[ch];
-                ddp = fmaf(d[ch], dp[ch], ddp);
-            }
-            const float q = u * ddp;
+                for (int ch = 0; ch < CP; ++ch) {
+                    d[ch] = cj[ch] - ci[m][ch];
+                    n2 = fmaf(d[ch], d[ch], n2);
+                }
+                const float t = clamp01(fmaf(-ech, n2, om));
+                const float t3 = (t * t) * t;
+                const float t4 = t3 * t;
+                float w = fmaf(-4.0f, t, 5.0f) * t4;
+                float u = t4 - t3;
+                if (BORDER) {
+                    w *= mj;
+                    u *= mj;
+                }
+                float dp[CP];
+                float ddp = 0.0f;
 #pragma unroll
-            for (int ch = 0; ch < CP; ++ch) {
-                acc[ch] = fmaf(w, dp[ch], acc[ch]);
-                accq[ch] = fmaf(q, d[ch], accq[ch]);
+                for (int ch = 0; ch < CP; ++ch) {
+                    dp[ch] = pj[ch] - pi[m][ch];
+                    ddp = fmaf(d[ch], dp[ch], ddp);
+                }
+                const float q = u * ddp;
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    acc[m][ch] = fmaf(w, dp[ch], acc[m][ch]);
+                    accq[m][ch] = fmaf(q, d[ch], accq[m][ch]);
+                }
+                sx[m] = fmaf(d2, q, sx[m]);
+                sc[m] = fmaf(n2, q, sc[m]);
             }
-            sx = fmaf(d2, q, sx);
-            sc = fmaf(n2, q, sc);
         }
     }
 }
 
-// One interaction tile of a transposed step; part[2*tile + {0,1}] receives the
-// workgroup's FP64 sums of the two control-gradient integrands.
+// One interaction tile of a transposed step (NP pixels per thread, as in the
+// forward step); part[2*tile + {0,1}] receives the workgroup's FP64 sums of
+// the two control-gradient integrands.
 template <int CP, int RT>
 __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const float* __restrict__ pin,
                                          float* __restrict__ pout, float ex, float ec, int H, int W, int C, int R,
                                          int tile, int tiles_x, float dts, float dx2, float dy2,
                                          double* __restrict__ part, float* lds, double* red) {
     constexpr int CS = Slot<CP>::CS;
-    const int TX = blockDim.x, TY = blockDim.y;
+    constexpr int NP = RowsPerThread<RT>::value;
+    const int TX = blockDim.x, TY = NP * blockDim.y;
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
@@ -359,32 +391,42 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
     stage_tile<CP>(ldc, c, H, W, C, x0, y0, R, LW, LH);
     stage_tile<CP>(ldp, pin, H, W, C, x0, y0, R, LW, LH);
     __syncthreads();
-    const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
-    float sx = 0.0f, sc = 0.0f;
+    const int gx = x0 + threadIdx.x, gy = y0 + NP * threadIdx.y;
+    double tsx = 0.0, tsc = 0.0;
     if (gx < W && gy < H) {
         const float exh = 0.5f * ex, ech = 0.5f * ec;
-        const int off = ((threadIdx.y + R) * LW + threadIdx.x + R) * CS;
+        const int off = ((NP * threadIdx.y + R) * LW + threadIdx.x + R) * CS;
         const float* mc = ldc + off;
         const float* mp = ldp + off;
-        float ci[CP], pi[CP], acc[CP], accq[CP], mi;
-        load_px<CP>(mc, ci, mi);
-        load_px<CP>(mp, pi, mi);
+        float ci[NP][CP], pi[NP][CP], acc[NP][CP], accq[NP][CP], sx[NP], sc[NP], mi;
 #pragma unroll
-        for (int ch = 0; ch < CP; ++ch) acc[ch] = accq[ch] = 0.0f;
+        for (int m = 0; m < NP; ++m) {
+            load_px<CP>(mc + m * LW * CS, ci[m], mi);
+            load_px<CP>(mp + m * LW * CS, pi[m], mi);
+            sx[m] = sc[m] = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) acc[m][ch] = accq[m][ch] = 0.0f;
+        }
         if (interior)
-            adj_window<CP, RT, false>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
-                                      dy2);
+            adj_window<CP, RT, NP, false>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
+                                          dy2);
         else
-            adj_window<CP, RT, true>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
-                                     dy2);
+            adj_window<CP, RT, NP, true>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
+                                         dy2);
         const float ec20 = 20.0f * ec;
-        float* o = pout + ((size_t)gy * W + gx) * C;
 #pragma unroll
-        for (int ch = 0; ch < CP; ++ch)
-            if (ch < C) o[ch] = fmaf(dts, fmaf(ec20, accq[ch], acc[ch]), pi[ch]);
+        for (int m = 0; m < NP; ++m) {
+            if (gy + m >= H) break;
+            float* o = pout + ((size_t)(gy + m) * W + gx) * C;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch)
+                if (ch < C) o[ch] = fmaf(dts, fmaf(ec20, accq[m][ch], acc[m][ch]), pi[m][ch]);
+            tsx += (double)sx[m];
+            tsc += (double)sc[m];
+        }
     }
-    const double bx = block_sum_f64((double)sx, red);
-    const double bc = block_sum_f64((double)sc, red);
+    const double bx = block_sum_f64(tsx, red);
+    const double bc = block_sum_f64(tsc, red);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         part[2 * tile + 0] = bx;
         part[2 * tile + 1] = bc;
@@ -1040,8 +1082,8 @@ hipError_t fwd_launch_t(const float* cin, float* cout, const float* eps, int k, 
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty), lds, s, cin, cout, eps, k, H, W, C, R, tiles_x, dts, dx2,
-                       dy2);
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, cin, cout, eps, k, H, W,
+                       C, R, tiles_x, dts, dx2, dy2);
     return hipGetLastError();
 }
 
@@ -1057,8 +1099,8 @@ hipError_t adj_launch_t(const float* c, const float* pin, float* pout, const flo
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty), lds, s, c, pin, pout, eps, k, H, W, C, R, tiles_x, dts,
-                       dx2, dy2, part);
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, c, pin, pout, eps, k, H,
+                       W, C, R, tiles_x, dts, dx2, dy2, part);
     return hipGetLastError();
 }
 
@@ -1181,7 +1223,7 @@ hipError_t fwdb_launch_t(const StepJob* jobs, int njobs, int total, int k, int C
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty), lds, s, jobs, njobs, k, C, R);
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, jobs, njobs, k, C, R);
     return hipGetLastError();
 }
 
@@ -1194,7 +1236,8 @@ hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty), lds, s, jobs, njobs, k, K, C, R);
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, jobs, njobs, k, K, C,
+                       R);
     return hipGetLastError();
 }
 
@@ -1265,17 +1308,23 @@ size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
             (size_t)(2 * R + 1) * (2 * R + 1)) * sizeof(float);
 }
 
+int rows_per_thread(int C, int R) {
+    const int cp = padded_channels(C);
+    return (cp >= 1 && cp <= 4 && R >= 1 && R <= 5) ? RowsPerThread<1>::value : RowsPerThread<0>::value;
+}
+
 bool tile_ok(int C, int R, Tile t, int fields) {
-    const int G = wide_lanes(C, R);
-    const int threads = t.tx * t.ty * G;
-    if (t.tx < 1 || t.ty < 1 || threads > (G > 1 ? kMaxWideThreads : kMaxThreads)) return false;
+    const int G = wide_lanes(C, R), NP = rows_per_thread(C, R);
+    if (t.tx < 1 || t.ty < 1 || t.ty % NP != 0) return false;
+    const int threads = t.tx * (t.ty / NP) * G;
+    if (threads > (G > 1 ? kMaxWideThreads : kMaxThreads)) return false;
     if (threads % kWave != 0) return false;
     return tile_lds_bytes(C, R, t, fields) <= kMaxLds;
 }
 
 // Waves one CU can hold for a tile, limited by LDS and by 8 waves per SIMD.
 static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
-    const int wpb = (t.tx * t.ty * wide_lanes(C, R) + kWave - 1) / kWave;
+    const int wpb = (t.tx * (t.ty / rows_per_thread(C, R)) * wide_lanes(C, R) + kWave - 1) / kWave;
     const size_t lds = tile_lds_bytes(C, R, t, fields);
     const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
     return std::min(by_lds, 32 / wpb) * wpb;
@@ -1285,7 +1334,8 @@ static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
 // that leaves fewer than 8 waves per CU (wide pixels), the candidate with the
 // most waves per CU wins instead, then the one with the least halo.
 Tile default_tile(int C, int R, int fields) {
-    static const Tile cands[] = {{32, 8}, {16, 16}, {64, 4}, {16, 8}, {32, 4}, {8, 16}, {8, 8}, {64, 1}};
+    static const Tile cands[] = {{32, 16}, {32, 8}, {16, 16}, {64, 4}, {16, 8}, {32, 4}, {8, 16}, {8, 8}, {64, 2},
+                                 {64, 1}};
     const size_t budget = 64 * 1024;
     for (const Tile& t : cands)
         if (tile_ok(C, R, t, fields) && tile_lds_bytes(C, R, t, fields) <= budget &&

@@ -94,7 +94,8 @@ def test_forward_and_adjoint_match_oracle(orc, H, W, C, R, K, seed):
 
 
 @pytest.mark.parametrize("C,R,tiles", [
-    (3, 2, [(32, 8), (16, 16), (64, 4), (8, 8), (64, 1), (16, 4)]),
+    (3, 2, [(32, 16), (32, 8), (16, 16), (64, 4), (8, 16), (128, 2), (16, 8)]),
+    (3, 5, [(32, 16), (64, 8), (16, 8), (32, 4)]),
     (31, 2, [(32, 8), (16, 16), (16, 8), (8, 8), (64, 4)]),
     (64, 1, [(16, 8), (8, 8), (8, 16), (32, 4)]),
 ])

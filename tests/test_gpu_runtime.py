@@ -51,7 +51,9 @@ def test_autotuner_picks_admissible_tiles_and_caches(tmp_path):
     print(f"[tune] fwd {tuned.tile_x}x{tuned.tile_y} {us[0]:.1f} us, adj {tuned.adj_tile_x}x{tuned.adj_tile_y} "
           f"{us[1]:.1f} us", flush=True)
     assert us[0] > 0 and us[1] > 0
-    assert tuned.tile_x * tuned.tile_y in (64, 128, 256) and tuned.adj_tile_x * tuned.adj_tile_y in (64, 128, 256)
+    # two pixels per thread at C = 3, R = 5: 64 to 256 threads hold 128 to 512 pixels
+    assert tuned.tile_x * tuned.tile_y in (128, 256, 512) and tuned.adj_tile_x * tuned.adj_tile_y in (128, 256, 512)
+    assert tuned.tile_y % 2 == 0 and tuned.adj_tile_y % 2 == 0
     data = json.load(open(cache))
     assert len(data) == 1 and list(data.values())[0]["fwd"] == [tuned.tile_x, tuned.tile_y]
     again, us2 = A.abc_autotune(c0, p, cache_path=cache)
