@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "0db4005bac7709dccebbad23df421274da6dc0b54d51d67af1ead9fccca35585",
-    "adj_step_kernel<3,5>": 11.54e6,
-    "adj_step_wide_kernel<31,2>": 2079.08e6,
+    "kernel_sha256": "975df440abaeeea7b3203f9433268e3e4265c129e39672a5e9d8d3c66e3afbf7",
+    "adj_step_kernel<3,5>": 11.55e6,
+    "adj_step_wide_kernel<31,2>": 2079.64e6,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")
 
@@ -71,11 +71,13 @@ def flops_per_pair(C: int, kind: str) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 50 for voronoi512, fewer for the longer workloads)")
     # The GPU's clocks settle only after tens of milliseconds of sustained load (per-launch
     # times of the interaction kernels fall by about 12% over the first 10 to 20 sweeps), so
-    # the default warm-up runs about a quarter of a second of steps before timing.
-    ap.add_argument("--warmup", type=int, default=100)
+    # the default warm-up of the headline line runs about a quarter of a second of steps.
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warm-up steps (default: 100 for voronoi512, fewer for the longer workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
                     help="repeat the oracle's full forward+adjoint sweep until this much time has passed")
@@ -94,6 +96,14 @@ def main() -> int:
                     help="only run a plain device copy of MIB MiB (5 times) and exit; used to calibrate "
                          "the HBM byte counters")
     args = ap.parse_args()
+    # (steps, warmup) per workload when not given: the longer workloads time whole solves.
+    defaults = {"voronoi512": (50, 100), "batch64": (3, 1), "segment512": (20, 3), "hyper2048": (5, 2),
+                "warmstart1024": (0, 1), "converge512": (1, 1), "transfer1024": (20, 5)}
+    d_steps, d_warm = defaults[args.workload]
+    if args.steps is None:
+        args.steps = d_steps
+    if args.warmup is None:
+        args.warmup = d_warm
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
               "single device, see the design notes for how it would shard)", file=sys.stderr)

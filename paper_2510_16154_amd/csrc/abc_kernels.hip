@@ -136,28 +136,46 @@ __device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m
 
 // Stage rows [y0-R, y0+TY+R) x cols [x0-R, x0+TX+R) of a HWC field into LDS
 // slots; channels >= C and cells outside the image are 0, the mask slot is 1
-// inside the image and 0 outside.
+// inside the image and 0 outside.  Loads carry no branches (a cell outside
+// the image reads pixel 0 and channel indices are clamped into the pixel;
+// the values are replaced by 0 afterwards), and each pass has the loads of
+// up to four cells (two rows x two columns) in flight before it writes LDS.
 template <int CP>
 __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__ src, int H, int W, int C,
                                            int x0, int y0, int R, int LW, int LH) {
     constexpr int NV = Slot<CP>::NV, CS = Slot<CP>::CS;
-    for (int ly = threadIdx.y; ly < LH; ly += blockDim.y) {
-        const int gy = y0 - R + ly;
-        for (int lx = threadIdx.x; lx < LW; lx += blockDim.x) {
-            const int gx = x0 - R + lx;
-            const bool in = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-            const float* s = src + (in ? ((size_t)gy * W + gx) * C : 0);
-            float t[CS];
+    for (int ly0 = threadIdx.y; ly0 < LH; ly0 += 2 * blockDim.y) {
+        for (int lx0 = threadIdx.x; lx0 < LW; lx0 += 2 * blockDim.x) {
+            float t[4][CS];
+            bool act[4];
+            int cell[4];
 #pragma unroll
-            for (int ch = 0; ch < CS; ++ch) t[ch] = (in && ch < CP && ch < C) ? s[ch] : 0.0f;
-            t[CP] = in ? 1.0f : 0.0f;
-            float* d = dst + (ly * LW + lx) * CS;
-            if constexpr (CP == 1) {
-                *reinterpret_cast<float2*>(d) = make_float2(t[0], t[1]);
-            } else {
+            for (int u = 0; u < 4; ++u) {
+                const int ly = ly0 + (u >> 1) * blockDim.y, lx = lx0 + (u & 1) * blockDim.x;
+                act[u] = ly < LH && lx < LW;
+                cell[u] = ly * LW + lx;
+                const int gy = y0 - R + ly, gx = x0 - R + lx;
+                const bool in = act[u] && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+                const float* s = src + (in ? ((size_t)gy * W + gx) * C : 0);
 #pragma unroll
-                for (int i = 0; i < NV; ++i)
-                    reinterpret_cast<float4*>(d)[i] = make_float4(t[4 * i], t[4 * i + 1], t[4 * i + 2], t[4 * i + 3]);
+                for (int ch = 0; ch < CS; ++ch) {
+                    const float x = ch < CP ? s[min(ch, C - 1)] : 0.0f;
+                    t[u][ch] = (in && ch < CP && ch < C) ? x : 0.0f;
+                }
+                t[u][CP] = in ? 1.0f : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (!act[u]) continue;
+                float* d = dst + cell[u] * CS;
+                if constexpr (CP == 1) {
+                    *reinterpret_cast<float2*>(d) = make_float2(t[u][0], t[u][1]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < NV; ++i)
+                        reinterpret_cast<float4*>(d)[i] =
+                            make_float4(t[u][4 * i], t[u][4 * i + 1], t[u][4 * i + 2], t[u][4 * i + 3]);
+                }
             }
         }
     }
@@ -519,29 +537,55 @@ __device__ __forceinline__ void load8(const float* p, float (&v)[8]) {
 // channel planes: thread (x, y) of the (TX G) x TY workgroup fills plane
 // x % G of cell x / G in every TY-th row, 8 channels as two 16-byte vectors
 // (the G lanes of a cell read one contiguous run of 4C bytes).  Cells
-// outside the image and channels >= C are 0.
+// outside the image and channels >= C are 0.  Every lane loads its 8
+// channels without branches: a lane whose channels run past C reads on into
+// the next pixel (only the image's last pixel takes clamped offsets, so no
+// read leaves the field), cells outside the image read pixel 0, and the
+// unwanted values are replaced by 0 afterwards.  Each row pass has the loads
+// of two cells in flight before it writes LDS.
 template <int G>
 __device__ __forceinline__ void stage_wide(float* dst, const float* __restrict__ src, int H, int W, int C, int x0,
                                            int y0, int R, int LW, int LH, int pf) {
     const int nx = LW * G;
+    const int g = threadIdx.x % G;  // blockDim.x is a multiple of G
+    const int c0 = min(8 * g, C - 1);
+    const int nvalid = min(8, C - 8 * g);
+    const size_t last = (size_t)H * W - 1;
     for (int ly = threadIdx.y; ly < LH; ly += blockDim.y) {
         const int gy = y0 - R + ly;
         const bool row_in = (unsigned)gy < (unsigned)H;
-        for (int e = threadIdx.x; e < nx; e += blockDim.x) {
-            const int lx = e / G, g = e % G;
-            const int gx = x0 - R + lx;
-            float v[8];
-            if (row_in && (unsigned)gx < (unsigned)W) {
-                const float* p = src + ((size_t)gy * W + gx) * C + 8 * g;
+        for (int e0 = threadIdx.x; e0 < nx; e0 += 2 * blockDim.x) {
+            float v[2][8];
+            int lxs[2];
+            bool act[2];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) v[k] = (8 * g + k < C) ? p[k] : 0.0f;
-            } else {
+            for (int u = 0; u < 2; ++u) {
+                const int e = e0 + u * blockDim.x;
+                act[u] = e < nx;
+                const int lx = (act[u] ? e : 0) / G;
+                lxs[u] = lx;
+                const int gx = x0 - R + lx;
+                const bool in = act[u] && row_in && (unsigned)gx < (unsigned)W;
+                const size_t pix = in ? (size_t)gy * W + gx : 0;
+                const float* p = src + pix * C + c0;
+                float x[8];
+                if (pix == last) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) v[k] = 0.0f;
+                    for (int k = 0; k < 8; ++k) x[k] = p[min(k, C - 1 - c0)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) x[k] = p[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[u][k] = (in && k < nvalid) ? x[k] : 0.0f;
             }
-            float4* d = reinterpret_cast<float4*>(dst + g * pf + wide_shift(G, g) * 4 + (ly * LW + lx) * 8);
-            d[0] = make_float4(v[0], v[1], v[2], v[3]);
-            d[1] = make_float4(v[4], v[5], v[6], v[7]);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (!act[u]) continue;
+                float4* d = reinterpret_cast<float4*>(dst + g * pf + wide_shift(G, g) * 4 + (ly * LW + lxs[u]) * 8);
+                d[0] = make_float4(v[u][0], v[u][1], v[u][2], v[u][3]);
+                d[1] = make_float4(v[u][4], v[u][5], v[u][6], v[u][7]);
+            }
         }
     }
 }
