@@ -68,7 +68,7 @@ size_t tile_lds_bytes(int C, int R, Tile t, int fields);
 Tile default_tile(int C, int R, int fields);
 
 // Pixels each thread of the interaction kernels computes (vertically adjacent):
-// 2 for 1 to 4 channels with a radius of 1 to 5, else 1.  A tile of tx x ty
+// 2 for 1 to 4 channels, else 1 (the wide kernels spread one pixel over lanes).  A tile of tx x ty
 // pixels runs as tx x ty / rows_per_thread threads (times the lanes per pixel
 // of the wide kernels).
 int rows_per_thread(int C, int R);

@@ -2,7 +2,7 @@
 //
 // Windowed interaction (forward Euler step of eq. MAsystem and its transpose,
 // Sec. 3.1): one workgroup per tile, one or two vertically adjacent pixels
-// per thread (two with a compile-time radius).  The workgroup
+// per thread (two for up to 4 channels).  The workgroup
 // stages its tile plus an R-pixel halo in LDS (channel-interleaved 16-byte
 // slots with one extra value per pixel that is 1 inside the image and 0 for
 // halo cells beyond the border), then every thread sums its (2R+1)^2 window in
@@ -105,10 +105,10 @@ struct Slot {
 };
 
 // Pixels per thread of the one-lane interaction kernels: two vertically
-// adjacent pixels with a compile-time radius, one with the runtime radius.
-template <int RT>
+// adjacent pixels for up to 4 channels (any radius), one for wider pixels.
+template <int CP>
 struct RowsPerThread {
-    static constexpr int value = RT > 0 ? 2 : 1;
+    static constexpr int value = CP <= 4 ? 2 : 1;
 };
 
 template <int CP>
@@ -197,12 +197,12 @@ __device__ __forceinline__ void offset_table(float* om, int RT, float Ax, float 
 // Forward step.
 // With a compile-time radius the offset constants om_ab come from a table in
 // LDS (filled once per workgroup with the same expression), which takes one
-// VALU operation per neighbour off the inner loop, and each thread computes
-// NP = 2 vertically adjacent pixels: a neighbour read from LDS serves every
-// pixel of the thread whose window holds it (the windows of rows y and y+1
-// share 2R of their 2R+1 rows).  Each pixel still sums its own window in the
-// (a, b) order, so the result is the same bit for bit as with one pixel per
-// thread.
+// VALU operation per neighbour off the inner loop.  For up to 4 channels each
+// thread computes NP = 2 vertically adjacent pixels: a neighbour read from
+// LDS serves every pixel of the thread whose window holds it (the windows of
+// rows y and y+1 share 2R of their 2R+1 rows).  Each pixel still sums its own
+// window in the (a, b) order, so the result is the same bit for bit as with
+// one pixel per thread.
 template <int CP, int RT, int NP, bool BORDER>
 __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const float (&ci)[NP][CP],
                                            float (&acc)[NP][CP], float Ax, float Ay, float ech, const float* omt) {
@@ -247,7 +247,7 @@ __device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* _
                                          float ech, int H, int W, int C, int R, int tile, int tiles_x, float dts,
                                          float dx2, float dy2, float* lds) {
     constexpr int CS = Slot<CP>::CS;
-    constexpr int NP = RowsPerThread<RT>::value;
+    constexpr int NP = RowsPerThread<CP>::value;
     const int TX = blockDim.x, TY = NP * blockDim.y;
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
@@ -399,7 +399,7 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
                                          int tile, int tiles_x, float dts, float dx2, float dy2,
                                          double* __restrict__ part, float* lds, double* red) {
     constexpr int CS = Slot<CP>::CS;
-    constexpr int NP = RowsPerThread<RT>::value;
+    constexpr int NP = RowsPerThread<CP>::value;
     const int TX = blockDim.x, TY = NP * blockDim.y;
     const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
@@ -1126,7 +1126,7 @@ hipError_t fwd_launch_t(const float* cin, float* cout, const float* eps, int k, 
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, cin, cout, eps, k, H, W,
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, cin, cout, eps, k, H, W,
                        C, R, tiles_x, dts, dx2, dy2);
     return hipGetLastError();
 }
@@ -1143,7 +1143,7 @@ hipError_t adj_launch_t(const float* c, const float* pin, float* pout, const flo
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, c, pin, pout, eps, k, H,
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, c, pin, pout, eps, k, H,
                        W, C, R, tiles_x, dts, dx2, dy2, part);
     return hipGetLastError();
 }
@@ -1267,7 +1267,7 @@ hipError_t fwdb_launch_t(const StepJob* jobs, int njobs, int total, int k, int C
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, jobs, njobs, k, C, R);
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, jobs, njobs, k, C, R);
     return hipGetLastError();
 }
 
@@ -1280,7 +1280,7 @@ hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<RT>::value), lds, s, jobs, njobs, k, K, C,
+    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, jobs, njobs, k, K, C,
                        R);
     return hipGetLastError();
 }
@@ -1354,7 +1354,8 @@ size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
 
 int rows_per_thread(int C, int R) {
     const int cp = padded_channels(C);
-    return (cp >= 1 && cp <= 4 && R >= 1 && R <= 5) ? RowsPerThread<1>::value : RowsPerThread<0>::value;
+    if (cp < 0 || wide_lanes(C, R) > 1) return 1;
+    return cp <= 4 ? RowsPerThread<4>::value : RowsPerThread<8>::value;
 }
 
 bool tile_ok(int C, int R, Tile t, int fields) {

@@ -70,6 +70,12 @@ FWD_CASES = [
     (20, 21, 17, 2, 3, 17),
     (33, 40, 40, 1, 2, 18),
     (1, 50, 31, 2, 2, 19),
+    # lanes whose 8 channels run past C (two lanes per pixel), eight channels per
+    # pixel slot with the runtime radius, and an odd height with two pixels per thread
+    (23, 37, 12, 2, 3, 20),
+    (29, 31, 7, 4, 3, 21),
+    (17, 9, 3, 4, 3, 22),
+    (25, 30, 2, 9, 2, 23),
 ]
 
 
