@@ -163,10 +163,12 @@ def main() -> int:
     eps_master = np.full((K, 2), float(params.eps_init))
     geps_h = torch.empty((K, 2), dtype=torch.float32, pin_memory=True)
     eps_h = torch.empty((K, 2), dtype=torch.float32, pin_memory=True)
+    ws_p = torch.empty(max(A.abc_workspace_bytes(A.ABC_WS_PD, H, W, C, params), 1), dtype=torch.uint8, device=dev)
+    gK_buf = torch.empty_like(c0)
     kstream = torch.cuda.current_stream()
 
     def step():
-        gK, _ = A.abc_pd_terminal(traj[-1], c0, v, mu, params, want_objective=False)
+        gK, _ = A.abc_pd_terminal(traj[-1], c0, v, mu, params, want_objective=False, gK=gK_buf, ws=ws_p)
         A.abc_adjoint_dynamics(traj, eps, params, gK, g0=g0, geps=geps, ws=ws_a)
         geps_h.copy_(geps, non_blocking=True)
         kstream.synchronize()
@@ -175,8 +177,8 @@ def main() -> int:
         eps_h.numpy()[:] = e_new
         eps_try.copy_(eps_h, non_blocking=True)
         A.abc_forward_dynamics(c0, eps_try, params, traj=traj2, ws=ws_f)
-        _, phit = A.abc_pd_terminal(traj2[-1], c0, v, mu, params, want_gradient=False)
-        return A.abc_pd_step(traj[-1], c0, v, mu, params, update_mu=True)
+        _, phit = A.abc_pd_terminal(traj2[-1], c0, v, mu, params, want_gradient=False, ws=ws_p)
+        return A.abc_pd_step(traj[-1], c0, v, mu, params, update_mu=True, ws=ws_p)
 
     for _ in range(args.warmup):
         step()

@@ -279,12 +279,19 @@ def abc_adjoint_dynamics(traj, eps, params: Params, gK, g0=None, geps=None, ws=N
     return g0, geps
 
 
-def abc_pd_terminal(cK, c0, v, mu, params: Params, want_gradient=True, want_objective=True):
-    """(dL~/dc at cK or None, L~ or None) -- the adjoint terminal condition (see abc.h)."""
+def abc_pd_terminal(cK, c0, v, mu, params: Params, want_gradient=True, want_objective=True, gK=None, ws=None):
+    """(dL~/dc at cK or None, L~ or None) -- the adjoint terminal condition (see abc.h).
+    ``gK`` (H x W x C) and ``ws`` (ABC_WS_PD bytes) may be passed in to avoid allocations."""
     torch = _torch()
     H, W, C = cK.shape
-    gK = torch.empty_like(cK) if want_gradient else None
-    ws, nb = _workspace(ABC_WS_PD, H, W, C, params, cK.device)
+    if want_gradient and gK is None:
+        gK = torch.empty_like(cK)
+    if not want_gradient:
+        gK = None
+    if ws is None:
+        ws, nb = _workspace(ABC_WS_PD, H, W, C, params, cK.device)
+    else:
+        nb = ws.numel()
     Lt = ct.c_double(0.0)
     p = params.to_c()
     _check(lib().abc_pd_terminal(_ptr(cK), _ptr(c0), _ptr(v), _ptr(mu), H, W, C, ct.byref(p), _ptr(gK),
@@ -293,10 +300,14 @@ def abc_pd_terminal(cK, c0, v, mu, params: Params, want_gradient=True, want_obje
     return gK, (Lt.value if want_objective else None)
 
 
-def abc_pd_step(cK, c0, v, mu, params: Params, update_mu=True, want_stats=True):
-    """Shrinkage of v and multiplier ascent, in place on v and mu; returns the stats dict."""
+def abc_pd_step(cK, c0, v, mu, params: Params, update_mu=True, want_stats=True, ws=None):
+    """Shrinkage of v and multiplier ascent, in place on v and mu; returns the stats dict.
+    ``ws`` (ABC_WS_PD bytes) may be passed in to avoid an allocation."""
     H, W, C = cK.shape
-    ws, nb = _workspace(ABC_WS_PD, H, W, C, params, cK.device)
+    if ws is None:
+        ws, nb = _workspace(ABC_WS_PD, H, W, C, params, cK.device)
+    else:
+        nb = ws.numel()
     st = AbcStats()
     p = params.to_c()
     _check(lib().abc_pd_step(_ptr(cK), _ptr(c0), H, W, C, ct.byref(p), _ptr(v), _ptr(mu), int(bool(update_mu)),
