@@ -65,3 +65,20 @@ def test_batched_wide_channels_equal_individual_solves_and_graphs():
     direct, _, _ = A.abc_solve_batched([T(x) for x in imgs], gp.replace(flags=A.ABC_FLAG_NO_GRAPHS))
     for x, y in zip(outs, direct):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("R,C,tile", [(7, 3, (32, 16)), (4, 2, (16, 16)), (3, 6, (32, 8))])
+def test_batched_default_and_runtime_radius_tiles_equal_individual_solves(R, C, tile):
+    """Two pixels per thread with a compile-time (R <= 5) and a runtime radius (R = 7),
+    and one pixel per thread for 6 channels, each in the batched launch and alone."""
+    print(f"[case] batched vs individual, R={R} C={C} tile={tile}", flush=True)
+    shapes = [(40, 57), (33, 33), (71, 24)]
+    imgs = [voronoi_image(h, w, C, 4, 0.05, 800 + i) for i, (h, w) in enumerate(shapes)]
+    gp = A.Params(K=5, R=R, alpha=20.0, max_outer=2, max_inner=2, tile_x=tile[0], tile_y=tile[1])
+    outs, stats, _ = A.abc_solve_batched([T(x) for x in imgs], gp)
+    torch.cuda.synchronize()
+    for i, x in enumerate(imgs):
+        ref = A.abc_solve(T(x), gp)
+        assert torch.equal(outs[i], ref["c"]), i
+        for key in ("K", "L", "inner_iters", "ls_evals", "outer_iters"):
+            assert stats[i][key] == ref["stats"][key], (i, key)
