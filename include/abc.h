@@ -69,7 +69,14 @@ typedef struct abc_params {
     double armijo_c;     /* sufficient-decrease constant c in (0,1)                 */
     int32_t ckpt_every;  /* 0 => full trajectory; k > 0 => checkpoint every k steps  */
     int32_t tile_x;      /* interaction tile width in pixels; 0 => library default  */
-    int32_t tile_y;      /* interaction tile height in pixels; 0 => library default */
+    int32_t tile_y;      /* interaction tile height in pixels; 0 => library default.
+                            A tile is valid when tile_y is a multiple of the pixels per
+                            thread (2 for up to 4 channels, else 1) and the workgroup,
+                            tile_x * tile_y / (pixels per thread) threads times the
+                            lanes per pixel (C/8 rounded up for 16-64 channels at
+                            R <= 3, else 1), is a whole number of 64-lane waves, at
+                            most 256 threads (1024 with several lanes per pixel), and
+                            fits in LDS; otherwise calls return ABC_EINVAL          */
     int32_t cost;        /* ABC_COST_TV or ABC_COST_QUADRATIC (see abc_solve)         */
     int32_t adj_tile_x;  /* adjoint tile width; 0 => tile_x (or library default)     */
     int32_t adj_tile_y;  /* adjoint tile height; 0 => tile_y (or library default)    */
