@@ -58,6 +58,24 @@ def test_invalid_parameters_are_rejected_on_the_host(bad):
     assert e.value.code == A.ABC_EINVAL
 
 
+@pytest.mark.parametrize("C,R,tile,ok", [
+    (3, 5, (32, 16), True), (3, 5, (32, 8), True), (3, 5, (16, 8), True),
+    (3, 5, (64, 1), False),  # two pixels per thread: the height must be even
+    (3, 5, (16, 4), False),  # 32 threads: not a whole wave
+    (3, 5, (64, 16), False),  # 512 threads
+    (2, 9, (32, 16), True), (6, 3, (32, 8), True), (6, 3, (64, 1), True),  # 6 channels: one pixel per thread
+    (31, 2, (16, 16), True), (31, 2, (32, 16), False),  # 4 lanes per pixel: 1024 and 2048 threads
+])
+def test_tile_rule_on_the_host(C, R, tile, ok):
+    p = A.Params(K=4, R=R, tile_x=tile[0], tile_y=tile[1])
+    if ok:
+        assert A.abc_workspace_bytes(A.ABC_WS_SOLVE, 40, 40, C, p) > 0
+    else:
+        with pytest.raises(A.AbcError) as e:
+            A.abc_workspace_bytes(A.ABC_WS_SOLVE, 40, 40, C, p)
+        assert e.value.code == A.ABC_EINVAL and "tile" in str(e.value)
+
+
 @pytest.mark.parametrize("shape", [(0, 4, 3), (4, 0, 3), (4, 4, 0), (4, 4, 65)])
 def test_invalid_shapes_are_rejected_before_any_launch(shape):
     L = B.lib()
