@@ -501,9 +501,35 @@ SegWs carve(void* base, int H, int W, int C) {
         SEG_HIP(hipGetLastError());                                                                 \
     } while (0)
 
+// Pinned host staging for the reads the round loop waits on: one per host
+// thread, allocated on its first use and kept until the process ends (a read
+// into pinned memory returns several microseconds sooner than one into
+// pageable memory, and the loop waits on one per round).  Layout: the flags,
+// then the IRV double and the IRC bit pattern.  NULL if the allocation failed.
+struct SegReadback {
+    int flags[kFlags];
+    double irv;
+    unsigned long long ircbits;
+};
+SegReadback* seg_readback() {
+    thread_local SegReadback* buf = nullptr;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc((void**)&buf, sizeof(SegReadback), hipHostMallocDefault) != hipSuccess) {
+            buf = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    return buf;
+}
+
 int read_flags(int* dst, const int* flags, hipStream_t st) {
-    SEG_HIP(hipMemcpyAsync(dst, flags, kFlags * sizeof(int), hipMemcpyDeviceToHost, st));
+    SegReadback* pin = seg_readback();
+    int* to = pin ? pin->flags : dst;
+    SEG_HIP(hipMemcpyAsync(to, flags, kFlags * sizeof(int), hipMemcpyDeviceToHost, st));
     SEG_HIP(hipStreamSynchronize(st));
+    if (pin) std::memcpy(dst, pin->flags, kFlags * sizeof(int));
     return ABC_OK;
 }
 
@@ -632,9 +658,14 @@ int abc_segment(const float* c, const float* c0, int H, int W, int C, float thet
     SEG_LAUNCH(irc_kernel, gb, (const double*)w.cnt, (const double*)w.s1, k, C, w.keys + 1);
     unsigned long long ircbits = 0;
     double irv = 0.0;
-    SEG_HIP(hipMemcpyAsync(&irv, w.irv, sizeof(double), hipMemcpyDeviceToHost, st));
-    SEG_HIP(hipMemcpyAsync(&ircbits, w.keys + 1, sizeof(ircbits), hipMemcpyDeviceToHost, st));
+    SegReadback* pin = seg_readback();
+    SEG_HIP(hipMemcpyAsync(pin ? &pin->irv : &irv, w.irv, sizeof(double), hipMemcpyDeviceToHost, st));
+    SEG_HIP(hipMemcpyAsync(pin ? &pin->ircbits : &ircbits, w.keys + 1, sizeof(ircbits), hipMemcpyDeviceToHost, st));
     if ((rc = read_flags(f, w.flags, st)) != ABC_OK) return rc;
+    if (pin) {
+        irv = pin->irv;
+        ircbits = pin->ircbits;
+    }
     out.nonempty = f[kNonEmpty];
     out.irv = irv;
     if (out.nonempty < 2) {
