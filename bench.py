@@ -499,7 +499,8 @@ def bench_warmstart(args) -> int:
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 solve, bf16 network",
            "data": "synthetic (held-out seeded Voronoi images)",
            "config": {"workload": "warmstart1024_rgb_r5_k50", "H": 1024, "W": 1024, "C": 3, "R": 5, "K": 50,
-                      "stop": "gap 1e-2, M <= 20, P = 10", "weights": "wsnet_k50.npy"},
+                      "stop": "gap 1e-2, M <= 20, P = 10", "weights": "wsnet_k50.npy",
+                      "warm_start": "predicted multiplier, cold controls"},
            "speedup_median": float(np.median(sp)), "fallbacks": int(sum(r["fallback"] for r in rows)),
            "plain_ms_mean": float(np.mean([r["cold_s"] for r in rows])) * 1e3, "rows": rows}
     print(json.dumps(out), flush=True)

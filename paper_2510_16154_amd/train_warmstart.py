@@ -44,6 +44,8 @@ def main(argv=None):
     ap.add_argument("--target-tol-alm", type=float, default=0.0,
                     help="ALM residual stop of the target solves (0: run --target-outer iterations)")
     ap.add_argument("--chunk", type=int, default=256, help="images solved per data chunk (one progress line each)")
+    ap.add_argument("--warm-eps", action="store_true",
+                    help="warm solves start from the predicted controls too (default: predicted multiplier only)")
     args = ap.parse_args(argv)
 
     import torch
@@ -92,7 +94,7 @@ def main(argv=None):
         pe = params.replace(max_outer=args.eval_outer, max_inner=10, tol_gap=args.tol_gap,
                             tol_alm=args.eval_tol_alm)
         cold = cold_solve(img, pe, keep_state=True)
-        warm = ws.solve(img, pe, cold=cold)
+        warm = ws.solve(img, pe, cold=cold, use_eps=args.warm_eps)
         ideal = ideal_warm_solve(img, pe, cold)
         rows.append({"seed": seed, "cold_K": cold["K"], "cold_outer": cold["outer_iters"], "cold_s": cold["seconds"],
                      "warm_outer": warm["outer_iters"], "warm_s": warm["seconds"], "warm_K": warm["K"],

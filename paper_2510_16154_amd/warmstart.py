@@ -2,12 +2,14 @@
 
 The network maps an image to a starting multiplier field mu0 and starting
 controls eps0 for ``abc_solve``; it is trained on pairs (image, final mu and
-eps) produced by the plain method itself.  The plain cold-started solve stays
-the reference: both solves run the solver's own stopping rule (the
-Lagrangian gap of Sec. 4.1, or the iteration cap), and the warm result is
-accepted only when its final TV energy is within a relative tolerance of the
-cold solve's (or below it); otherwise the cold solve is the answer.  Orchestration only; every arithmetic step is a library
-call.
+eps) produced by the plain method itself.  The warm solve uses the predicted
+multiplier with the cold controls by default (``use_eps`` adds the predicted
+controls).  The plain cold-started solve stays the reference: both solves run
+the solver's own stopping rule (the Lagrangian gap of Sec. 4.1, or the
+iteration cap), and the warm result is accepted only when its final TV energy
+is within a relative tolerance of the cold solve's (or below it); otherwise
+the cold solve is the answer.  Orchestration only; every arithmetic step is a
+library call.
 """
 from __future__ import annotations
 
@@ -102,16 +104,24 @@ class WarmStart:
         torch.cuda.synchronize()
         return TrainLog(losses, time.perf_counter() - t0)
 
-    def solve(self, img, params: B.Params, cold=None, rel_tol: float = 1e-4):
+    def solve(self, img, params: B.Params, cold=None, rel_tol: float = 1e-4, use_eps: bool = False):
         """Warm solve of one image (H x W x 3): predicted start, then the plain
         solver with its own stopping rule.  The result stands when its final
         TV energy is within rel_tol of the cold solve's (or lower) and finite;
         otherwise the cold solve is the answer and its time is added.
-        ``cold``: an earlier ``cold_solve`` result (computed here if None)."""
+        ``cold``: an earlier ``cold_solve`` result (computed here if None).
+        ``use_eps``: start from the predicted controls as well; by default only
+        the predicted multiplier is used and the controls start cold (on
+        held-out images the predicted controls leave the energy well above the
+        solved one, while the predicted multiplier shortens the multiplier loop)."""
         import torch
         t0 = time.perf_counter()
         mu0, eps0 = self.predict(img[None])
-        out = B.abc_solve(img, params, eps=eps0[0].contiguous(), mu=mu0[0].contiguous())
+        if use_eps:
+            e0 = eps0[0].contiguous()
+        else:
+            e0 = torch.full((params.K, 2), params.eps_init, dtype=torch.float32, device=img.device)
+        out = B.abc_solve(img, params, eps=e0, mu=mu0[0].contiguous())
         torch.cuda.synchronize()
         t_warm = time.perf_counter() - t0
         st = out["stats"]

@@ -92,8 +92,9 @@ def test_trained_network_gains_over_the_cold_start():
     held-out 256 x 256 images solved by the plain method (seeds outside the
     training range), the predicted start (mu0, eps0) lies closer to the solved
     (mu, eps) than the cold start (mu = 0, eps = eps_init), in the training
-    loss; and a warm solve under the gap stop ends at the cold solve's energy
-    or below (else it falls back to the cold result)."""
+    loss; and a warm solve under the gap stop (predicted multiplier with cold
+    controls, and with the predicted controls too) ends at the cold solve's
+    energy or below (else it falls back to the cold result)."""
     from paper_2510_16154_amd.warmstart import TRAINED_K50, WarmStart, cold_solve, make_dataset
     params = A.Params(K=50, R=5, max_outer=5, max_inner=10, alpha=3000.0)
     ws = WarmStart.load(TRAINED_K50, 50, params)
@@ -110,7 +111,8 @@ def test_trained_network_gains_over_the_cold_start():
     for i in range(2):
         img = x[i].contiguous()
         cold = cold_solve(img, pe)
-        warm = ws.solve(img, pe, cold=cold)
-        print(f"image {i}: cold {cold['seconds']:.3f} s K {cold['K']:.5g}; warm {warm['seconds']:.3f} s "
-              f"K {warm['K']:.5g} fallback {warm['fallback']}", flush=True)
-        assert warm["K"] <= cold["K"] * (1 + 1e-4)
+        for use_eps in (False, True):
+            warm = ws.solve(img, pe, cold=cold, use_eps=use_eps)
+            print(f"image {i}: cold {cold['seconds']:.3f} s K {cold['K']:.5g}; warm (eps {use_eps}) "
+                  f"{warm['seconds']:.3f} s K {warm['K']:.5g} fallback {warm['fallback']}", flush=True)
+            assert warm["K"] <= cold["K"] * (1 + 1e-4)
