@@ -509,14 +509,23 @@ int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* ep
         ABC_HIP(hipMemsetAsync(geps, 0, (size_t)p->K * 2 * sizeof(float), st));
         return ABC_OK;
     }
-    ABC_HIP(hipMemcpyAsync(w.pa, gK, f * sizeof(float), hipMemcpyDeviceToDevice, st));
-    float* cur = w.pa;
-    float* spare = w.pb;
+    // The first step reads gK itself and the last one writes g0 itself (through the
+    // ping-pong buffers in between), except that a single step with g0 == gK goes
+    // through a buffer and a copy.
+    const float* pin = gK;
+    float* bufs[2] = {w.pa, w.pb};
+    int nbuf = 0;
+    auto step = [&](const float* ck, int k) -> int {
+        float* out = (k == 0 && (const float*)g0 != pin) ? g0 : bufs[nbuf];
+        ABC_HIP(abc::launch_adjoint_step(ck, pin, out, eps, k, s.H, s.W, s.C, p->R, dts, ta,
+                                         w.part + (size_t)k * tiles * 2, st));
+        if (out == bufs[nbuf]) nbuf ^= 1;
+        pin = out;
+        return ABC_OK;
+    };
     if (p->ckpt_every <= 0) {
-        std::vector<const float*> states(p->K);
-        for (int k = 0; k < p->K; ++k) states[k] = traj + (size_t)k * f;
-        if ((rc = adjoint_steps(states.data(), 0, p->K, eps, s, p, dts, ta, cur, spare, w.part, tiles, st)))
-            return rc;
+        for (int k = p->K - 1; k >= 0; --k)
+            if ((rc = step(traj + (size_t)k * f, k))) return rc;
     } else {
         const int e = p->ckpt_every;
         const int nseg = (p->K + e - 1) / e;
@@ -530,11 +539,11 @@ int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* ep
             if (!dst.empty())
                 if ((rc = forward_steps(states[0], dst.data(), k0, k1 - 1, eps, s, p, dts, tf, st))) return rc;
             for (int k = k0 + 1; k < k1; ++k) states[k - k0] = w.seg + (size_t)(k - k0) * f;
-            if ((rc = adjoint_steps(states.data(), k0, k1, eps, s, p, dts, ta, cur, spare, w.part, tiles, st)))
-                return rc;
+            for (int k = k1 - 1; k >= k0; --k)
+                if ((rc = step(states[k - k0], k))) return rc;
         }
     }
-    ABC_HIP(hipMemcpyAsync(g0, cur, f * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (pin != g0) ABC_HIP(hipMemcpyAsync(g0, pin, f * sizeof(float), hipMemcpyDeviceToDevice, st));
     // dl/deps^k = -5 dt s * (raw sums of the adjoint kernel), summed in FP64
     ABC_HIP(abc::launch_reduce_rows_f64(w.part, p->K, tiles, 2, -5.0 * (double)p->dt * (double)snorm, nullptr, geps,
                                         st));

@@ -331,3 +331,21 @@ def test_gap_stop_matches_oracle(orc):
     out = A.abc_solve(T(c0), gp, decisions=ref["decisions"], eps_replay=ref["eps_log"])
     assert out["stats"]["outer_iters"] == ref["stats"]["outer_iters"]
     assert relinf(N(out["c"]), ref["c"]) < FIELD_TOL
+
+
+@pytest.mark.parametrize("K,ckpt", [(1, 0), (3, 0), (5, 2)])
+def test_adjoint_in_place_equals_separate_output(K, ckpt):
+    """dl/dc^0 may overwrite dl/dc^K (g0 == gK): same bits as a separate output,
+    for a single step, several steps and a checkpointed trajectory."""
+    H, W, C, R = 37, 29, 3, 3
+    c0 = voronoi_image(H, W, C, 3, 0.05, 31)
+    eps = rand_eps(K, 31)
+    gp = A.Params(K=K, R=R, ckpt_every=ckpt)
+    traj = A.abc_forward_dynamics(T(c0), T(eps), gp)
+    gK = T(np.random.default_rng(32).normal(size=(H, W, C)))
+    g_sep, ge_sep = A.abc_adjoint_dynamics(traj, T(eps), gp, gK.clone())
+    g_in = gK.clone()
+    g_out, ge_in = A.abc_adjoint_dynamics(traj, T(eps), gp, g_in, g0=g_in)
+    torch.cuda.synchronize()
+    assert g_out.data_ptr() == g_in.data_ptr()
+    assert torch.equal(g_in, g_sep) and torch.equal(ge_in, ge_sep)
