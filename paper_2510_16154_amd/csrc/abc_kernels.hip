@@ -362,10 +362,11 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
                     n2 = fmaf(d[ch], d[ch], n2);
                 }
                 const float t = clamp01(fmaf(-ech, n2, om));
+                // phi'/20 = t^3 (t - 1), with t - 1 exact inside the fused operation;
+                // phi = t^4 (5 - 4t) = t^3 + t^3 (t - 1)(1 - 4t) reuses it instead of forming t^4
                 const float t3 = (t * t) * t;
-                const float t4 = t3 * t;
-                float w = fmaf(-4.0f, t, 5.0f) * t4;
-                float u = t4 - t3;
+                float u = fmaf(t3, t, -t3);
+                float w = fmaf(u, fmaf(-4.0f, t, 1.0f), t3);
                 if (BORDER) {
                     w *= mj;
                     u *= mj;
@@ -688,7 +689,7 @@ __device__ __forceinline__ void adj_window_wide(const float* mc, const float* mp
             const float t2 = t * t;
             const float t3 = t2 * t;
             float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
-            float u = (t - 1.0f) * t3;
+            float u = fmaf(t3, t, -t3);  // t^3 (t - 1) in one fused operation
             if (BORDER) {
                 const float m = (row_in && (unsigned)(gx + b) < (unsigned)W) ? 1.0f : 0.0f;
                 w *= m;
