@@ -99,6 +99,43 @@ def test_forward_and_adjoint_match_oracle(orc, H, W, C, R, K, seed):
         assert np.all(N(geps) == 0)
 
 
+# Controls at the corners of the box E = [2, 1100]^2 (Sec. 3.2), the same for every
+# step or alternating between corners: eps_x = 2 keeps the kernel argument of the
+# nearest neighbours within 1e-3 of t = 1, eps_c = 1100 cuts most pairs off at the
+# edge of the support (all of them at 31 channels, where the gradient is exactly 0).
+# At (2, 1100) with 6 channels the gradient (norm 2.7e-7) is carried by pairs near
+# t = 0, where t = 1 - r is a difference of numbers close to 1 and FP32 leaves it a
+# relative error of about 2^-24 / t; the gradient's relative error is 5.7e-5 there,
+# the largest of these cases, and the same in a plain FP32 evaluation of the sums.
+BOX_CORNERS = [(2.0, 2.0), (2.0, 1100.0), (1100.0, 2.0), (1100.0, 1100.0), None]
+
+
+@pytest.mark.parametrize("C,R", [(3, 5), (6, 3), (31, 2)])
+@pytest.mark.parametrize("corner", BOX_CORNERS)
+def test_forward_and_adjoint_at_the_corners_of_the_control_box(orc, C, R, corner):
+    H, W, K = 48, 40, 4
+    print(f"[case] box corner {corner} C={C} R={R}", flush=True)
+    c0 = voronoi_image(H, W, C, 4, 0.05, 31)
+    if corner is None:
+        eps = np.array([[2.0, 1100.0], [1100.0, 2.0], [2.0, 2.0], [1100.0, 1100.0]])
+    else:
+        eps = np.tile(corner, (K, 1))
+    gp, op = both_params(orc, H, W, K=K, R=R)
+    traj = A.abc_forward_dynamics(T(c0), T(eps), gp)
+    want = orc.forward_sweep(c0, op, eps)
+    assert relinf(N(traj), want) < FIELD_TOL / 10
+    gK = np.random.default_rng(131).normal(size=(H, W, C))
+    g0, geps = A.abc_adjoint_dynamics(traj, T(eps), gp, T(gK))
+    p0, ge = orc.adjoint_sweep(want, op, gK, eps)
+    print(f"  errors: c^K {relinf(N(traj), want):.2e} p^0 {relinf(N(g0), p0):.2e} "
+          f"dl/deps {rel2(N(geps), ge):.2e} (|dl/deps| {np.linalg.norm(ge):.2e})", flush=True)
+    assert relinf(N(g0), p0) < FIELD_TOL
+    if np.linalg.norm(ge) > 0:
+        assert rel2(N(geps), ge) < FIELD_TOL
+    else:
+        assert np.all(N(geps) == 0)
+
+
 @pytest.mark.parametrize("C,R,tiles", [
     (3, 2, [(32, 16), (32, 8), (16, 16), (64, 4), (8, 16), (128, 2), (16, 8)]),
     (3, 5, [(32, 16), (64, 8), (16, 8), (32, 4)]),
