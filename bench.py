@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "dfb63b5030922e6081a77c4ee1b0bdb8b1e2d4203636697efa28120949aa3ca1",
-    "adj_step_kernel<3,5>": 11.54e6,
-    "adj_step_wide_kernel<31,2>": 2079.55e6,
+    "kernel_sha256": "be2dc61a43b46e8308ff6351ce060389c763f0e4569a6ddd0ac6a3e55476d7ee",
+    "adj_step_kernel<3,5>": 11.56e6,
+    "adj_step_wide_kernel<31,2>": 2079.54e6,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")
 

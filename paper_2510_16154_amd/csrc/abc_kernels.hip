@@ -136,15 +136,31 @@ __device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m
 
 // Stage rows [y0-R, y0+TY+R) x cols [x0-R, x0+TX+R) of a HWC field into LDS
 // slots; channels >= C and cells outside the image are 0, the mask slot is 1
-// inside the image and 0 outside.  Loads carry no branches (a cell outside
-// the image reads pixel 0 and channel indices are clamped into the pixel;
-// the values are replaced by 0 afterwards), and each pass has the loads of
-// up to four cells (two rows x two columns) in flight before it writes LDS.
-template <int CP>
-__device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__ src, int H, int W, int C,
-                                           int x0, int y0, int R, int LW, int LH) {
+// inside the image and 0 outside.  Loads carry no branches: every cell reads
+// the image pixel nearest to it (row and column clamped into the image, so
+// every address lies in the field; lanes past the staged block read its last
+// row or column, so no load leaves the block's own cache lines) and the values
+// of cells outside the image are replaced by 0 afterwards.  Element indices are 32-bit (H W C is at most
+// 4e9); with C == CP the channel offsets are constants of the load
+// instructions, otherwise they are clamped into the pixel.  Each pass has the
+// loads of up to four cells (two rows x two columns) in flight before it
+// writes LDS.
+template <int CP, bool EXACT>
+__device__ __forceinline__ void stage_cells(float* dst, const float* __restrict__ src, int H, int W, int C,
+                                            int x0, int y0, int R, int LW, int LH) {
     constexpr int NV = Slot<CP>::NV, CS = Slot<CP>::CS;
+    const unsigned WC = (unsigned)W * (unsigned)C;
     for (int ly0 = threadIdx.y; ly0 < LH; ly0 += 2 * blockDim.y) {
+        unsigned rbase[2];
+        bool row_in[2];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            // rows past the tile (no cell of theirs is written) read its last row
+            const int gy = y0 - R + min(ly0 + v * (int)blockDim.y, LH - 1);
+            const int gyc = min(max(gy, 0), H - 1);
+            row_in[v] = gy == gyc;
+            rbase[v] = (unsigned)gyc * WC;
+        }
         for (int lx0 = threadIdx.x; lx0 < LW; lx0 += 2 * blockDim.x) {
             float t[4][CS];
             bool act[4];
@@ -154,13 +170,15 @@ __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__
                 const int ly = ly0 + (u >> 1) * blockDim.y, lx = lx0 + (u & 1) * blockDim.x;
                 act[u] = ly < LH && lx < LW;
                 cell[u] = ly * LW + lx;
-                const int gy = y0 - R + ly, gx = x0 - R + lx;
-                const bool in = act[u] && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-                const float* s = src + (in ? ((size_t)gy * W + gx) * C : 0);
+                const int gx = x0 - R + min(lx, LW - 1);
+                const int gxc = min(max(gx, 0), W - 1);
+                const bool in = act[u] && row_in[u >> 1] && gx == gxc;
+                const unsigned col = EXACT ? (unsigned)gxc * (unsigned)CP : (unsigned)gxc * (unsigned)C;
+                const float* s = src + (rbase[u >> 1] + col);
 #pragma unroll
                 for (int ch = 0; ch < CS; ++ch) {
-                    const float x = ch < CP ? s[min(ch, C - 1)] : 0.0f;
-                    t[u][ch] = (in && ch < CP && ch < C) ? x : 0.0f;
+                    const float x = ch < CP ? s[EXACT ? ch : min(ch, C - 1)] : 0.0f;
+                    t[u][ch] = (in && ch < CP && (EXACT || ch < C)) ? x : 0.0f;
                 }
                 t[u][CP] = in ? 1.0f : 0.0f;
             }
@@ -179,6 +197,15 @@ __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__
             }
         }
     }
+}
+
+template <int CP>
+__device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__ src, int H, int W, int C,
+                                           int x0, int y0, int R, int LW, int LH) {
+    if (C == CP)
+        stage_cells<CP, true>(dst, src, H, W, C, x0, y0, R, LW, LH);
+    else
+        stage_cells<CP, false>(dst, src, H, W, C, x0, y0, R, LW, LH);
 }
 
 // Offset constants of a window of radius RT, written by the threads of a
