@@ -17,6 +17,8 @@
  *  - Controls are K x 2: eps[2k] = eps_x on step k, eps[2k+1] = eps_c
  *    (piecewise constant in time).
  *  - Grid spacing dx = 1/W, dy = 1/H (Def. 3.1); positions are normalised.
+ *  - Shapes: H, W >= 1, 1 <= C <= 64 and H * W * C <= 4e9 (every element
+ *    index of a field fits 32 unsigned bits); larger images give ABC_EINVAL.
  *  - All work is ordered on `stream` (a hipStream_t; NULL = the null stream).
  *    Calls that return host scalars synchronise that stream.
  *  - Return value: ABC_OK (0), a negative error or a positive warning.

@@ -137,7 +137,7 @@ float norm_factor(const abc_params* p, const Shape& s) {
 int check_shape(int H, int W, int C) {
     if (H < 1 || W < 1) return fail(ABC_EINVAL, "H and W must be >= 1");
     if (C < 1 || C > ABC_MAX_CHANNELS) return fail(ABC_EINVAL, "C must be in [1, 64]");
-    if ((double)H * (double)W * (double)C > 4.0e9) return fail(ABC_EINVAL, "image too large");
+    if ((double)H * (double)W * (double)C > 4.0e9) return fail(ABC_EINVAL, "H * W * C must be <= 4e9");
     return ABC_OK;
 }
 

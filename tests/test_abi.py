@@ -76,7 +76,7 @@ def test_tile_rule_on_the_host(C, R, tile, ok):
         assert e.value.code == A.ABC_EINVAL and "tile" in str(e.value)
 
 
-@pytest.mark.parametrize("shape", [(0, 4, 3), (4, 0, 3), (4, 4, 0), (4, 4, 65)])
+@pytest.mark.parametrize("shape", [(0, 4, 3), (4, 0, 3), (4, 4, 0), (4, 4, 65), (70000, 70000, 1), (1, 2**31 - 1, 2)])
 def test_invalid_shapes_are_rejected_before_any_launch(shape):
     L = B.lib()
     p = A.Params().to_c()
