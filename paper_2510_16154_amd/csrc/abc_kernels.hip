@@ -921,7 +921,8 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
     const size_t i = (size_t)blk * blockDim.x + threadIdx.x;
     float obj = 0.0f, tv = 0.0f, fid = 0.0f;
     if (i < N) {
-        const int r = (int)(i / W), q = (int)(i % W);
+        const unsigned iu = (unsigned)i;  // H W C <= 4e9: pixel indices fit 32 bits
+        const int r = (int)(iu / (unsigned)W), q = (int)(iu % (unsigned)W);
         const float inv_rho = 1.0f / rho;
         const bool xl = q - 1 >= 1, xr = q + 1 <= W - 2, yu = r - 1 >= 1, yd = r + 1 <= H - 2;
         float sh2 = 0.0f, nv2 = 0.0f, nf2 = 0.0f, ng2 = 0.0f;
@@ -1027,7 +1028,8 @@ __device__ __forceinline__ void pd_block(const float* __restrict__ c, const floa
     const float inv_rho = 1.0f / rho;
     float qv[kPdQuantities] = {0, 0, 0, 0, 0, 0, 0};
     if (i < N) {
-        const int r = (int)(i / W), q = (int)(i % W);
+        const unsigned iu = (unsigned)i;  // H W C <= 4e9: pixel indices fit 32 bits
+        const int r = (int)(iu / (unsigned)W), q = (int)(iu % (unsigned)W);
         float na2 = 0.0f, ng2 = 0.0f, sf = 0.0f;
 #pragma unroll
         for (int ch = 0; ch < CP; ++ch) {
@@ -1053,19 +1055,26 @@ __device__ __forceinline__ void pd_block(const float* __restrict__ c, const floa
         qv[6] = nv;
     }
     __syncthreads();
-    const size_t n2c = 2 * (size_t)C;
+    // Entries are indexed from the workgroup's first pixel p0 (32-bit: at most
+    // blockDim.x * 2C of them); row and column come from p0's in 32-bit division.
+    const unsigned n2c = 2u * (unsigned)C;
     const size_t pend = p0 + blockDim.x < N ? p0 + blockDim.x : N;
-    const size_t e0 = p0 * n2c, e1 = pend * n2c;
+    const unsigned nloc = (unsigned)(pend > p0 ? pend - p0 : 0) * n2c;
+    const unsigned p0u = (unsigned)p0;  // H W C <= 4e9: pixel indices fit 32 bits
+    const unsigned r0 = p0u / (unsigned)W, q0 = p0u % (unsigned)W;
     float svg = 0.0f, muvg = 0.0f, sh2 = 0.0f;
-    for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const size_t px = e / n2c;
-        const int rem = (int)(e - px * n2c);
+    for (unsigned el = threadIdx.x; el < nloc; el += blockDim.x) {
+        const unsigned lp = el / n2c;
+        const int rem = (int)(el - lp * n2c);
         const int dim = rem >= C;
         const int ch = rem - dim * C;
-        const int r = (int)(px / W), q = (int)(px % W);
+        const size_t px = p0 + lp;
+        const unsigned qq = q0 + lp;
+        const int r = (int)(r0 + qq / (unsigned)W), q = (int)(qq % (unsigned)W);
+        const size_t e = p0 * (size_t)n2c + el;
         const float g = dim == 0 ? grad_x(c, px, q, W, C, ch, inv2dx) : grad_y(c, px, r, H, W, C, ch, inv2dy);
         const float m = mu[e];
-        const float vn = fac_s[px - p0] * (g - m * inv_rho);
+        const float vn = fac_s[lp] * (g - m * inv_rho);
         const float mn = update_mu ? fmaf(gamma, vn - g, m) : m;
         v[e] = vn;
         if (update_mu) mu[e] = mn;
