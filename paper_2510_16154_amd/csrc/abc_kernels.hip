@@ -912,7 +912,10 @@ __device__ __forceinline__ float grad_y(const float* __restrict__ c, size_t i, i
 // gK = area [ div(mu + rho (v - grad c)) + alpha (c - c0) ], div = -grad#^T, and the
 // workgroup sums of the per-pixel objective rho/2 |v - g + mu/rho|^2 + |v| + alpha/2 |c - c0|^2,
 // of |grad c| and of |c - c0|^2 (kTermQuantities values per workgroup).
-template <int CP>
+// FAST: C == CP and v, mu given, so the channel loop and the loads carry no
+// conditions and the scheduler can put a pixel's loads of every channel in
+// flight together.
+template <int CP, bool FAST>
 __device__ __forceinline__ void terminal_block(const float* __restrict__ c, const float* __restrict__ c0,
                                                const float* __restrict__ v, const float* __restrict__ mu, int H, int W,
                                                int C, float rho, float alpha, float area, float inv2dx, float inv2dy,
@@ -924,18 +927,35 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
         const unsigned iu = (unsigned)i;  // H W C <= 4e9: pixel indices fit 32 bits
         const int r = (int)(iu / (unsigned)W), q = (int)(iu % (unsigned)W);
         const float inv_rho = 1.0f / rho;
+        // gx, gy at i exist for 1 <= q <= W-2 (rows likewise); the divergence takes
+        // the neighbours whose own gradient exists (xr: q+1 <= W-2, ...).  Every
+        // load is unconditional, at the neighbour's index or at i where the term
+        // does not exist, and a missing divergence term is multiplied by 0 (no
+        // branch the compiler could sink the loads into), so the loads of a pixel
+        // are in flight together.  For finite fields the results equal those of
+        // skipping the term bit for bit (dv is never -0, so adding a signed zero
+        // leaves it unchanged); a non-finite v, mu or c at a border pixel makes
+        // its dropped term, and so its gradient entry, NaN, as its objective
+        // terms already are.
+        const bool gxi = q >= 1 && q <= W - 2, gyi = r >= 1 && r <= H - 2;
         const bool xl = q - 1 >= 1, xr = q + 1 <= W - 2, yu = r - 1 >= 1, yd = r + 1 <= H - 2;
+        const size_t sW = (size_t)W;
+        const size_t ixp = gxi ? i + 1 : i, ixm = gxi ? i - 1 : i, iyp = gyi ? i + sW : i, iym = gyi ? i - sW : i;
+        const size_t jr = xr ? i + 1 : i, jl = xl ? i - 1 : i, jd = yd ? i + sW : i, ju = yu ? i - sW : i;
+        const size_t jrr = xr ? i + 2 : i, jll = xl ? i - 2 : i, jdd = yd ? i + 2 * sW : i, juu = yu ? i - 2 * sW : i;
+        const float mr = xr ? 1.0f : 0.0f, ml = xl ? 1.0f : 0.0f, md = yd ? 1.0f : 0.0f, mu_ = yu ? 1.0f : 0.0f;
         float sh2 = 0.0f, nv2 = 0.0f, nf2 = 0.0f, ng2 = 0.0f;
 #pragma unroll
         for (int ch = 0; ch < CP; ++ch) {
-            if (ch >= C) break;
+            if (!FAST && ch >= C) break;
             const float cc = c[i * C + ch];
-            const float gx = grad_x(c, i, q, W, C, ch, inv2dx);
-            const float gy = grad_y(c, i, r, H, W, C, ch, inv2dy);
-            const float vx = v ? v[(i * 2 + 0) * C + ch] : 0.0f;
-            const float vy = v ? v[(i * 2 + 1) * C + ch] : 0.0f;
-            const float mx = mu ? mu[(i * 2 + 0) * C + ch] : 0.0f;
-            const float my = mu ? mu[(i * 2 + 1) * C + ch] : 0.0f;
+            // where the gradient does not exist both indices are i and the difference is +0
+            const float gx = (c[ixp * C + ch] - c[ixm * C + ch]) * inv2dx;
+            const float gy = (c[iyp * C + ch] - c[iym * C + ch]) * inv2dy;
+            const float vx = (FAST || v) ? v[(i * 2 + 0) * C + ch] : 0.0f;
+            const float vy = (FAST || v) ? v[(i * 2 + 1) * C + ch] : 0.0f;
+            const float mx = (FAST || mu) ? mu[(i * 2 + 0) * C + ch] : 0.0f;
+            const float my = (FAST || mu) ? mu[(i * 2 + 1) * C + ch] : 0.0f;
             const float shx = fmaf(mx, inv_rho, vx - gx);
             const float shy = fmaf(my, inv_rho, vy - gy);
             sh2 = fmaf(shx, shx, fmaf(shy, shy, sh2));
@@ -943,35 +963,39 @@ __device__ __forceinline__ void terminal_block(const float* __restrict__ c, cons
             ng2 = fmaf(gx, gx, fmaf(gy, gy, ng2));
             const float e = cc - c0[i * C + ch];
             nf2 = fmaf(e, e, nf2);
-            if (pK) {
+        }
+        // the gradient output in a loop of its own, so that a channel's loads do not
+        // wait behind the previous channel's store
+        if (pK) {
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) {
+                if (!FAST && ch >= C) break;
+                const float cc = c[i * C + ch];
+                const float e = cc - c0[i * C + ch];
                 float dv = 0.0f;
-                if (xr) {
-                    const size_t j = i + 1;
-                    const float g = (c[(j + 1) * C + ch] - cc) * inv2dx;
-                    const float vv = v ? v[(j * 2 + 0) * C + ch] : 0.0f;
-                    const float mm = mu ? mu[(j * 2 + 0) * C + ch] : 0.0f;
-                    dv = fmaf(fmaf(rho, vv - g, mm), inv2dx, dv);
+                {
+                    const float g = (c[jrr * C + ch] - cc) * inv2dx;
+                    const float vv = (FAST || v) ? v[(jr * 2 + 0) * C + ch] : 0.0f;
+                    const float mm = (FAST || mu) ? mu[(jr * 2 + 0) * C + ch] : 0.0f;
+                    dv = fmaf(fmaf(rho, vv - g, mm) * mr, inv2dx, dv);
                 }
-                if (xl) {
-                    const size_t j = i - 1;
-                    const float g = (cc - c[(j - 1) * C + ch]) * inv2dx;
-                    const float vv = v ? v[(j * 2 + 0) * C + ch] : 0.0f;
-                    const float mm = mu ? mu[(j * 2 + 0) * C + ch] : 0.0f;
-                    dv = fmaf(-fmaf(rho, vv - g, mm), inv2dx, dv);
+                {
+                    const float g = (cc - c[jll * C + ch]) * inv2dx;
+                    const float vv = (FAST || v) ? v[(jl * 2 + 0) * C + ch] : 0.0f;
+                    const float mm = (FAST || mu) ? mu[(jl * 2 + 0) * C + ch] : 0.0f;
+                    dv = fmaf(-fmaf(rho, vv - g, mm) * ml, inv2dx, dv);
                 }
-                if (yd) {
-                    const size_t j = i + W;
-                    const float g = (c[(j + W) * C + ch] - cc) * inv2dy;
-                    const float vv = v ? v[(j * 2 + 1) * C + ch] : 0.0f;
-                    const float mm = mu ? mu[(j * 2 + 1) * C + ch] : 0.0f;
-                    dv = fmaf(fmaf(rho, vv - g, mm), inv2dy, dv);
+                {
+                    const float g = (c[jdd * C + ch] - cc) * inv2dy;
+                    const float vv = (FAST || v) ? v[(jd * 2 + 1) * C + ch] : 0.0f;
+                    const float mm = (FAST || mu) ? mu[(jd * 2 + 1) * C + ch] : 0.0f;
+                    dv = fmaf(fmaf(rho, vv - g, mm) * md, inv2dy, dv);
                 }
-                if (yu) {
-                    const size_t j = i - W;
-                    const float g = (cc - c[(j - W) * C + ch]) * inv2dy;
-                    const float vv = v ? v[(j * 2 + 1) * C + ch] : 0.0f;
-                    const float mm = mu ? mu[(j * 2 + 1) * C + ch] : 0.0f;
-                    dv = fmaf(-fmaf(rho, vv - g, mm), inv2dy, dv);
+                {
+                    const float g = (cc - c[juu * C + ch]) * inv2dy;
+                    const float vv = (FAST || v) ? v[(ju * 2 + 1) * C + ch] : 0.0f;
+                    const float mm = (FAST || mu) ? mu[(ju * 2 + 1) * C + ch] : 0.0f;
+                    dv = fmaf(-fmaf(rho, vv - g, mm) * mu_, inv2dy, dv);
                 }
                 pK[i * C + ch] = area * fmaf(alpha, e, dv);
             }
@@ -996,8 +1020,12 @@ terminal_kernel(const float* __restrict__ c, const float* __restrict__ c0, const
                 const float* __restrict__ mu, int H, int W, int C, float rho, float alpha, float area,
                 float inv2dx, float inv2dy, float* __restrict__ pK, float* __restrict__ part) {
     __shared__ float red[16];
-    terminal_block<CP>(c, c0, v, mu, H, W, C, rho, alpha, area, inv2dx, inv2dy, pK, part,
-                       xcd_tile(blockIdx.x, gridDim.x), red);
+    if (C == CP && v && mu)
+        terminal_block<CP, true>(c, c0, v, mu, H, W, CP, rho, alpha, area, inv2dx, inv2dy, pK, part,
+                                 xcd_tile(blockIdx.x, gridDim.x), red);
+    else
+        terminal_block<CP, false>(c, c0, v, mu, H, W, C, rho, alpha, area, inv2dx, inv2dy, pK, part,
+                                  xcd_tile(blockIdx.x, gridDim.x), red);
 }
 
 // Terminal condition / objective of several images: jobs[j].start is the first
@@ -1008,8 +1036,12 @@ terminal_batched_kernel(const PixJob* __restrict__ jobs, int njobs, int C, float
     __shared__ float red[16];
     const int g = xcd_tile(blockIdx.x, gridDim.x);
     const PixJob& J = jobs[find_job(jobs, njobs, g)];
-    terminal_block<CP>(J.c, J.c0, J.v, J.mu, J.H, J.W, C, rho, alpha, J.area, J.inv2dx, J.inv2dy, J.pK, J.part,
-                       g - J.start, red);
+    if (C == CP && J.v && J.mu)
+        terminal_block<CP, true>(J.c, J.c0, J.v, J.mu, J.H, J.W, CP, rho, alpha, J.area, J.inv2dx, J.inv2dy, J.pK,
+                                 J.part, g - J.start, red);
+    else
+        terminal_block<CP, false>(J.c, J.c0, J.v, J.mu, J.H, J.W, C, rho, alpha, J.area, J.inv2dx, J.inv2dy, J.pK,
+                                  J.part, g - J.start, red);
 }
 
 // v = shrink(grad c - mu/rho) jointly over the 2C components of each pixel;
