@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "846ad3bb3745bc7f2ab851bc33b714d4325ce7019c4cb6ca542fd169a18b7450",
+    "kernel_sha256": "76a0de6c940cddfd0b0d8e78f0305e398bd15bd6e6dd6be3413d7aad2700974b",
     "adj_step_kernel<3,5>": 11.56e6,
     "adj_step_wide_kernel<31,2>": 2079.54e6,
 }

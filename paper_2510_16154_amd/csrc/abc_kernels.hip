@@ -899,14 +899,21 @@ reduce_jobs_kernel(const RedJob* __restrict__ jobs, int nq) {
 // below a range are mostly in the same L2.  CP is the padded channel count:
 // the channel loops unroll and every load of a pixel is in flight at once.
 
+// Centred differences of grad# (Def. 3.1), 0 where the stencil leaves the image.
+// The loads are unconditional: where the difference does not exist both indices
+// are i, and x - x = +0 gives the 0 bit for bit for finite fields.
 __device__ __forceinline__ float grad_x(const float* __restrict__ c, size_t i, int q, int W, int C, int ch,
                                         float inv2dx) {
-    return (q >= 1 && q <= W - 2) ? (c[(i + 1) * C + ch] - c[(i - 1) * C + ch]) * inv2dx : 0.0f;
+    const bool ok = q >= 1 && q <= W - 2;
+    const size_t a = ok ? i + 1 : i, b = ok ? i - 1 : i;
+    return (c[a * C + ch] - c[b * C + ch]) * inv2dx;
 }
 
 __device__ __forceinline__ float grad_y(const float* __restrict__ c, size_t i, int r, int H, int W, int C,
                                         int ch, float inv2dy) {
-    return (r >= 1 && r <= H - 2) ? (c[(i + W) * C + ch] - c[(i - W) * C + ch]) * inv2dy : 0.0f;
+    const bool ok = r >= 1 && r <= H - 2;
+    const size_t a = ok ? i + (size_t)W : i, b = ok ? i - (size_t)W : i;
+    return (c[a * C + ch] - c[b * C + ch]) * inv2dy;
 }
 
 // gK = area [ div(mu + rho (v - grad c)) + alpha (c - c0) ], div = -grad#^T, and the
@@ -1048,8 +1055,9 @@ terminal_batched_kernel(const PixJob* __restrict__ jobs, int njobs, int C, float
 // mu += gamma (v - grad c) when update_mu.  Partial sums (kPdQuantities).
 // Two passes over the workgroup's pixel range: one thread per pixel finds the
 // shrink factor and the per-pixel norms, then one thread per v/mu entry
-// (consecutive threads on consecutive floats) writes v and mu.
-template <int CP>
+// (consecutive threads on consecutive floats) writes v and mu.  EXACT: C == CP,
+// so the channel loop has no conditions and 2C is a constant.
+template <int CP, bool EXACT>
 __device__ __forceinline__ void pd_block(const float* __restrict__ c, const float* __restrict__ c0,
                                          float* __restrict__ v, float* __restrict__ mu, int update_mu, int H, int W,
                                          int C, float rho, float gamma, float inv2dx, float inv2dy,
@@ -1065,7 +1073,7 @@ __device__ __forceinline__ void pd_block(const float* __restrict__ c, const floa
         float na2 = 0.0f, ng2 = 0.0f, sf = 0.0f;
 #pragma unroll
         for (int ch = 0; ch < CP; ++ch) {
-            if (ch >= C) break;
+            if (!EXACT && ch >= C) break;
             const float gx = grad_x(c, i, q, W, C, ch, inv2dx);
             const float gy = grad_y(c, i, r, H, W, C, ch, inv2dy);
             const float ax = gx - mu[(i * 2 + 0) * C + ch] * inv_rho;
@@ -1095,26 +1103,46 @@ __device__ __forceinline__ void pd_block(const float* __restrict__ c, const floa
     const unsigned p0u = (unsigned)p0;  // H W C <= 4e9: pixel indices fit 32 bits
     const unsigned r0 = p0u / (unsigned)W, q0 = p0u % (unsigned)W;
     float svg = 0.0f, muvg = 0.0f, sh2 = 0.0f;
-    for (unsigned el = threadIdx.x; el < nloc; el += blockDim.x) {
-        const unsigned lp = el / n2c;
-        const int rem = (int)(el - lp * n2c);
-        const int dim = rem >= C;
-        const int ch = rem - dim * C;
-        const size_t px = p0 + lp;
-        const unsigned qq = q0 + lp;
-        const int r = (int)(r0 + qq / (unsigned)W), q = (int)(qq % (unsigned)W);
-        const size_t e = p0 * (size_t)n2c + el;
-        const float g = dim == 0 ? grad_x(c, px, q, W, C, ch, inv2dx) : grad_y(c, px, r, H, W, C, ch, inv2dy);
-        const float m = mu[e];
-        const float vn = fac_s[lp] * (g - m * inv_rho);
-        const float mn = update_mu ? fmaf(gamma, vn - g, m) : m;
-        v[e] = vn;
-        if (update_mu) mu[e] = mn;
-        const float vg = vn - g;
-        svg = fmaf(vg, vg, svg);
-        muvg = fmaf(mn, vg, muvg);
-        const float sh = fmaf(mn, inv_rho, vg);
-        sh2 = fmaf(sh, sh, sh2);
+    // two entries per pass (el and el + blockDim.x), loaded together; the sums
+    // take them in the order of a one-entry loop
+    for (unsigned el0 = threadIdx.x; el0 < nloc; el0 += 2 * blockDim.x) {
+        float g[2], m[2];
+        size_t e[2];
+        unsigned lps[2];
+        bool act[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            act[u] = el0 + u * blockDim.x < nloc;
+            const unsigned el = act[u] ? el0 + u * blockDim.x : el0;  // a spare lane reloads el0
+            const unsigned lp = el / n2c;
+            const int rem = (int)(el - lp * n2c);
+            const int dim = rem >= C;
+            const int ch = rem - dim * C;
+            const size_t px = p0 + lp;
+            const unsigned qq = q0 + lp;
+            const int r = (int)(r0 + qq / (unsigned)W), q = (int)(qq % (unsigned)W);
+            e[u] = p0 * (size_t)n2c + el;
+            // grad_x or grad_y of the entry without a branch (dim differs between lanes)
+            const bool ok = dim == 0 ? (q >= 1 && q <= W - 2) : (r >= 1 && r <= H - 2);
+            const size_t step = dim == 0 ? 1 : (size_t)W;
+            const size_t ia = ok ? px + step : px, ib = ok ? px - step : px;
+            g[u] = (c[ia * C + ch] - c[ib * C + ch]) * (dim == 0 ? inv2dx : inv2dy);
+            m[u] = mu[e[u]];
+            lps[u] = lp;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!act[u]) break;
+            const float vn = fac_s[lps[u]] * (g[u] - m[u] * inv_rho);
+            const float mn = update_mu ? fmaf(gamma, vn - g[u], m[u]) : m[u];
+            v[e[u]] = vn;
+            if (update_mu) mu[e[u]] = mn;
+            const float vg = vn - g[u];
+            svg = fmaf(vg, vg, svg);
+            muvg = fmaf(mn, vg, muvg);
+            const float sh = fmaf(mn, inv_rho, vg);
+            sh2 = fmaf(sh, sh, sh2);
+        }
     }
     qv[0] = svg;
     qv[5] += muvg;
@@ -1133,8 +1161,12 @@ pd_step_kernel(const float* __restrict__ c, const float* __restrict__ c0, float*
                float inv2dx, float inv2dy, float* __restrict__ part) {
     __shared__ float red[16];
     __shared__ float fac_s[kMaxThreads];
-    pd_block<CP>(c, c0, v, mu, update_mu, H, W, C, rho, gamma, inv2dx, inv2dy, part,
-                 xcd_tile(blockIdx.x, gridDim.x), red, fac_s);
+    if (C == CP)
+        pd_block<CP, true>(c, c0, v, mu, update_mu, H, W, CP, rho, gamma, inv2dx, inv2dy, part,
+                           xcd_tile(blockIdx.x, gridDim.x), red, fac_s);
+    else
+        pd_block<CP, false>(c, c0, v, mu, update_mu, H, W, C, rho, gamma, inv2dx, inv2dy, part,
+                            xcd_tile(blockIdx.x, gridDim.x), red, fac_s);
 }
 
 template <int CP>
@@ -1144,8 +1176,12 @@ pd_step_batched_kernel(const PixJob* __restrict__ jobs, int njobs, int update_mu
     __shared__ float fac_s[kMaxThreads];
     const int g = xcd_tile(blockIdx.x, gridDim.x);
     const PixJob& J = jobs[find_job(jobs, njobs, g)];
-    pd_block<CP>(J.c, J.c0, J.v, J.mu, update_mu, J.H, J.W, C, rho, gamma, J.inv2dx, J.inv2dy, J.part,
-                 g - J.start, red, fac_s);
+    if (C == CP)
+        pd_block<CP, true>(J.c, J.c0, J.v, J.mu, update_mu, J.H, J.W, CP, rho, gamma, J.inv2dx, J.inv2dy, J.part,
+                           g - J.start, red, fac_s);
+    else
+        pd_block<CP, false>(J.c, J.c0, J.v, J.mu, update_mu, J.H, J.W, C, rho, gamma, J.inv2dx, J.inv2dy, J.part,
+                            g - J.start, red, fac_s);
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
