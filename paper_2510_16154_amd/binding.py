@@ -91,7 +91,24 @@ class Params:
     stop_K: float = 0.0  # > 0: stop once the TV energy K reaches this value
     tol_gap: float = 0.0  # > 0: stop once L changes by less than this (relative) between iterations
 
+    def __setattr__(self, name, value):
+        # the converted struct (see to_c) is dropped whenever a field is assigned;
+        # the two boxes are stored as tuples so that they cannot change in place
+        if name in ("eps_min", "eps_max"):
+            value = tuple(float(x) for x in value)
+        object.__setattr__(self, name, value)
+        object.__setattr__(self, "_c", None)
+
     def to_c(self) -> AbcParams:
+        """The ``abc_params`` struct of these values, converted once and kept until
+        a field is assigned (the library only reads it)."""
+        c = self.__dict__.get("_c")
+        if c is None:
+            c = self._convert()
+            object.__setattr__(self, "_c", c)
+        return c
+
+    def _convert(self) -> AbcParams:
         p = AbcParams()
         for f in fields(self):
             val = getattr(self, f.name)
@@ -412,7 +429,7 @@ def abc_autotune(c0, params: Params, cache_path=None):
     H, W, C = c0.shape
     nb = abc_workspace_bytes(ABC_WS_TUNE, H, W, C, params)
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=c0.device)
-    p = params.to_c()
+    p = params._convert()  # a fresh struct: the library writes the tuned tiles into it
     us = (ct.c_double * 2)()
     path = cache_path.encode() if cache_path else None
     _check(lib().abc_autotune(_ptr(c0), H, W, C, ct.byref(p), path, ct.c_void_p(ws.data_ptr()), nb, _stream(), us))

@@ -113,3 +113,16 @@ def test_segment_entry_points_check_arguments_on_the_host():
     need = B.abc_segment_workspace_bytes(8, 8, 3)
     assert L.abc_segment(dummy, dummy, 8, 8, 3, ct.c_float(0.02), None, None, ct.byref(st), dummy, need - 1,
                          None) == A.ABC_EINVAL
+
+
+def test_params_struct_is_converted_once_and_follows_assignments():
+    p = A.Params(K=50, R=5)
+    c = p.to_c()
+    assert p.to_c() is c and (c.K, c.R) == (50, 5)
+    p.K = 9
+    assert p.to_c() is not c and p.to_c().K == 9 and c.K == 50
+    p.eps_min = [3, 4]
+    assert p.eps_min == (3.0, 4.0) and tuple(p.to_c().eps_min) == (3.0, 4.0)
+    q = p.replace(R=2)
+    assert q.to_c().R == 2 and p.to_c().R == 5
+    assert p == A.Params(K=9, R=5, eps_min=(3.0, 4.0))
