@@ -167,18 +167,28 @@ def test_constant_image_is_a_bitwise_fixed_point(C):
     assert np.all(traj == 0.4375)
 
 
-def test_terminal_and_pd_step_match_oracle(orc):
-    H, W, C = 37, 45, 3
-    rng = np.random.default_rng(31)
+# C = 3 and 31 with v, mu given take the pixel kernels' condition-free channel
+# loops; 5 channels (padded to 8), 1 channel on a 2-pixel-wide image and NULL
+# v, mu take the general loops.
+@pytest.mark.parametrize("H,W,C,with_vmu", [(37, 45, 3, True), (29, 33, 5, True), (23, 17, 31, True),
+                                            (31, 26, 3, False), (19, 2, 1, True)])
+def test_terminal_and_pd_step_match_oracle(orc, H, W, C, with_vmu):
+    print(f"[case] terminal/pd H={H} W={W} C={C} v,mu={'given' if with_vmu else 'NULL'}", flush=True)
+    rng = np.random.default_rng(31 + C)
     c0 = voronoi_image(H, W, C, 4, 0.05, 31)
     c = np.clip(c0 + rng.normal(scale=0.02, size=c0.shape), 0, 1).astype(np.float32)
     v = rng.normal(scale=20.0, size=(H, W, 2, C)).astype(np.float32)
     mu = rng.normal(scale=0.5, size=(H, W, 2, C)).astype(np.float32)
+    if not with_vmu:
+        v[:] = 0.0
+        mu[:] = 0.0
     gp, op = both_params(orc, H, W, alpha=40.0)
-    gK, Lt = A.abc_pd_terminal(T(c), T(c0), T(v), T(mu), gp)
+    gK, Lt = A.abc_pd_terminal(T(c), T(c0), T(v) if with_vmu else None, T(mu) if with_vmu else None, gp)
     pK, Lt_o = orc.terminal(c, c0, v, mu, op)
     assert relinf(N(gK), pK) < FIELD_TOL
     assert abs(Lt - Lt_o) / abs(Lt_o) < ENERGY_TOL
+    if not with_vmu:
+        return
     vt, mt = T(v), T(mu)
     st = A.abc_pd_step(T(c), T(c0), vt, mt, gp, update_mu=True)
     vo, mo, E = orc.pd_step(c, c0, v, mu, op, update_mu=True)
