@@ -145,15 +145,18 @@ static double dkern(const or_params* P, double r)
 /* one explicit Euler step:                                             */
 /*   c_i <- c_i + dt * s * sum_{j in W(i)} phi(r_ij) (c_j - c_i),       */
 /*   r_ij = ex/2 |x_j - x_i|^2 + ec/2 |c_j - c_i|^2.                    */
-void or_forward_step(const double* c, double* cn, int H, int W, int C,
-                     const or_params* P, double ex, double ec)
+int or_forward_step(const double* c, double* cn, int H, int W, int C,
+                    const or_params* P, double ex, double ec)
 {
     const double dx = 1.0 / W, dy = 1.0 / H;
     const int R = P->R;
+    /* per-row scratch: the force F and the differences d of one pixel */
+    double* scratch = (double*)malloc(sizeof(double) * 2 * (size_t)H * (size_t)C);
+    if (!scratch) return OR_ENOMEM;
 #pragma omp parallel for schedule(static)
     for (int r = 0; r < H; ++r) {
-        double* F = (double*)malloc(sizeof(double) * (size_t)C);
-        double* d = (double*)malloc(sizeof(double) * (size_t)C);
+        double* F = scratch + 2 * (size_t)r * C;
+        double* d = F + C;
         for (int q = 0; q < W; ++q) {
             const double* ci = c + ((size_t)r * W + q) * C;
             for (int ch = 0; ch < C; ++ch) F[ch] = 0.0;
@@ -178,20 +181,23 @@ void or_forward_step(const double* c, double* cn, int H, int W, int C,
             double* co = cn + ((size_t)r * W + q) * C;
             for (int ch = 0; ch < C; ++ch) co[ch] = ci[ch] + P->dt * P->s * F[ch];
         }
-        free(F);
-        free(d);
     }
+    free(scratch);
+    return OR_OK;
 }
 
 /* Forward sweep: traj holds K+1 fields, traj[0] = c0. */
-void or_forward_sweep(const double* c0, int H, int W, int C, const or_params* P,
-                      const double* eps, double* traj)
+int or_forward_sweep(const double* c0, int H, int W, int C, const or_params* P,
+                     const double* eps, double* traj)
 {
     const size_t n = (size_t)H * W * C;
     memcpy(traj, c0, n * sizeof(double));
-    for (int k = 0; k < P->K; ++k)
-        or_forward_step(traj + (size_t)k * n, traj + (size_t)(k + 1) * n, H, W, C, P,
-                        eps[2 * k], eps[2 * k + 1]);
+    for (int k = 0; k < P->K; ++k) {
+        int rc = or_forward_step(traj + (size_t)k * n, traj + (size_t)(k + 1) * n, H, W, C, P,
+                                 eps[2 * k], eps[2 * k + 1]);
+        if (rc) return rc;
+    }
+    return OR_OK;
 }
 
 /* ------------------------------------------------------------------ */
@@ -202,17 +208,26 @@ void or_forward_sweep(const double* c0, int H, int W, int C, const or_params* P,
 /*   dl/d ex = dt s/2 sum_i sum_j phi' d2_ij   (p_i . D_ij)              */
 /*   dl/d ec = dt s/2 sum_i sum_j phi' |D_ij|^2 (p_i . D_ij)             */
 /* with D_ij = c_j - c_i, r and phi at (c^k, eps^k) and p = p^{k+1}.     */
-void or_adjoint_step(const double* c, const double* p, double* pn, int H, int W, int C,
-                     const or_params* P, double ex, double ec, double* gk /*[2]*/)
+int or_adjoint_step(const double* c, const double* p, double* pn, int H, int W, int C,
+                    const or_params* P, double ex, double ec, double* gk /*[2]*/)
 {
     const double dx = 1.0 / W, dy = 1.0 / H;
     const int R = P->R;
+    /* per-row partial sums of the two control integrands, and per-row scratch
+       (accumulator and differences of one pixel) */
     double* rowx = (double*)calloc((size_t)H, sizeof(double));
     double* rowc = (double*)calloc((size_t)H, sizeof(double));
+    double* scratch = (double*)malloc(sizeof(double) * 2 * (size_t)H * (size_t)C);
+    if (!rowx || !rowc || !scratch) {
+        free(rowx);
+        free(rowc);
+        free(scratch);
+        return OR_ENOMEM;
+    }
 #pragma omp parallel for schedule(static)
     for (int r = 0; r < H; ++r) {
-        double* acc = (double*)malloc(sizeof(double) * (size_t)C);
-        double* d = (double*)malloc(sizeof(double) * (size_t)C);
+        double* acc = scratch + 2 * (size_t)r * C;
+        double* d = acc + C;
         double sx = 0.0, sc = 0.0;
         for (int q = 0; q < W; ++q) {
             const size_t i = ((size_t)r * W + q) * C;
@@ -252,8 +267,6 @@ void or_adjoint_step(const double* c, const double* p, double* pn, int H, int W,
         }
         rowx[r] = sx;
         rowc[r] = sc;
-        free(acc);
-        free(d);
     }
     double tx = 0.0, tc = 0.0;
     for (int r = 0; r < H; ++r) {
@@ -264,6 +277,8 @@ void or_adjoint_step(const double* c, const double* p, double* pn, int H, int W,
     gk[1] = P->dt * 0.5 * P->s * tc;
     free(rowx);
     free(rowc);
+    free(scratch);
+    return OR_OK;
 }
 
 /* Adjoint sweep from p^K = pK back to p^0; geps[k*2+{0,1}] = dl/d eps^k. */
@@ -280,8 +295,13 @@ int or_adjoint_sweep(const double* traj, int H, int W, int C, const or_params* P
     }
     memcpy(a, pK, n * sizeof(double));
     for (int k = P->K - 1; k >= 0; --k) {
-        or_adjoint_step(traj + (size_t)k * n, a, b, H, W, C, P, eps[2 * k], eps[2 * k + 1],
-                        geps + 2 * k);
+        int rc = or_adjoint_step(traj + (size_t)k * n, a, b, H, W, C, P, eps[2 * k], eps[2 * k + 1],
+                                 geps + 2 * k);
+        if (rc) {
+            free(a);
+            free(b);
+            return rc;
+        }
         double* t = a;
         a = b;
         b = t;
@@ -336,14 +356,19 @@ void or_div(const double* w, int H, int W, int C, double* out)
 /* Energies: TV and fidelity (eq. cost_TV), the regularised Lagrangian  */
 /* L (eq. cost_tv_regular) and the completed square L~ (eq.              */
 /* complete_square), plus the residual of v - grad c.                    */
-void or_energies_eval(const double* c, const double* c0, const double* v, const double* mu,
-                      int H, int W, int C, const or_params* P, or_energies* E)
+int or_energies_eval(const double* c, const double* c0, const double* v, const double* mu,
+                     int H, int W, int C, const or_params* P, or_energies* E)
 {
     const size_t n2c = (size_t)H * W * 2 * C;
     const double dx = 1.0 / W, dy = 1.0 / H, area = dx * dy;
     double* g = (double*)malloc(n2c * sizeof(double));
-    or_grad(c, H, W, C, g);
     double* acc = (double*)calloc((size_t)H * 8, sizeof(double));
+    if (!g || !acc) {
+        free(g);
+        free(acc);
+        return OR_ENOMEM;
+    }
+    or_grad(c, H, W, C, g);
 #pragma omp parallel for schedule(static)
     for (int r = 0; r < H; ++r) {
         double tv = 0, fid = 0, lsum = 0, lt = 0, svg = 0, sg = 0, sv = 0;
@@ -401,19 +426,25 @@ void or_energies_eval(const double* c, const double* c0, const double* v, const 
     E->r_rel = sqrt(t[4]) / den;
     free(g);
     free(acc);
+    return OR_OK;
 }
 
 /* Completed-square objective L~(c, v) and its gradient in c            */
 /* (eq. admm_terminal rewritten with div = -grad#^T):                    */
 /*   dL~/dc = dx dy [ div(mu + rho (v - grad c)) + alpha (c - c0) ].     */
-void or_terminal(const double* c, const double* c0, const double* v, const double* mu,
-                 int H, int W, int C, const or_params* P, double* pK, double* Ltilde)
+int or_terminal(const double* c, const double* c0, const double* v, const double* mu,
+                int H, int W, int C, const or_params* P, double* pK, double* Ltilde)
 {
     const size_t n = (size_t)H * W * C, n2c = 2 * n;
     const double area = (1.0 / W) * (1.0 / H);
     double* g = (double*)malloc(n2c * sizeof(double));
     double* qf = (double*)malloc(n2c * sizeof(double));
     double* dv = (double*)malloc(n * sizeof(double));
+    int rc = OR_OK;
+    if (!g || !qf || !dv) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
     or_grad(c, H, W, C, g);
     for (size_t k = 0; k < n2c; ++k) {
         double vk = v ? v[k] : 0.0, mk = mu ? mu[k] : 0.0;
@@ -424,12 +455,14 @@ void or_terminal(const double* c, const double* c0, const double* v, const doubl
         for (size_t k = 0; k < n; ++k) pK[k] = area * (dv[k] + P->alpha * (c[k] - c0[k]));
     if (Ltilde) {
         or_energies E;
-        or_energies_eval(c, c0, v, mu, H, W, C, P, &E);
-        *Ltilde = E.Ltilde;
+        rc = or_energies_eval(c, c0, v, mu, H, W, C, P, &E);
+        if (rc == OR_OK) *Ltilde = E.Ltilde;
     }
+done:
     free(g);
     free(qf);
     free(dv);
+    return rc;
 }
 
 /* Shrinkage (eq. soft_threshold): per pixel, with a = grad c - mu/rho   */
@@ -437,11 +470,12 @@ void or_terminal(const double* c, const double* c0, const double* v, const doubl
 /*   v = (|a| - 1/rho) a/|a|  if |a| > 1/rho,  else 0.                    */
 /* Then, if update_mu, the dual ascent of eq. dual_ascent:                */
 /*   mu <- mu + gamma (v - grad c).                                       */
-void or_pd_step(const double* c, const double* c0, int H, int W, int C, const or_params* P,
-                double* v, double* mu, int update_mu, or_energies* E)
+int or_pd_step(const double* c, const double* c0, int H, int W, int C, const or_params* P,
+               double* v, double* mu, int update_mu, or_energies* E)
 {
     const size_t npix = (size_t)H * W, n2c = npix * 2 * C;
     double* g = (double*)malloc(n2c * sizeof(double));
+    if (!g) return OR_ENOMEM;
     or_grad(c, H, W, C, g);
     const double thr = 1.0 / P->rho;
 #pragma omp parallel for schedule(static)
@@ -460,8 +494,8 @@ void or_pd_step(const double* c, const double* c0, int H, int W, int C, const or
             for (int k = 0; k < 2 * C; ++k)
                 mu[pix * 2 * C + k] += P->gamma * (v[pix * 2 * C + k] - g[pix * 2 * C + k]);
     }
-    if (E) or_energies_eval(c, c0, v, mu, H, W, C, P, E);
     free(g);
+    return E ? or_energies_eval(c, c0, v, mu, H, W, C, P, E) : OR_OK;
 }
 
 /* ------------------------------------------------------------------ */
@@ -479,10 +513,14 @@ void or_pd_step(const double* c, const double* c0, int H, int W, int C, const or
 /* out [max_outer][max_inner]: the accepted step tau (> 0), or 0 where   */
 /* the inner loop ended without a step.  With decisions_in the search is */
 /* replaced by the recorded steps (replay).  trace_out, when given, gets */
-/* three doubles per DAL iteration: Phi before the step, Phi after it    */
-/* (0 when no step was taken) and the number of trials.  eps_log and     */
-/* grad_log ([max_outer][max_inner][K][2]) receive the controls after    */
-/* each accepted step and the gradient G of each DAL iteration.          */
+/* OR_TRACE doubles per DAL iteration: Phi before the step, Phi after it */
+/* (0 when no step was taken), the number of trials, and the smallest   */
+/* Armijo margin of those trials, min |Phi(0) + c <G, de> - Phi(tau)| /  */
+/* |Phi(0)| (how far each sufficient-decrease test was from going the   */
+/* other way; NaN when no trial ran).  eps_log and grad_log             */
+/* ([max_outer][max_inner][K][2]) receive the controls after each        */
+/* accepted step and the gradient G of each DAL iteration.               */
+#define OR_TRACE 4
 
 static double clampd(double x, double lo, double hi)
 {
@@ -500,19 +538,27 @@ static void project_step(const double* eps, const double* G, double tau, const o
 /* One Armijo trial: eps(tau) = Pi_E(eps - tau G), forward sweep into traj,
    Phi(tau) = L~(c^K(tau)), and the projected sufficient-decrease test
    Phi(tau) <= Phi(0) + c <G, eps(tau) - eps>, with the rectangular-rule
-   inner product dt * sum_k (Sec. 3.2).  Returns 1 when the test passes. */
+   inner product dt * sum_k (Sec. 3.2).  *pass is 1 when the test passes;
+   *margin (may be NULL) receives (Phi(0) + c <G, de> - Phi(tau)) / |Phi(0)|.
+   Returns OR_OK or an error code. */
 static int armijo_trial(const double* c0, int H, int W, int C, const or_params* P,
                         const double* v, const double* mu, const double* eps, const double* G,
-                        double tau, double phi0, double* e_out, double* traj, double* phi_out)
+                        double tau, double phi0, double* e_out, double* traj, double* phi_out,
+                        int* pass, double* margin)
 {
     const size_t n = (size_t)H * W * C;
     project_step(eps, G, tau, P, e_out);
-    or_forward_sweep(c0, H, W, C, P, e_out, traj);
-    or_terminal(traj + (size_t)P->K * n, c0, v, mu, H, W, C, P, NULL, phi_out);
+    int rc = or_forward_sweep(c0, H, W, C, P, e_out, traj);
+    if (rc) return rc;
+    rc = or_terminal(traj + (size_t)P->K * n, c0, v, mu, H, W, C, P, NULL, phi_out);
+    if (rc) return rc;
     double ip = 0.0;
     for (int k = 0; k < 2 * P->K; ++k) ip += G[k] * (e_out[k] - eps[k]);
     ip *= P->dt;
-    return *phi_out <= phi0 + P->armijo_c * ip;
+    const double rhs = phi0 + P->armijo_c * ip;
+    *pass = *phi_out <= rhs;
+    if (margin) *margin = (rhs - *phi_out) / fabs(phi0);
+    return OR_OK;
 }
 
 int or_solve(const double* c0, int H, int W, int C, const or_params* P,
@@ -535,10 +581,15 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
     double* e_try = (double*)malloc(2 * (size_t)K * sizeof(double));
     double* e_cand = (double*)malloc(2 * (size_t)K * sizeof(double));
     double* e_next = (double*)malloc(2 * (size_t)K * sizeof(double));
+    int rc = OR_OK;
+#define OR_TRY(expr)              \
+    do {                          \
+        if ((rc = (expr)) != 0)   \
+            goto cleanup;         \
+    } while (0)
     if (!base || !cand || !trial || !pK || !p0 || !G || !e_try || !e_cand || !e_next) {
-        free(base); free(cand); free(trial); free(pK); free(p0); free(G);
-        free(e_try); free(e_cand); free(e_next);
-        return OR_ENOMEM;
+        rc = OR_ENOMEM;
+        goto cleanup;
     }
     or_stats S;
     memset(&S, 0, sizeof(S));
@@ -551,19 +602,24 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
     if (decisions_out)
         for (int k = 0; k < P->max_outer * P->max_inner; ++k) decisions_out[k] = 0.0;
     if (trace_out)
-        for (int k = 0; k < 3 * P->max_outer * P->max_inner; ++k) trace_out[k] = 0.0;
+        for (int k = 0; k < P->max_outer * P->max_inner; ++k) {
+            trace_out[OR_TRACE * k + 0] = 0.0;
+            trace_out[OR_TRACE * k + 1] = 0.0;
+            trace_out[OR_TRACE * k + 2] = 0.0;
+            trace_out[OR_TRACE * k + 3] = NAN;
+        }
     const size_t nlog = (size_t)P->max_outer * P->max_inner * 2 * (size_t)P->K;
     if (eps_log) memset(eps_log, 0, nlog * sizeof(double));
     if (grad_log) memset(grad_log, 0, nlog * sizeof(double));
 
     double sigma = P->sigma0;
     /* Alg. 2: forward integration, then v^(0) = argmin_v L(c^(0), v, mu^(0)). */
-    or_forward_sweep(c0, H, W, C, P, eps, base);
+    OR_TRY(or_forward_sweep(c0, H, W, C, P, eps, base));
     if (quad) {
         memset(v, 0, 2 * n * sizeof(double));
         memset(mu, 0, 2 * n * sizeof(double));
     } else {
-        or_pd_step(base + (size_t)K * n, c0, H, W, C, P, v, mu, 0, NULL);
+        OR_TRY(or_pd_step(base + (size_t)K * n, c0, H, W, C, P, v, mu, 0, NULL));
     }
     double L_prev = NAN;
     int phi_seen = 0;
@@ -575,37 +631,42 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
         for (int it = 0; it < P->max_inner; ++it) {
             const int slot = j * P->max_inner + it;
             double phi0;
-            or_terminal(base + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, pK, &phi0);
+            OR_TRY(or_terminal(base + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, pK, &phi0));
             if (!phi_seen) {
                 S.phi_first = phi0;
                 phi_seen = 1;
             }
             S.phi_last = phi0;
-            or_adjoint_sweep(base, H, W, C, P, eps, pK, p0, G);
+            OR_TRY(or_adjoint_sweep(base, H, W, C, P, eps, pK, p0, G));
             int all_zero = 1;
             for (int k = 0; k < 2 * K; ++k) {
                 G[k] /= P->dt; /* L^2(0,T) gradient: dPhi/deps^k / dt */
                 if (G[k] != 0.0) all_zero = 0;
             }
             S.inner_iters++;
-            if (trace_out) trace_out[3 * slot + 0] = phi0;
+            if (trace_out) trace_out[OR_TRACE * slot + 0] = phi0;
             if (grad_log) memcpy(grad_log + (size_t)slot * 2 * K, G, 2 * (size_t)K * sizeof(double));
             if (decisions_in && decisions_in[slot] <= 0.0) break;
             if (!decisions_in && all_zero) break;
 
             double accepted = 0.0, phi_acc = phi0;
+            double margin = 0.0, min_margin = INFINITY;
+            int ok = 0;
             if (decisions_in) {
+                /* replayed step: one trial at the recorded tau, taken whatever its test says */
                 accepted = decisions_in[slot];
-                project_step(eps, G, accepted, P, e_cand);
-                or_forward_sweep(c0, H, W, C, P, e_cand, cand);
-                or_terminal(cand + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, NULL, &phi_acc);
+                OR_TRY(armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, accepted, phi0, e_cand, cand,
+                                    &phi_acc, &ok, &margin));
+                min_margin = fabs(margin);
                 S.ls_evals++;
             } else {
                 /* Two-way search along the projected path (Alg. 1). */
                 double tau = sigma, phit;
                 int evals = 0, have = 0;
-                int ok = armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial, &phit);
+                OR_TRY(armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial, &phit,
+                                    &ok, &margin));
                 evals++;
+                min_margin = fabs(margin);
                 if (ok) {
                     /* expanding branch: grow tau while the test keeps passing */
                     { double* t = cand; cand = trial; trial = t; }
@@ -618,8 +679,10 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
                         if (memcmp(e_next, e_cand, 2 * (size_t)K * sizeof(double)) == 0)
                             break; /* the projected point no longer moves */
                         tau /= P->armijo_b;
-                        ok = armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial, &phit);
+                        OR_TRY(armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial,
+                                            &phit, &ok, &margin));
                         evals++;
+                        if (fabs(margin) < min_margin) min_margin = fabs(margin);
                         if (!ok) break;
                         { double* t = cand; cand = trial; trial = t; }
                         memcpy(e_cand, e_try, 2 * (size_t)K * sizeof(double));
@@ -630,8 +693,10 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
                     /* backtracking branch: shrink tau until the test passes */
                     while (evals < P->max_ls) {
                         tau *= P->armijo_b;
-                        ok = armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial, &phit);
+                        OR_TRY(armijo_trial(c0, H, W, C, &Pq, tv, tmu, eps, G, tau, phi0, e_try, trial,
+                                            &phit, &ok, &margin));
                         evals++;
+                        if (fabs(margin) < min_margin) min_margin = fabs(margin);
                         if (ok) {
                             { double* t = cand; cand = trial; trial = t; }
                             memcpy(e_cand, e_try, 2 * (size_t)K * sizeof(double));
@@ -643,7 +708,8 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
                     }
                 }
                 S.ls_evals += evals;
-                if (trace_out) trace_out[3 * slot + 2] = evals;
+                if (trace_out) trace_out[OR_TRACE * slot + 2] = evals;
+                if (trace_out) trace_out[OR_TRACE * slot + 3] = min_margin;
                 if (!have) break; /* no admissible step: the control argmin ends here */
                 sigma = accepted;
             }
@@ -651,17 +717,21 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
             memcpy(eps, e_cand, 2 * (size_t)K * sizeof(double));
             { double* t = base; base = cand; cand = t; }
             if (decisions_out) decisions_out[slot] = accepted;
-            if (trace_out) trace_out[3 * slot + 1] = phi_acc;
+            if (trace_out) {
+                trace_out[OR_TRACE * slot + 1] = phi_acc;
+                trace_out[OR_TRACE * slot + 3] = min_margin;
+            }
             if (eps_log) memcpy(eps_log + (size_t)slot * 2 * K, eps, 2 * (size_t)K * sizeof(double));
+            /* relative stationarity of the inner objective (Rmk. on the convergence criteria) */
             if (P->tol_dal > 0.0 && fabs(phi_acc - phi0) < P->tol_dal * fabs(phi0)) break;
         }
         if (quad) {
-            or_energies_eval(base + (size_t)K * n, c0, NULL, NULL, H, W, C, &Pq, &E);
+            OR_TRY(or_energies_eval(base + (size_t)K * n, c0, NULL, NULL, H, W, C, &Pq, &E));
             S.outer_iters = 1;
             break;
         }
         /* v- and mu-updates (Alg. 2, eq. soft_threshold and eq. dual_ascent) */
-        or_pd_step(base + (size_t)K * n, c0, H, W, C, P, v, mu, 1, &E);
+        OR_TRY(or_pd_step(base + (size_t)K * n, c0, H, W, C, P, v, mu, 1, &E));
         S.outer_iters = j + 1;
         S.gap_rel = isnan(L_prev) ? NAN : fabs(E.L - L_prev) / fabs(L_prev);
         L_prev = E.L;
@@ -669,7 +739,7 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
         /* stop once the Lagrangian's change between multiplier iterations is small (Sec. 4.1) */
         if (P->tol_gap > 0.0 && !isnan(S.gap_rel) && S.gap_rel < P->tol_gap) break;
     }
-    if (S.outer_iters == 0) or_energies_eval(base + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, &E);
+    if (S.outer_iters == 0) OR_TRY(or_energies_eval(base + (size_t)K * n, c0, tv, tmu, H, W, C, &Pq, &E));
     memcpy(cK, base + (size_t)K * n, n * sizeof(double));
     S.K = E.K;
     S.TV = E.TV;
@@ -680,9 +750,11 @@ int or_solve(const double* c0, int H, int W, int C, const or_params* P,
     S.r_abs = E.r_abs;
     S.status = (!quad && P->tol_alm > 0.0 && !(E.r_rel < P->tol_alm)) ? 1 : 0;
     if (st) *st = S;
+cleanup:
+#undef OR_TRY
     free(base); free(cand); free(trial); free(pK); free(p0); free(G);
     free(e_try); free(e_cand); free(e_next);
-    return OR_OK;
+    return rc;
 }
 
 int or_num_threads(void)

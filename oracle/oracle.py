@@ -16,7 +16,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ABC_ORACLE_LIB names another build of the same sources (the sanitizer build of the tests)
+_LIB_PATH = os.environ.get("ABC_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 _lib = None
 
 _dp = ct.POINTER(ct.c_double)
@@ -105,9 +106,12 @@ def lib():
             getattr(L, name).argtypes = [ct.c_double]
         L.or_forward_step.argtypes = [_dp, _dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params),
                                       ct.c_double, ct.c_double]
+        L.or_forward_step.restype = ct.c_int
         L.or_forward_sweep.argtypes = [_dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params), _dp, _dp]
+        L.or_forward_sweep.restype = ct.c_int
         L.or_adjoint_step.argtypes = [_dp, _dp, _dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params),
                                       ct.c_double, ct.c_double, _dp]
+        L.or_adjoint_step.restype = ct.c_int
         L.or_adjoint_sweep.argtypes = [_dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params), _dp, _dp,
                                        _dp, _dp]
         L.or_adjoint_sweep.restype = ct.c_int
@@ -115,10 +119,13 @@ def lib():
         L.or_div.argtypes = [_dp, ct.c_int, ct.c_int, ct.c_int, _dp]
         L.or_energies_eval.argtypes = [_dp, _dp, _dp, _dp, ct.c_int, ct.c_int, ct.c_int,
                                        ct.POINTER(_Params), ct.POINTER(_Energies)]
+        L.or_energies_eval.restype = ct.c_int
         L.or_terminal.argtypes = [_dp, _dp, _dp, _dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params),
                                   _dp, _dp]
+        L.or_terminal.restype = ct.c_int
         L.or_pd_step.argtypes = [_dp, _dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params), _dp, _dp,
                                  ct.c_int, ct.POINTER(_Energies)]
+        L.or_pd_step.restype = ct.c_int
         L.or_solve.argtypes = [_dp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(_Params), _dp, _dp, _dp, _dp,
                                _dp, _dp, _dp, _dp, _dp, ct.POINTER(_Stats)]
         L.or_solve.restype = ct.c_int
@@ -133,6 +140,13 @@ def lib():
         L.or_set_num_threads.argtypes = [ct.c_int]
         _lib = L
     return _lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc == -4:
+        raise MemoryError(f"oracle {what}: out of memory")
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
 
 
 def _ptr(a):
@@ -176,7 +190,8 @@ def forward_step(c, P: Params, ex: float, ec: float):
     H, W, C = c.shape
     out = np.empty_like(c)
     pc = P.to_c(H, W)
-    lib().or_forward_step(_ptr(c), _ptr(out), H, W, C, ct.byref(pc), float(ex), float(ec))
+    _check(lib().or_forward_step(_ptr(c), _ptr(out), H, W, C, ct.byref(pc), float(ex), float(ec)),
+           "forward step")
     return out
 
 
@@ -187,7 +202,7 @@ def forward_sweep(c0, P: Params, eps=None):
     e = _eps_array(P, eps)
     traj = np.empty((P.K + 1, H, W, C))
     pc = P.to_c(H, W)
-    lib().or_forward_sweep(_ptr(c0), H, W, C, ct.byref(pc), _ptr(e), _ptr(traj))
+    _check(lib().or_forward_sweep(_ptr(c0), H, W, C, ct.byref(pc), _ptr(e), _ptr(traj)), "forward sweep")
     return traj
 
 
@@ -198,8 +213,8 @@ def adjoint_step(c, p, P: Params, ex: float, ec: float):
     out = np.empty_like(p)
     gk = np.zeros(2)
     pc = P.to_c(H, W)
-    lib().or_adjoint_step(_ptr(c), _ptr(p), _ptr(out), H, W, C, ct.byref(pc), float(ex), float(ec),
-                          _ptr(gk))
+    _check(lib().or_adjoint_step(_ptr(c), _ptr(p), _ptr(out), H, W, C, ct.byref(pc), float(ex), float(ec),
+                                 _ptr(gk)), "adjoint step")
     return out, gk
 
 
@@ -212,9 +227,8 @@ def adjoint_sweep(traj, P: Params, pK, eps=None):
     p0 = np.empty((H, W, C))
     geps = np.zeros((P.K, 2))
     pc = P.to_c(H, W)
-    rc = lib().or_adjoint_sweep(_ptr(traj), H, W, C, ct.byref(pc), _ptr(e), _ptr(pK), _ptr(p0), _ptr(geps))
-    if rc != 0:
-        raise MemoryError("oracle adjoint sweep failed")
+    _check(lib().or_adjoint_sweep(_ptr(traj), H, W, C, ct.byref(pc), _ptr(e), _ptr(pK), _ptr(p0), _ptr(geps)),
+           "adjoint sweep")
     return p0, geps
 
 
@@ -244,7 +258,8 @@ def energies(c, c0, v, mu, P: Params) -> dict:
     mu = None if mu is None else _f64(mu)
     E = _Energies()
     pc = P.to_c(H, W)
-    lib().or_energies_eval(_ptr(c), _ptr(c0), _ptr(v), _ptr(mu), H, W, C, ct.byref(pc), ct.byref(E))
+    _check(lib().or_energies_eval(_ptr(c), _ptr(c0), _ptr(v), _ptr(mu), H, W, C, ct.byref(pc), ct.byref(E)),
+           "energies")
     return {n: getattr(E, n) for n, _ in _Energies._fields_}
 
 
@@ -257,8 +272,8 @@ def terminal(cK, c0, v, mu, P: Params):
     pK = np.empty((H, W, C))
     Lt = ct.c_double(0.0)
     pc = P.to_c(H, W)
-    lib().or_terminal(_ptr(cK), _ptr(c0), _ptr(v), _ptr(mu), H, W, C, ct.byref(pc), _ptr(pK),
-                      ct.cast(ct.pointer(Lt), _dp))
+    _check(lib().or_terminal(_ptr(cK), _ptr(c0), _ptr(v), _ptr(mu), H, W, C, ct.byref(pc), _ptr(pK),
+                             ct.cast(ct.pointer(Lt), _dp)), "terminal")
     return pK, Lt.value
 
 
@@ -270,8 +285,8 @@ def pd_step(cK, c0, v, mu, P: Params, update_mu: bool = True):
     mu = np.zeros((H, W, 2, C)) if mu is None else _f64(mu).copy()
     E = _Energies()
     pc = P.to_c(H, W)
-    lib().or_pd_step(_ptr(cK), _ptr(c0), H, W, C, ct.byref(pc), _ptr(v), _ptr(mu), int(update_mu),
-                     ct.byref(E))
+    _check(lib().or_pd_step(_ptr(cK), _ptr(c0), H, W, C, ct.byref(pc), _ptr(v), _ptr(mu), int(update_mu),
+                            ct.byref(E)), "pd step")
     return v, mu, {n: getattr(E, n) for n, _ in _Energies._fields_}
 
 
@@ -281,8 +296,8 @@ def solve(c0, P: Params, eps=None, mu=None, decisions=None):
     ``decisions``: optional ``(max_outer, max_inner)`` array of accepted steps
     to replay instead of running the line search.  Returns a dict with the
     final field ``c``, ``eps``, ``v``, ``mu``, the decision log, a per-DAL
-    iteration trace ``(max_outer, max_inner, 3)`` = (Phi before, Phi after,
-    trials), the controls after every accepted step ``eps_log`` and the
+    iteration trace ``(max_outer, max_inner, 4)`` = (Phi before, Phi after,
+    trials, smallest relative Armijo margin of the slot's trials), the controls after every accepted step ``eps_log`` and the
     gradient of every DAL iteration ``grad_log`` (both ``(M, P, K, 2)``) and
     stats.
     """
@@ -294,15 +309,14 @@ def solve(c0, P: Params, eps=None, mu=None, decisions=None):
     cK = np.empty((H, W, C))
     dec_out = np.zeros((max(P.max_outer, 1), max(P.max_inner, 1)))
     dec_in = None if decisions is None else _f64(decisions).reshape(P.max_outer, P.max_inner).copy()
-    trace = np.zeros((max(P.max_outer, 1), max(P.max_inner, 1), 3))
+    trace = np.zeros((max(P.max_outer, 1), max(P.max_inner, 1), 4))
     eps_log = np.zeros((max(P.max_outer, 1), max(P.max_inner, 1), P.K, 2))
     grad_log = np.zeros_like(eps_log)
     st = _Stats()
     pc = P.to_c(H, W)
-    rc = lib().or_solve(_ptr(c0), H, W, C, ct.byref(pc), _ptr(e), _ptr(m), _ptr(v), _ptr(cK),
-                        _ptr(dec_in), _ptr(dec_out), _ptr(trace), _ptr(eps_log), _ptr(grad_log), ct.byref(st))
-    if rc != 0:
-        raise ValueError(f"oracle solve failed with code {rc}")
+    _check(lib().or_solve(_ptr(c0), H, W, C, ct.byref(pc), _ptr(e), _ptr(m), _ptr(v), _ptr(cK),
+                          _ptr(dec_in), _ptr(dec_out), _ptr(trace), _ptr(eps_log), _ptr(grad_log), ct.byref(st)),
+           "solve")
     stats = {n: getattr(st, n) for n, _ in _Stats._fields_}
     return {"c": cK, "eps": e, "v": v, "mu": m, "decisions": dec_out, "trace": trace, "eps_log": eps_log,
             "grad_log": grad_log, "stats": stats}

@@ -485,3 +485,101 @@ def test_lagrangian_gap_stop(orc):
     assert res["stats"]["gap_rel"] < tol
     assert np.array_equal(res["c"], orc.solve(c0, _P(orc, **dict(base, max_outer=stop)))["c"])
     assert full["stats"]["outer_iters"] == 8
+
+
+# ---------------------------------------------------------------- O12 residual and TV on a hand-worked ramp
+def test_alm_residual_and_tv_of_a_ramp(orc):
+    """c = a q + b r + const on a 5 x 7 x 2 image: grad# is (a W, b H) inside and 0
+    on the border columns / rows (reflective rule of Def. 3.1), so TV, r_abs and
+    r_rel = |v - grad c| / max(|grad c|, |v|) have closed forms for v = f grad c.
+    f = 3 gives 2/3 (2 without the max with |v|), f = -1 gives 2."""
+    H, W, C = 5, 7, 2
+    a, b = 0.03, -0.05
+    q = np.arange(W)[None, :, None]
+    r = np.arange(H)[:, None, None]
+    c = a * q + b * r + np.array([0.1, 0.4])[None, None, :]
+    g = np.zeros((H, W, 2, C))
+    g[:, 1:W - 1, 0, :] = a * W
+    g[1:H - 1, :, 1, :] = b * H
+    area = 1.0 / (H * W)
+    P = _P(orc, alpha=7.0)
+    tv = area * np.sqrt(C) * ((W - 2) * (H - 2) * np.hypot(a * W, b * H) + (W - 2) * 2 * abs(a * W)
+                              + (H - 2) * 2 * abs(b * H))
+    ng = np.sqrt(np.sum(g ** 2))
+    for f, want in [(0.0, 1.0), (0.5, 0.5), (2.0, 0.5), (3.0, 2.0 / 3.0), (-1.0, 2.0)]:
+        E = orc.energies(c, c, f * g, None, P)
+        assert E["TV"] == pytest.approx(tv, rel=1e-13)
+        assert E["fid"] == 0.0
+        assert E["r_rel"] == pytest.approx(want, rel=1e-13), f
+        assert E["r_abs"] == pytest.approx(abs(1.0 - f) * np.sqrt(area) * ng, rel=1e-13)
+    # the fidelity term of eq. cost_TV: alpha/2 |c - c0|^2 dx dy
+    E = orc.energies(c, c - 0.25, g, None, P)
+    assert E["fid"] == pytest.approx(area * 0.5 * 7.0 * H * W * C * 0.25 ** 2, rel=1e-13)
+    assert E["r_rel"] < 1e-14  # v equals grad c up to the rounding of the ramp's differences
+
+
+# ---------------------------------------------------------------- stationarity stop of the inner loop
+def test_dal_stationarity_stop(orc):
+    """The inner loop ends at the first accepted DAL step whose relative change of
+    the inner objective, |Phi(tau) - Phi(0)| / |Phi(0)|, is below tol_dal (Rmk. on
+    the convergence criteria, Sec. 3.2), read from the oracle's own trace; the
+    iterations before it are those of the run without the stop."""
+    c0 = voronoi_image(16, 16, 3, 4, 0.05, 211).astype(np.float64)
+    base = dict(K=6, R=2, alpha=20.0, max_outer=2, max_inner=8)
+    full = orc.solve(c0, _P(orc, **base))
+    tr = full["trace"][0]
+    taken = full["decisions"][0] > 0
+    assert taken.sum() >= 5
+    rel = np.abs(tr[:, 1] - tr[:, 0]) / np.abs(tr[:, 0])
+    # the first step's change is the threshold: the loop ends at the first later
+    # step that changes the objective by less
+    tol = float(rel[0])
+    stop = next(i for i in range(1, 8) if taken[i] and rel[i] < tol)
+    res = orc.solve(c0, _P(orc, **dict(base, tol_dal=tol)))
+    d = res["decisions"][0]
+    assert np.array_equal(d[:stop + 1], full["decisions"][0][:stop + 1])
+    assert np.all(d[stop + 1:] == 0) and np.all(res["trace"][0, stop + 1:, 0] == 0)
+    assert res["trace"][1, 0, 0] != 0  # the next multiplier iteration runs
+    assert res["stats"]["inner_iters"] < full["stats"]["inner_iters"]
+
+
+# ---------------------------------------------------------------- kernel as printed (reading of eq. kernel)
+def test_literal_kernel_derivative(orc):
+    """The printed (4r-1)(1-r)^4 and its derivative, against central differences
+    and the expanded polynomial."""
+    h = 1e-6
+    for r in np.linspace(0.01, 0.99, 29):
+        fd = (orc.phi(r + h, literal=True) - orc.phi(r - h, literal=True)) / (2 * h)
+        assert orc.dphi(r, literal=True) == pytest.approx(fd, rel=1e-7, abs=1e-9)
+        # (4r - 1)(1 - 4r + 6r^2 - 4r^3 + r^4) expanded, and its derivative
+        poly = -1 + 8 * r - 22 * r ** 2 + 28 * r ** 3 - 17 * r ** 4 + 4 * r ** 5
+        dpoly = 8 - 44 * r + 84 * r ** 2 - 68 * r ** 3 + 20 * r ** 4
+        assert orc.phi(r, literal=True) == pytest.approx(poly, rel=1e-12, abs=1e-14)
+        assert orc.dphi(r, literal=True) == pytest.approx(dpoly, rel=1e-12, abs=1e-13)
+    assert orc.dphi(1.5, literal=True) == 0.0 and orc.dphi(-0.1, literal=True) == 0.0
+
+
+# ---------------------------------------------------------------- Armijo margins in the trace
+def test_armijo_margins_in_the_trace(orc):
+    """Column 3 of the trace is the smallest |Phi(0) + c <G, de> - Phi(tau)| / |Phi(0)|
+    over the slot's trials; for the accepted trial the signed margin (recomputed
+    from the logged controls, gradient and objectives) is >= 0 and at least that."""
+    c0 = voronoi_image(12, 14, 3, 3, 0.05, 171).astype(np.float64)
+    P = _P(orc, K=6, R=2, alpha=20.0, max_outer=2, max_inner=4)
+    res = orc.solve(c0, P)
+    prev = np.full((P.K, 2), P.eps_init)
+    n = 0
+    for j in range(2):
+        for it in range(4):
+            tau = res["decisions"][j, it]
+            if tau <= 0:
+                break
+            phi0, phi1, trials, m = res["trace"][j, it]
+            de = res["eps_log"][j, it] - prev
+            ip = P.dt * np.sum(res["grad_log"][j, it] * de)
+            acc = (phi0 + P.armijo_c * ip - phi1) / abs(phi0)
+            assert acc >= 0.0
+            assert 0.0 <= m <= acc * (1 + 1e-12) and trials >= 1
+            prev = res["eps_log"][j, it]
+            n += 1
+    assert n >= 4
