@@ -205,7 +205,12 @@ int abc_pd_step(const float* cK, const float* c0, int H, int W, int C, const abc
  *   phi_out:       [slots][5] objective before the step, after it, trials,
  *                  TV energy K after the step, milliseconds since the call.
  *   outer_out:     [max_outer][4] after each multiplier iteration: K, L,
- *                  r_rel and the elapsed milliseconds since the call began. */
+ *                  r_rel and the elapsed milliseconds since the call began.
+ *   eps_out:       [slots][K][2] the controls Pi_E(eps - tau G) of each
+ *                  accepted step, from this run's own gradient G and the
+ *                  accepted tau; with eps_replay they are computed from the
+ *                  replayed base controls and logged, not taken (0 where no
+ *                  step was accepted). */
 typedef struct abc_solve_log {
     const double* decisions_in;
     double* decisions_out;
@@ -213,6 +218,7 @@ typedef struct abc_solve_log {
     double* grad_out;
     double* phi_out;
     double* outer_out;
+    double* eps_out;
 } abc_solve_log;
 
 /* Full solve: method of multipliers (Alg. 2) whose control argmin is the
@@ -277,10 +283,13 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
  *   st: host array of n stats (may be NULL).
  *   finish_ms: host array of n completion times in ms after the call began
  *     (may be NULL).
+ *   logs: host array of n record / replay logs, one per image, with the
+ *     meaning and sizes abc_solve gives them (may be NULL, and so may each
+ *     array in them); outer_out's times are ms since this call began.
  * Returns ABC_OK, or ABC_ENOCONV when some image did not reach tol_alm.
  * Synchronises the stream before returning. */
 int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, void* ws, size_t ws_bytes,
-                      void* stream, abc_stats* st, double* finish_ms);
+                      void* stream, abc_stats* st, double* finish_ms, const abc_solve_log* logs);
 
 /* ---- Learned warm start ---------------------------------------------------
  * A convolutional encoder-decoder predicting a starting multiplier field mu0

@@ -40,7 +40,8 @@ class AbcParams(ct.Structure):
 class AbcSolveLog(ct.Structure):
     _fields_ = [("decisions_in", ct.POINTER(ct.c_double)), ("decisions_out", ct.POINTER(ct.c_double)),
                 ("eps_replay", ct.POINTER(ct.c_double)), ("grad_out", ct.POINTER(ct.c_double)),
-                ("phi_out", ct.POINTER(ct.c_double)), ("outer_out", ct.POINTER(ct.c_double))]
+                ("phi_out", ct.POINTER(ct.c_double)), ("outer_out", ct.POINTER(ct.c_double)),
+                ("eps_out", ct.POINTER(ct.c_double))]
 
 
 class AbcImage(ct.Structure):
@@ -178,7 +179,8 @@ def lib():
     L.abc_workspace_bytes_batched.argtypes = [ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.c_int, ct.c_int,
                                               ct.POINTER(AbcParams), ct.POINTER(ct.c_size_t)]
     L.abc_solve_batched.argtypes = [ct.POINTER(AbcImage), ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp,
-                                    ct.c_size_t, _vp, ct.POINTER(AbcStats), ct.POINTER(ct.c_double)]
+                                    ct.c_size_t, _vp, ct.POINTER(AbcStats), ct.POINTER(ct.c_double),
+                                    ct.POINTER(AbcSolveLog)]
     L.abc_segment_workspace_bytes.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]
     L.abc_segment.argtypes = [_vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.c_float, _vp, _vp, ct.POINTER(AbcSegStats),
                               _vp, ct.c_size_t, _vp]
@@ -337,9 +339,11 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     ``eps`` and ``mu`` (the tensors passed in, updated, when given), ``v``,
     ``stats``, and the logs (numpy): ``decisions`` (max_outer x max_inner),
     ``grad_log`` (M x P x K x 2), ``phi_log`` (M x P x 5: objective before and
-    after the step, trials, K after the step, ms) and ``outer_log``
-    (M x 4: K, L, r_rel, elapsed ms after each multiplier iteration).  ``decisions``
-    and ``eps_replay`` (M x P x K x 2) replay a recorded control argmin."""
+    after the step, trials, K after the step, ms), ``outer_log``
+    (M x 4: K, L, r_rel, elapsed ms after each multiplier iteration) and
+    ``eps_log`` (M x P x K x 2: the projected controls of each accepted step
+    from the run's own gradient).  ``decisions`` and ``eps_replay``
+    (M x P x K x 2) replay a recorded control argmin."""
     import numpy as np
     torch = _torch()
     H, W, C = c0.shape
@@ -356,6 +360,7 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     grad_log = np.zeros((M, P, K, 2), dtype=np.float64)
     phi_log = np.zeros((M, P, 5), dtype=np.float64)
     outer_log = np.zeros((M, 4), dtype=np.float64)
+    eps_log = np.zeros((M, P, K, 2), dtype=np.float64)
     log = AbcSolveLog()
     keep = []
     if decisions is not None:
@@ -370,13 +375,14 @@ def abc_solve(c0, params: Params, eps=None, mu=None, want_v=True, decisions=None
     log.grad_out = grad_log.ctypes.data_as(dp)
     log.phi_out = phi_log.ctypes.data_as(dp)
     log.outer_out = outer_log.ctypes.data_as(dp)
+    log.eps_out = eps_log.ctypes.data_as(dp)
     st = AbcStats()
     p = params.to_c()
     rc = lib().abc_solve(_ptr(c0), H, W, C, ct.byref(p), _ptr(eps), _ptr(mu), _ptr(v), _ptr(c_out),
                          ct.c_void_p(ws.data_ptr()), nb, _stream(), ct.byref(st), ct.byref(log))
     _check(rc, allow=(ABC_OK, ABC_ENOCONV))
     return {"c": c_out, "eps": eps, "mu": mu, "v": v, "stats": _stats_dict(st), "decisions": dec_out,
-            "grad_log": grad_log, "phi_log": phi_log, "outer_log": outer_log, "status": rc}
+            "grad_log": grad_log, "phi_log": phi_log, "outer_log": outer_log, "eps_log": eps_log, "status": rc}
 
 
 def abc_workspace_bytes_batched(shapes, C: int, params: Params) -> int:
@@ -389,10 +395,15 @@ def abc_workspace_bytes_batched(shapes, C: int, params: Params) -> int:
     return nb.value
 
 
-def abc_solve_batched(images, params: Params, eps=None, mu=None, ws=None):
+def abc_solve_batched(images, params: Params, eps=None, mu=None, ws=None, decisions=None, eps_replay=None,
+                      want_logs=False):
     """Batched solve of a list of H x W x C images (see abc_solve_batched in
     abc.h).  ``eps`` / ``mu``: optional lists of per-image tensors (in/out).
-    Returns (list of final fields, list of stats dicts, finish times in ms)."""
+    ``decisions`` / ``eps_replay``: optional lists of per-image replay arrays
+    (shapes as in abc_solve; an entry may be None).  Returns (list of final
+    fields, list of stats dicts, finish times in ms), and with ``want_logs`` a
+    fourth item: per image, the dict of logs abc_solve returns (decisions,
+    grad_log, phi_log, outer_log, eps_log)."""
     import numpy as np
     torch = _torch()
     n = len(images)
@@ -413,12 +424,40 @@ def abc_solve_batched(images, params: Params, eps=None, mu=None, ws=None):
         ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=images[0].device)
     else:
         nb = ws.numel()
+    logs_c = None
+    logs = []
+    keep = []
+    if want_logs or decisions is not None or eps_replay is not None:
+        M, P, K = max(params.max_outer, 1), max(params.max_inner, 1), params.K
+        dp = ct.POINTER(ct.c_double)
+        logs_c = (AbcSolveLog * n)()
+        for i in range(n):
+            d = {"decisions": np.zeros((M, P)), "grad_log": np.zeros((M, P, K, 2)),
+                 "phi_log": np.zeros((M, P, 5)), "outer_log": np.zeros((M, 4)),
+                 "eps_log": np.zeros((M, P, K, 2))}
+            logs.append(d)
+            lg = logs_c[i]
+            lg.decisions_out = d["decisions"].ctypes.data_as(dp)
+            lg.grad_out = d["grad_log"].ctypes.data_as(dp)
+            lg.phi_out = d["phi_log"].ctypes.data_as(dp)
+            lg.outer_out = d["outer_log"].ctypes.data_as(dp)
+            lg.eps_out = d["eps_log"].ctypes.data_as(dp)
+            if decisions is not None and decisions[i] is not None:
+                di = np.ascontiguousarray(np.asarray(decisions[i], dtype=np.float64).reshape(M, P))
+                keep.append(di)
+                lg.decisions_in = di.ctypes.data_as(dp)
+            if eps_replay is not None and eps_replay[i] is not None:
+                er = np.ascontiguousarray(np.asarray(eps_replay[i], dtype=np.float64).reshape(M, P, K, 2))
+                keep.append(er)
+                lg.eps_replay = er.ctypes.data_as(dp)
     st = (AbcStats * n)()
     fin = np.zeros(n, dtype=np.float64)
     p = params.to_c()
     rc = lib().abc_solve_batched(descs, n, C, ct.byref(p), ct.c_void_p(ws.data_ptr()), nb, _stream(), st,
-                                 fin.ctypes.data_as(ct.POINTER(ct.c_double)))
+                                 fin.ctypes.data_as(ct.POINTER(ct.c_double)), logs_c)
     _check(rc, allow=(ABC_OK, ABC_ENOCONV))
+    if want_logs:
+        return outs, [_stats_dict(s) for s in st], fin, logs
     return outs, [_stats_dict(s) for s in st], fin
 
 

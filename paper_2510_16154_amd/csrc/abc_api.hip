@@ -10,6 +10,7 @@
 #include <chrono>
 #include <map>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -74,11 +75,15 @@ struct PinnedHost {
 // Captured HIP graphs of sweep launches, keyed by the caller.  A sweep is
 // recorded once on a private capture stream and replayed on the caller's
 // stream; kernels read controls, job tables and buffers through pointers
-// that stay fixed, so one recording serves every replay.
+// that stay fixed, so one recording serves every replay.  The key must name
+// everything a recorded launch depends on (buffers, sizes, launch shapes and
+// scalar arguments).  A cache with max_entries > 0 drops all its graphs
+// (after draining the stream) before it would hold more.
 struct GraphCache {
     hipStream_t cap = nullptr;
     hipStream_t last = nullptr;
-    std::map<std::array<long, 4>, hipGraphExec_t> execs;
+    size_t max_entries = 0;
+    std::map<std::vector<long>, hipGraphExec_t> execs;
     GraphCache() = default;
     GraphCache(const GraphCache&) = delete;
     GraphCache& operator=(const GraphCache&) = delete;
@@ -88,10 +93,15 @@ struct GraphCache {
         if (cap) (void)hipStreamDestroy(cap);
     }
     template <class F>
-    int run(bool enabled, const std::array<long, 4>& key, hipStream_t st, F&& record) {
+    int run(bool enabled, const std::vector<long>& key, hipStream_t st, F&& record) {
         last = st;
         if (!enabled) return record(st);
         auto it = execs.find(key);
+        if (it == execs.end() && max_entries > 0 && execs.size() >= max_entries) {
+            ABC_HIP(hipStreamSynchronize(st));
+            for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
+            execs.clear();
+        }
         if (it == execs.end()) {
             if (!cap) ABC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             ABC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -113,6 +123,24 @@ struct GraphCache {
         return ABC_OK;
     }
 };
+
+// Sweep graphs of abc_solve, kept per host thread across calls (a solve
+// records six: three trajectory buffers forward, three adjoint).  Never
+// destroyed: the process end reclaims them, and no HIP call runs at exit.
+GraphCache& solve_graphs() {
+    thread_local GraphCache* g = nullptr;
+    if (!g) {
+        g = new GraphCache;
+        g->max_entries = 48;
+    }
+    return *g;
+}
+
+long float_bits(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, sizeof(u));
+    return (long)u;
+}
 
 // Columns of abc_solve_log.phi_out per DAL iteration.
 constexpr int kStepLog = 5;
@@ -388,6 +416,14 @@ int check_finite(const float* x, size_t n, const PdWs& w, hipStream_t st, const 
 
 namespace {
 size_t tune_ws_bytes(int H, int W, int C);
+int adjoint_dynamics_impl(const float* traj, int H, int W, int C, const float* eps, const abc_params* p,
+                          const float* gK, float* g0, float* geps, void* ws, size_t ws_bytes, void* stream);
+
+__global__ void zero_kernel(float* __restrict__ x, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0f;
+}
+
 }
 
 // ===========================================================================
@@ -487,6 +523,15 @@ int abc_forward_dynamics(const float* c0, int H, int W, int C, const float* eps,
 
 int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* eps, const abc_params* p,
                          const float* gK, float* g0, float* geps, void* ws, size_t ws_bytes, void* stream) {
+    return adjoint_dynamics_impl(traj, H, W, C, eps, p, gK, g0, geps, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+int adjoint_dynamics_impl(const float* traj, int H, int W, int C, const float* eps, const abc_params* p,
+                          const float* gK, float* g0, float* geps, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
@@ -506,7 +551,10 @@ int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* ep
     const float dts = p->dt * snorm;
     if (p->R == 0) {
         if (g0 != gK) ABC_HIP(hipMemcpyAsync(g0, gK, f * sizeof(float), hipMemcpyDeviceToDevice, st));
-        ABC_HIP(hipMemsetAsync(geps, 0, (size_t)p->K * 2 * sizeof(float), st));
+        // a kernel rather than a memset node, so that captured graphs replay it correctly
+        const int n = p->K * 2;
+        zero_kernel<<<(n + 255) / 256, 256, 0, st>>>(geps, n);
+        ABC_HIP(hipGetLastError());
         return ABC_OK;
     }
     // The first step reads gK itself and the last one writes g0 itself (through the
@@ -549,6 +597,10 @@ int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* ep
                                         st));
     return ABC_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int abc_pd_terminal(const float* cK, const float* c0, const float* v, const float* mu, int H, int W, int C,
                     const abc_params* p, float* gK, double* Ltilde, void* ws, size_t ws_bytes, void* stream) {
@@ -594,6 +646,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     double* grad_out = log ? log->grad_out : nullptr;
     double* phi_out = log ? log->phi_out : nullptr;
     double* outer_out = log ? log->outer_out : nullptr;
+    double* eps_out = log ? log->eps_out : nullptr;
     if (eps_replay && !decisions_in) return fail(ABC_EINVAL, "eps_replay needs decisions_in");
     const auto t_start = std::chrono::steady_clock::now();
     const Shape s{H, W, C};
@@ -654,14 +707,22 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     };
     const size_t traj_stride = (size_t)K * f;  // offset of c^K inside a trajectory
     int base = 0, cand = 1, trial = 2;
-    GraphCache graphs;
+    GraphCache& graphs = solve_graphs();
     const bool use_graphs = !(p->flags & ABC_FLAG_NO_GRAPHS) && p->R > 0;
+    // what the recorded sweeps depend on: device, workspace (every buffer is carved
+    // from it in a fixed order), sizes, window, launch shapes and the step scale
+    int device = 0;
+    ABC_HIP(hipGetDevice(&device));
+    auto gkey = [&](long kind, long idx) -> std::vector<long> {
+        return {kind, idx, (long)device, (long)(uintptr_t)ws, (long)H, (long)W, (long)C, (long)K, (long)p->R,
+                float_bits(dts), float_bits(snorm), (long)tf.tx, (long)tf.ty, (long)ta.tx, (long)ta.ty};
+    };
     // slot 0 of every trajectory holds c0 for the whole solve
     for (int b = 0; b < 3; ++b) ABC_HIP(hipMemcpyAsync(w.traj[b], c0, f * sizeof(float), hipMemcpyDeviceToDevice, st));
     // K forward steps into trajectory buffer `idx` under the controls eps[idx]
     auto sweep = [&](int idx) -> int {
         if (p->R == 0) return forward_sweep_full(c0, w.traj[idx], w.eps[idx], s, p, dts, tf, st);
-        return graphs.run(use_graphs, {0, idx, 0, 0}, st, [&](hipStream_t s2) -> int {
+        return graphs.run(use_graphs, gkey(0, idx), st, [&](hipStream_t s2) -> int {
             for (int k = 0; k < K; ++k)
                 ABC_HIP(abc::launch_forward_step(w.traj[idx] + k * f, w.traj[idx] + (k + 1) * f, w.eps[idx], k, H, W, C,
                                                  p->R, dts, tf, s2));
@@ -693,6 +754,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     if (grad_out) std::fill(grad_out, grad_out + nslots * 2 * K, 0.0);
     if (phi_out) std::fill(phi_out, phi_out + nslots * kStepLog, 0.0);
     if (outer_out) std::fill(outer_out, outer_out + (size_t)M * 4, 0.0);
+    if (eps_out) std::fill(eps_out, eps_out + nslots * 2 * K, 0.0);
 
     // Alg. 2: forward integration, v^(0) = argmin_v L(c^(0), v, mu^(0)).
     if ((rc = upload(e_base, w.eps[base]))) return rc;
@@ -732,7 +794,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
             if (p->R > 0) {
                 std::vector<const float*> states(K);
                 for (int k = 0; k < K; ++k) states[k] = w.traj[base] + (size_t)k * f;
-                rc = graphs.run(use_graphs, {1, base, 0, 0}, st, [&](hipStream_t s2) -> int {
+                rc = graphs.run(use_graphs, gkey(1, base), st, [&](hipStream_t s2) -> int {
                     float* c2 = cur;
                     float* sp2 = spare;
                     int r3 = adjoint_steps(states.data(), 0, K, w.eps[base], s, p, dts, ta, c2, sp2, w.adj.part, tiles,
@@ -775,6 +837,11 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
                 accepted = decisions_in[slot];
                 bool ok = false;
                 if (eps_replay) {
+                    // the step this iteration's own gradient gives, logged but not taken
+                    if (eps_out) {
+                        project(G, accepted, e_next);
+                        std::copy(e_next.begin(), e_next.end(), eps_out + slot * 2 * K);
+                    }
                     e_try.assign(eps_replay + slot * 2 * K, eps_replay + (slot + 1) * 2 * K);
                     if ((rc = upload(e_try, w.eps[trial]))) return rc;
                     if ((rc = sweep(trial))) return rc;
@@ -841,6 +908,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
             e_base = e_cand;
             std::swap(base, cand);
             if (decisions_out) decisions_out[slot] = accepted;
+            if (eps_out && !eps_replay) std::copy(e_base.begin(), e_base.end(), eps_out + slot * 2 * K);
             if (phi_out) {
                 phi_out[kStepLog * slot + 1] = phi_acc;
                 phi_out[kStepLog * slot + 3] = K_acc;
@@ -957,6 +1025,8 @@ struct BImg {
     int phase = 0;  // kPhGrad, kPhSearch, kPhPd or kPhDone
     int j = 0;      // multiplier iteration in progress
     int it = 0;     // gradient evaluations within it
+    double K_acc = 0.0;             // TV energy after the last accepted trial
+    const abc_solve_log* log = nullptr;  // caller's record / replay arrays (may be NULL)
     abc_stats S;
     abc_stats E;
     double finish_ms = 0;
@@ -1119,14 +1189,22 @@ struct Batch {
         return ABC_OK;
     }
 
-    // Waits for the lane and reads the objectives queued by objective_launch into phi.
-    int objective_read(const std::vector<int>& who, BatchLane& L, std::vector<double>& phi) {
+    // Waits for the lane and reads the objectives queued by objective_launch into
+    // phi (and the TV energies K = TV + fidelity of the same fields into Kv, if given).
+    int objective_read(const std::vector<int>& who, BatchLane& L, std::vector<double>& phi,
+                       std::vector<double>* Kv = nullptr) {
         phi.assign(who.size(), 0.0);
+        if (Kv) Kv->assign(who.size(), 0.0);
         if (who.empty()) return ABC_OK;
         std::vector<float> q(who.size() * abc::kPdQuantities);
         ABC_HIP(hipMemcpyAsync(q.data(), L.q_all, q.size() * sizeof(float), hipMemcpyDeviceToHost, L.st));
         ABC_HIP(hipStreamSynchronize(L.st));
-        for (size_t j = 0; j < who.size(); ++j) phi[j] = im[who[j]].area * (double)q[j * abc::kPdQuantities];
+        for (size_t j = 0; j < who.size(); ++j) {
+            const double a = im[who[j]].area;
+            const float* qj = q.data() + j * abc::kPdQuantities;
+            phi[j] = a * (double)qj[0];
+            if (Kv) (*Kv)[j] = a * (double)qj[1] + a * 0.5 * (double)p->alpha * (double)qj[2];
+        }
         return ABC_OK;
     }
 
@@ -1281,7 +1359,7 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
 }
 
 int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, void* ws, size_t ws_bytes,
-                      void* stream, abc_stats* st, double* finish_ms) {
+                      void* stream, abc_stats* st, double* finish_ms, const abc_solve_log* logs) {
     int rc = check_params(p);
     if (rc) return rc;
     if (!imgs || n < 1) return fail(ABC_EINVAL, "imgs must be non-NULL and n >= 1");
@@ -1292,6 +1370,8 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
         if (!imgs[i].c0 || !imgs[i].c_out) return fail(ABC_EINVAL, "every image needs c0 and c_out");
         Hs[i] = imgs[i].H;
         Ws[i] = imgs[i].W;
+        if (logs && logs[i].eps_replay && !logs[i].decisions_in)
+            return fail(ABC_EINVAL, "eps_replay needs decisions_in");
     }
     Batch B;
     B.n = n;
@@ -1336,6 +1416,15 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
         m.c_out = imgs[i].c_out;
         m.eps_user = imgs[i].eps;
         m.mu_user = imgs[i].mu;
+        m.log = logs ? &logs[i] : nullptr;
+        if (m.log) {
+            const size_t nslots = (size_t)std::max(p->max_outer, 1) * std::max(p->max_inner, 1);
+            if (m.log->decisions_out) std::fill(m.log->decisions_out, m.log->decisions_out + nslots, 0.0);
+            if (m.log->grad_out) std::fill(m.log->grad_out, m.log->grad_out + nslots * 2 * K, 0.0);
+            if (m.log->phi_out) std::fill(m.log->phi_out, m.log->phi_out + nslots * kStepLog, 0.0);
+            if (m.log->outer_out) std::fill(m.log->outer_out, m.log->outer_out + (size_t)std::max(p->max_outer, 1) * 4, 0.0);
+            if (m.log->eps_out) std::fill(m.log->eps_out, m.log->eps_out + nslots * 2 * K, 0.0);
+        }
         m.e_base.assign((size_t)K * 2, (double)p->eps_init);
         m.e_try = m.e_cand = m.e_next = m.e_base;
         m.sigma = p->sigma0;
@@ -1392,7 +1481,7 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
             if (B.im[i].phase == ph) v.push_back(i);
         return v;
     };
-    std::vector<double> phi_s;
+    std::vector<double> phi_s, K_s;
     for (;;) {
         std::vector<int> act = in_phase(kPhGrad);
         std::vector<int> search = in_phase(kPhSearch);
@@ -1404,7 +1493,11 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
             std::vector<const std::vector<double>*> vals;
             for (int i : search) {
                 BImg& m = B.im[i];
-                B.project(m, m.tau, m.e_try);
+                const size_t slot = (size_t)m.j * P + (m.it - 1);
+                if (m.log && m.log->eps_replay)
+                    m.e_try.assign(m.log->eps_replay + slot * 2 * K, m.log->eps_replay + (slot + 1) * 2 * K);
+                else
+                    B.project(m, m.tau, m.e_try);
                 tslot.push_back(m.trial);
                 vals.push_back(&m.e_try);
             }
@@ -1428,13 +1521,18 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
                 m.S.phi_last = m.phi0;
                 m.S.inner_iters++;
                 m.it++;
+                const size_t slot = (size_t)m.j * P + (m.it - 1);
+                const abc_solve_log* lg = m.log;
+                if (lg && lg->grad_out) std::copy(m.G.begin(), m.G.end(), lg->grad_out + slot * 2 * K);
+                if (lg && lg->phi_out) lg->phi_out[kStepLog * slot] = m.phi0;
                 bool all_zero = true;
                 for (double g : m.G) all_zero = all_zero && (g == 0.0);
-                if (all_zero) {
+                const bool replay = lg && lg->decisions_in;
+                if (replay ? !(lg->decisions_in[slot] > 0.0) : all_zero) {
                     end_inner(m);
                     continue;
                 }
-                m.tau = m.sigma;
+                m.tau = replay ? lg->decisions_in[slot] : m.sigma;
                 m.evals = 0;
                 m.branch = 0;
                 m.have = false;
@@ -1446,9 +1544,12 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
         }
         // Armijo decisions of the trials
         if (!search.empty()) {
-            if ((rc = B.objective_read(search, B.w.b, phi_s))) return rc;
+            if ((rc = B.objective_read(search, B.w.b, phi_s, &K_s))) return rc;
             for (size_t a = 0; a < search.size(); ++a) {
                 BImg& m = B.im[search[a]];
+                const size_t slot = (size_t)m.j * P + (m.it - 1);
+                const abc_solve_log* lg = m.log;
+                const bool replay = lg && lg->decisions_in;
                 m.evals++;
                 double ip = 0.0;
                 for (int q = 0; q < 2 * K; ++q) ip += m.G[q] * (m.e_try[q] - m.e_base[q]);
@@ -1459,10 +1560,20 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
                     m.e_cand = m.e_try;
                     m.accepted = m.tau;
                     m.phi_acc = phi_s[a];
+                    m.K_acc = K_s[a];
                     m.have = true;
                 };
                 bool more = false;
-                if (m.branch == 0) {
+                if (replay) {
+                    // a replayed step is taken as recorded; with replayed controls the
+                    // step this iteration's own gradient gives is logged
+                    if (lg->eps_replay && lg->eps_out) {
+                        B.project(m, m.tau, m.e_next);
+                        std::copy(m.e_next.begin(), m.e_next.end(), lg->eps_out + slot * 2 * K);
+                    }
+                    keep();
+                    m.ls_done = true;
+                } else if (m.branch == 0) {
                     if (ok) {
                         keep();
                         m.branch = 1;
@@ -1492,13 +1603,24 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
                 }
                 if (more) continue;
                 m.S.ls_evals += m.evals;
+                if (lg && lg->phi_out) lg->phi_out[kStepLog * slot + 2] = m.evals;
                 if (!m.have) {
                     end_inner(m);
                     continue;
                 }
-                m.sigma = m.accepted;
+                if (!replay) m.sigma = m.accepted;
                 m.e_base = m.e_cand;
                 std::swap(m.base, m.cand);
+                if (lg) {
+                    if (lg->decisions_out) lg->decisions_out[slot] = m.accepted;
+                    if (lg->eps_out && !lg->eps_replay)
+                        std::copy(m.e_base.begin(), m.e_base.end(), lg->eps_out + slot * 2 * K);
+                    if (lg->phi_out) {
+                        lg->phi_out[kStepLog * slot + 1] = m.phi_acc;
+                        lg->phi_out[kStepLog * slot + 3] = m.K_acc;
+                        lg->phi_out[kStepLog * slot + 4] = now_ms();
+                    }
+                }
                 if ((p->tol_dal > 0.0 && std::fabs(m.phi_acc - m.phi0) < p->tol_dal * std::fabs(m.phi0)) ||
                     m.it >= P)
                     end_inner(m);
@@ -1525,6 +1647,13 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
             m.S.outer_iters = m.j + 1;
             m.S.gap_rel = std::isnan(m.L_prev) ? NAN : std::fabs(m.E.L - m.L_prev) / std::fabs(m.L_prev);
             m.L_prev = m.E.L;
+            if (m.log && m.log->outer_out) {
+                double* o = m.log->outer_out + 4 * (size_t)m.j;
+                o[0] = m.E.K;
+                o[1] = m.E.L;
+                o[2] = m.E.r_rel;
+                o[3] = t_now;
+            }
             const bool gap_ok = p->tol_gap > 0.0 && !std::isnan(m.S.gap_rel) && m.S.gap_rel < p->tol_gap;
             if ((p->tol_alm > 0.0 && m.E.r_rel < p->tol_alm) || (p->stop_K > 0.0 && m.E.K <= p->stop_K) || gap_ok ||
                 m.j + 1 == M) {

@@ -82,3 +82,45 @@ def test_batched_default_and_runtime_radius_tiles_equal_individual_solves(R, C, 
         assert torch.equal(outs[i], ref["c"]), i
         for key in ("K", "L", "inner_iters", "ls_evals", "outer_iters"):
             assert stats[i][key] == ref["stats"][key], (i, key)
+
+
+@pytest.mark.parametrize("C,cost", [(3, A.ABC_COST_TV), (3, A.ABC_COST_QUADRATIC), (31, A.ABC_COST_TV)])
+def test_batched_images_match_the_oracle_under_control_replay(orc, C, cost):
+    """Every image of an uneven batch against its own FP64 oracle solve (Alg. 2
+    around Alg. 1, or Alg. 1 alone on the quadratic cost), with each image's
+    accepted controls replayed as in the single-image parity tests: final field
+    1e-4, energies 1e-5, the control gradient of every DAL iteration 1e-4
+    (relative l2), and the GPU's own projected step from its gradient."""
+    from tests.solve_checks import grad_errors, own_step_errors
+    print(f"[case] batched vs oracle, C={C} cost={cost}", flush=True)
+    shapes = [(40, 57), (33, 33), (16, 90), (27, 44)] if C == 3 else [(24, 30), (17, 33), (30, 16)]
+    K = 10 if C == 3 else 5
+    # 31 noisy bands put every pair of pixels outside the kernel's support at sigma = 0.05
+    # (G = 0 from the start), so the spectral images carry less noise
+    noise = 0.05 if C == 3 else 0.01
+    imgs = [voronoi_image(h, w, C, 4, noise, 900 + i, spectra=C > 3) for i, (h, w) in enumerate(shapes)]
+    gp = A.Params(K=K, R=2, alpha=20.0, max_outer=2, max_inner=4, cost=cost)
+    refs = []
+    for x in imgs:
+        op = orc.Params(K=K, R=2, alpha=20.0, max_outer=2, max_inner=4, cost=1 if cost else 0)
+        refs.append(orc.solve(x, op))
+    outs, stats, _, logs = A.abc_solve_batched(
+        [T(x) for x in imgs], gp, eps=[T(np.full((K, 2), 57.0)) for _ in imgs],
+        decisions=[r["decisions"] for r in refs], eps_replay=[r["eps_log"] for r in refs], want_logs=True)
+    torch.cuda.synchronize()
+    for i, (x, ref) in enumerate(zip(imgs, refs)):
+        assert np.count_nonzero(ref["decisions"]) >= 2, i
+        c = outs[i].cpu().numpy().astype(np.float64)
+        e_c = np.max(np.abs(c - ref["c"])) / np.max(np.abs(ref["c"]))
+        g_err = grad_errors(logs[i]["grad_log"], ref["grad_log"])
+        steps = own_step_errors(logs[i], ref)
+        print(f"[batched] image {i} {shapes[i]}: c {e_c:.2e} grad {g_err.max():.2e} "
+              f"own step {steps[:, 1].max():.2e} (bound {steps[:, 2].max():.2e})", flush=True)
+        assert np.array_equal(logs[i]["decisions"], ref["decisions"]), i
+        assert e_c < 1e-4, i
+        keys = ("K", "TV", "fid", "Ltilde") if cost else ("K", "TV", "fid", "L", "Ltilde")
+        for key in keys:
+            assert abs(stats[i][key] - ref["stats"][key]) <= 1e-5 * abs(ref["stats"][key]), (i, key)
+        assert g_err.size > 0 and g_err.max() < 1e-4, i
+        assert np.all(steps[:, 0] <= 1e-12 * 1100.0), i
+        assert np.all(steps[:, 1] <= steps[:, 2] * (1 + 1e-9) + 1e-9), i
