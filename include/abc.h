@@ -168,6 +168,24 @@ int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* ep
                          const abc_params* p, const float* gK, float* g0, float* geps,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* abc_adjoint_dynamics for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and results (bit for bit) as
+ * abc_adjoint_dynamics, without ws / ws_bytes: the workspace (the two adjoint
+ * ping-pong fields, the per-step control-gradient partials and, when
+ * checkpointed, the recomputed segment) lives in a device array of
+ * ABC_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  Nothing is allocated or freed by the call.  Every
+ * call on a GPU shares that GPU's array, so calls that overlap on one GPU
+ * (different streams or host threads) race: order them.  Returns ABC_EINVAL,
+ * before any launch, when abc_workspace_bytes(ABC_WS_ADJOINT, ...) exceeds
+ * ABC_NOALLOC_SCRATCH_BYTES (for example 3 channels at K = 50 fit up to about
+ * 1.3 million pixels).  Asynchronous. */
+#define ABC_NOALLOC_SCRATCH_BYTES (32u << 20)
+int abc_adjoint_dynamics_noalloc(const float* traj, int H, int W, int C, const float* eps,
+                                 const abc_params* p, const float* gK, float* g0, float* geps,
+                                 void* stream);
+
 /* Terminal condition of the adjoint for the completed-square functional
  * (eq. complete_square, eq. admm_terminal with div = -grad#^T):
  *   gK = dx dy [ div(mu + rho (v - grad# cK)) + alpha (cK - c0) ],

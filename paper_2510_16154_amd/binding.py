@@ -168,6 +168,8 @@ def lib():
                                        ct.c_size_t, _vp]
     L.abc_adjoint_dynamics.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, _vp, ct.POINTER(AbcParams), _vp, _vp,
                                        _vp, _vp, ct.c_size_t, _vp]
+    L.abc_adjoint_dynamics_noalloc.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, _vp, ct.POINTER(AbcParams), _vp,
+                                               _vp, _vp, _vp]
     L.abc_pd_terminal.argtypes = [_vp, _vp, _vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp,
                                   ct.POINTER(ct.c_double), _vp, ct.c_size_t, _vp]
     L.abc_pd_step.argtypes = [_vp, _vp, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams), _vp, _vp, ct.c_int,
@@ -295,6 +297,17 @@ def abc_adjoint_dynamics(traj, eps, params: Params, gK, g0=None, geps=None, ws=N
     p = params.to_c()
     _check(lib().abc_adjoint_dynamics(_ptr(traj), H, W, C, _ptr(eps), ct.byref(p), _ptr(gK), _ptr(g0),
                                       _ptr(geps), ct.c_void_p(ws.data_ptr()), nb, _stream()))
+    return g0, geps
+
+
+def abc_adjoint_dynamics_noalloc(traj, eps, params: Params, gK, g0, geps):
+    """abc_adjoint_dynamics on the library's own per-GPU scratch (see abc.h):
+    the caller passes the outputs g0 (like gK) and geps (K x 2); nothing is
+    allocated.  Calls that overlap on one GPU race."""
+    H, W, C = gK.shape
+    p = params.to_c()
+    _check(lib().abc_adjoint_dynamics_noalloc(_ptr(traj), H, W, C, _ptr(eps), ct.byref(p), _ptr(gK), _ptr(g0),
+                                              _ptr(geps), _stream()))
     return g0, geps
 
 

@@ -9,6 +9,7 @@
 #include <array>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -424,6 +425,33 @@ __global__ void zero_kernel(float* __restrict__ x, int n) {
     if (i < n) x[i] = 0.0f;
 }
 
+}  // namespace
+
+// Scratch of abc_adjoint_dynamics_noalloc: one array per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, so the
+// device address comes from hipGetSymbolAddress, once per device (with that
+// device current), and only that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[ABC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(void** out) {
+    int dev = 0;
+    ABC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ABC_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        ABC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(ABC_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ABC_OK;
+}
 }
 
 // ===========================================================================
@@ -524,6 +552,24 @@ int abc_forward_dynamics(const float* c0, int H, int W, int C, const float* eps,
 int abc_adjoint_dynamics(const float* traj, int H, int W, int C, const float* eps, const abc_params* p,
                          const float* gK, float* g0, float* geps, void* ws, size_t ws_bytes, void* stream) {
     return adjoint_dynamics_impl(traj, H, W, C, eps, p, gK, g0, geps, ws, ws_bytes, stream);
+}
+
+int abc_adjoint_dynamics_noalloc(const float* traj, int H, int W, int C, const float* eps, const abc_params* p,
+                                 const float* gK, float* g0, float* geps, void* stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if ((rc = check_shape(H, W, C))) return rc;
+    abc::Tile tf, ta;
+    if ((rc = pick_tile(p, C, 1, &tf))) return rc;
+    if ((rc = pick_tile(p, C, 2, &ta))) return rc;
+    const size_t need = ws_bytes_for(ABC_WS_ADJOINT, Shape{H, W, C}, p, tf, ta);
+    if (need > ABC_NOALLOC_SCRATCH_BYTES)
+        return fail(ABC_EINVAL, "abc_adjoint_dynamics_noalloc: this shape needs " + std::to_string(need) +
+                                    " bytes of scratch, more than the " +
+                                    std::to_string((size_t)ABC_NOALLOC_SCRATCH_BYTES) + " the library holds");
+    void* sp = nullptr;
+    if ((rc = scratch_ptr(&sp))) return rc;
+    return adjoint_dynamics_impl(traj, H, W, C, eps, p, gK, g0, geps, sp, ABC_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 }  // extern "C"
