@@ -88,13 +88,17 @@ def test_training_lowers_the_loss():
 
 
 def test_trained_network_gains_over_the_cold_start():
-    """What the packaged weights buy over the method without them.  On eight
-    held-out 256 x 256 images solved by the plain method (seeds outside the
-    training range), the predicted start (mu0, eps0) lies closer to the solved
-    (mu, eps) than the cold start (mu = 0, eps = eps_init), in the training
-    loss; and a warm solve under the gap stop (predicted multiplier with cold
-    controls, and with the predicted controls too) ends at the cold solve's
-    energy or below (else it falls back to the cold result)."""
+    """What the packaged weights buy over the method without them, on eight
+    held-out 256 x 256 images (seeds outside the training range):
+    - the predicted start (mu0, eps0) lies closer to the solved (mu, eps) than
+      the cold start (mu = 0, eps = eps_init), in the training loss;
+    - solved under the gap stop of Sec. 4.1 (at most 20 multiplier x 10 DAL
+      iterations), the warm solve (predicted multiplier, cold controls) needs
+      fewer multiplier iterations and fewer DAL iterations than the cold one, in
+      the median over the images.  A warm solve that ends above the cold
+      solve's energy (1e-4 relative) falls back to the cold result and is
+      counted with the iterations of both solves.  Iteration counts are
+      deterministic (the library's sums have a fixed order)."""
     from paper_2510_16154_amd.warmstart import TRAINED_K50, WarmStart, cold_solve, make_dataset
     params = A.Params(K=50, R=5, max_outer=5, max_inner=10, alpha=3000.0)
     ws = WarmStart.load(TRAINED_K50, 50, params)
@@ -108,11 +112,18 @@ def test_trained_network_gains_over_the_cold_start():
     print(f"held-out loss: trained {loss_net:.4f}, cold start {loss_cold:.4f}", flush=True)
     assert loss_net < 0.8 * loss_cold
     pe = params.replace(max_outer=20, tol_gap=1e-2)
-    for i in range(2):
+    rows = []
+    for i in range(8):
         img = x[i].contiguous()
         cold = cold_solve(img, pe)
-        for use_eps in (False, True):
-            warm = ws.solve(img, pe, cold=cold, use_eps=use_eps)
-            print(f"image {i}: cold {cold['seconds']:.3f} s K {cold['K']:.5g}; warm (eps {use_eps}) "
-                  f"{warm['seconds']:.3f} s K {warm['K']:.5g} fallback {warm['fallback']}", flush=True)
-            assert warm["K"] <= cold["K"] * (1 + 1e-4)
+        warm = ws.solve(img, pe, cold=cold)
+        print(f"image {i}: cold {cold['outer_iters']} x / {cold['dal_iters']} DAL, K {cold['K']:.5g}; warm "
+              f"{warm['outer_iters']} x / {warm['dal_iters']} DAL, K {warm['K']:.5g}, fallback {warm['fallback']}",
+              flush=True)
+        assert warm["K"] <= cold["K"] * (1 + 1e-4)
+        rows.append((cold["outer_iters"], warm["outer_iters"], cold["dal_iters"], warm["dal_iters"]))
+    r = np.array(rows, dtype=float)
+    print(f"median multiplier iterations cold {np.median(r[:, 0])} warm {np.median(r[:, 1])}; "
+          f"DAL cold {np.median(r[:, 2])} warm {np.median(r[:, 3])}", flush=True)
+    assert np.median(r[:, 1]) < np.median(r[:, 0])
+    assert np.median(r[:, 3]) < np.median(r[:, 2])
