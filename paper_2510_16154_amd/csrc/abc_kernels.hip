@@ -354,10 +354,13 @@ fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 // The control gradient uses the symmetric-window identity
 //   sum_i sum_j phi' w (p_i . D_ij) = -1/2 sum_i sum_j phi' w (D_ij . (p_j - p_i))
 // (w symmetric, D antisymmetric), so dl/deps_x^k = -5 dt s sum sx and
-// dl/deps_c^k = -5 dt s sum sc.  Each pixel sums its window in FP32; the sum
-// over pixels is carried in FP64 (the solver's projected steps can reach
-// 1e13 or more, which amplifies rounding in this sum directly into the
-// controls).
+// dl/deps_c^k = -5 dt s sum sc.  The integrands d^2 q and |D|^2 q of a pair are
+// the same numbers for (i, j) and (j, i) (D and dp only change sign), so with a
+// compile-time radius each pixel sums them over the forward half of its window
+// (a > 0, or a = 0 and b > 0) and the workgroup doubles its sums.  Each pixel
+// sums its window in FP32; the sum over pixels is carried in FP64 (the
+// solver's projected steps can reach 1e13 or more, which amplifies rounding
+// in this sum directly into the controls).
 template <int CP, int RT, int NP, bool BORDER>
 __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int LW, int R,
                                            const float (&ci)[NP][CP], const float (&pi)[NP][CP],
@@ -411,8 +414,10 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
                     acc[m][ch] = fmaf(w, dp[ch], acc[m][ch]);
                     accq[m][ch] = fmaf(q, d[ch], accq[m][ch]);
                 }
-                sx[m] = fmaf(d2, q, sx[m]);
-                sc[m] = fmaf(n2, q, sc[m]);
+                if (RT == 0 || a > 0 || (a == 0 && b > 0)) {
+                    sx[m] = fmaf(d2, q, sx[m]);
+                    sc[m] = fmaf(n2, q, sc[m]);
+                }
             }
         }
     }
@@ -467,8 +472,9 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
 #pragma unroll
             for (int ch = 0; ch < CP; ++ch)
                 if (ch < C) o[ch] = fmaf(dts, fmaf(ec20, accq[m][ch], acc[m][ch]), pi[m][ch]);
-            tsx += (double)sx[m];
-            tsc += (double)sc[m];
+            // half-window sums count each unordered pair once
+            tsx += (RT > 0 ? 2.0 : 1.0) * (double)sx[m];
+            tsc += (RT > 0 ? 2.0 : 1.0) * (double)sc[m];
         }
     }
     const double bx = block_sum_f64(tsx, red);
