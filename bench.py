@@ -102,6 +102,12 @@ def main() -> int:
                     help="voronoi512: DAL stationarity tolerance of the second converged solve")
     ap.add_argument("--no-graphs", action="store_true",
                     help="batch64: launch every sweep step directly instead of replaying captured graphs")
+    ap.add_argument("--persistent", type=int, default=None, choices=[0, 1],
+                    help="batch64: persistent sweeps over per-step tile queues (1) or one workgroup per tile (0); "
+                         "default: the faster form as measured (see the design notes)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="batch64: tiles timed by the library's tuner on the largest image (1, default) or the "
+                         "library's default tiles (0)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit; used to calibrate "
                          "the HBM byte counters")
@@ -259,6 +265,10 @@ def main() -> int:
     return 0
 
 
+# Whether the batched line runs its sweeps as persistent launches over per-step tile
+# queues (ABC_FLAG_PERSISTENT): the faster of the two forms as measured on the 64-image batch.
+BATCH_PERSISTENT = True
+
 # Relative change of the inner objective below which the second converged solve
 # ends a control argmin (convergence remark, Sec. 3.2).  The paper's 1e-10 is
 # below what FP32 objectives resolve; this is the smallest value measurably
@@ -373,7 +383,10 @@ def bench_batch(args) -> int:
 
     dev = torch.device("cuda:0")
     imgs = [torch.as_tensor(x, device=dev) for x in wb.images()]
-    params = wb.params(flags=A.ABC_FLAG_NO_GRAPHS if args.no_graphs else 0)
+    persistent = BATCH_PERSISTENT if args.persistent is None else bool(args.persistent)
+    flags = ((A.ABC_FLAG_NO_GRAPHS if args.no_graphs else 0) | (A.ABC_FLAG_PERSISTENT if persistent else 0) |
+             (A.ABC_FLAG_AUTOTUNE if args.autotune else 0))
+    params = wb.params(flags=flags)
     shapes = [(x.shape[0], x.shape[1]) for x in imgs]
     ws = torch.empty(A.abc_workspace_bytes_batched(shapes, wb.C, params), dtype=torch.uint8, device=dev)
     npx = sum(h * w for h, w in shapes)
@@ -394,7 +407,8 @@ def bench_batch(args) -> int:
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded Voronoi images)",
            "config": {"workload": wb.name, "images": wb.n, "pixels": npx, "R": wb.R, "K": wb.K,
-                      "schedule": f"{wb.max_outer}x{wb.max_inner}", "graphs": not args.no_graphs},
+                      "schedule": f"{wb.max_outer}x{wb.max_inner}", "graphs": not args.no_graphs,
+                      "persistent": persistent, "autotune": bool(args.autotune)},
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
            "sweeps_per_solve": evals,
            "agent_steps_per_s": npx * wb.K * evals / len(stats) / t}

@@ -91,6 +91,14 @@ typedef struct abc_params {
 } abc_params;
 
 #define ABC_FLAG_NO_GRAPHS 1 /* launch every sweep step directly instead of replaying captured HIP graphs */
+#define ABC_FLAG_AUTOTUNE 2  /* abc_solve_batched with no tile given: time the tile candidates on the batch's
+                                largest image first (as abc_autotune) and use the fastest; the choice is kept
+                                for the process per GPU architecture, C, R and size class.  Other entry
+                                points ignore it */
+#define ABC_FLAG_PERSISTENT 4 /* abc_solve_batched: each Euler step runs as a grid of as many workgroups as
+                                 the GPU holds at once, taking the tiles of all images from per-step atomic
+                                 counters, instead of one workgroup per tile.  Same results.  Other entry
+                                 points ignore it */
 
 #define ABC_COST_TV 0        /* TV + fidelity (eq. cost_TV), method of multipliers (Alg. 2)  */
 #define ABC_COST_QUADRATIC 1 /* quadratic J (Def. 3.2), direct-adjoint loop alone (Alg. 1) */
@@ -301,6 +309,8 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
  *   st: host array of n stats (may be NULL).
  *   finish_ms: host array of n completion times in ms after the call began
  *     (may be NULL).
+ *   Workspace: abc_workspace_bytes_batched() with the same flags (ABC_FLAG_AUTOTUNE
+ *     asks for room for any tile the tuner may pick).
  *   logs: host array of n record / replay logs, one per image, with the
  *     meaning and sizes abc_solve gives them (may be NULL, and so may each
  *     array in them); outer_out's times are ms since this call began.

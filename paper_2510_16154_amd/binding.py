@@ -21,6 +21,8 @@ ABC_WS_SOLVE, ABC_WS_FORWARD, ABC_WS_ADJOINT, ABC_WS_PD = 0, 1, 2, 3
 ABC_COST_TV, ABC_COST_QUADRATIC = 0, 1
 ABC_WS_TUNE = 4
 ABC_FLAG_NO_GRAPHS = 1
+ABC_FLAG_AUTOTUNE = 2
+ABC_FLAG_PERSISTENT = 4
 
 
 class AbcParams(ct.Structure):
@@ -88,7 +90,7 @@ class Params:
     cost: int = 0  # ABC_COST_TV (0) or ABC_COST_QUADRATIC (1)
     adj_tile_x: int = 0
     adj_tile_y: int = 0
-    flags: int = 0  # ABC_FLAG_NO_GRAPHS (1): direct launches instead of captured sweeps
+    flags: int = 0  # ABC_FLAG_NO_GRAPHS (1), ABC_FLAG_AUTOTUNE (2), ABC_FLAG_PERSISTENT (4); see abc.h
     stop_K: float = 0.0  # > 0: stop once the TV energy K reaches this value
     tol_gap: float = 0.0  # > 0: stop once L changes by less than this (relative) between iterations
 

@@ -189,7 +189,8 @@ int check_params(const abc_params* p) {
         return fail(ABC_EINVAL, "Armijo parameters: sigma0 > 0, b and c in (0,1)");
     if (p->ckpt_every < 0) return fail(ABC_EINVAL, "ckpt_every must be >= 0");
     if (p->cost != ABC_COST_TV && p->cost != ABC_COST_QUADRATIC) return fail(ABC_EINVAL, "unknown cost");
-    if (p->flags & ~ABC_FLAG_NO_GRAPHS) return fail(ABC_EINVAL, "unknown flag bits");
+    if (p->flags & ~(ABC_FLAG_NO_GRAPHS | ABC_FLAG_AUTOTUNE | ABC_FLAG_PERSISTENT))
+        return fail(ABC_EINVAL, "unknown flag bits");
     if (!(p->stop_K >= 0.0)) return fail(ABC_EINVAL, "stop_K must be >= 0");
     if (!(p->tol_gap >= 0.0)) return fail(ABC_EINVAL, "tol_gap must be >= 0");
     return ABC_OK;
@@ -423,6 +424,11 @@ int adjoint_dynamics_impl(const float* traj, int H, int W, int C, const float* e
 __global__ void zero_kernel(float* __restrict__ x, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0.0f;
+}
+
+__global__ void zero_i32_kernel(int* __restrict__ x, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0;
 }
 
 }  // namespace
@@ -1033,6 +1039,137 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
 
 }  // extern "C"
 
+namespace {
+
+struct TuneEntry {
+    int ftx, fty, atx, aty;
+    double fus, aus;
+};
+
+std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
+    std::map<std::string, TuneEntry> out;
+    if (!path) return out;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), fp)) {
+        const char* q1 = std::strchr(line, '"');
+        if (!q1) continue;
+        const char* q2 = std::strchr(q1 + 1, '"');
+        if (!q2) continue;
+        TuneEntry e;
+        if (std::sscanf(q2 + 1, ": {\"fwd\": [%d, %d], \"adj\": [%d, %d], \"fwd_us\": %lf, \"adj_us\": %lf}", &e.ftx,
+                        &e.fty, &e.atx, &e.aty, &e.fus, &e.aus) == 6)
+            out[std::string(q1 + 1, q2)] = e;
+    }
+    std::fclose(fp);
+    return out;
+}
+
+bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return false;
+    std::fprintf(fp, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m) {
+        const TuneEntry& e = kv.second;
+        std::fprintf(fp, "  \"%s\": {\"fwd\": [%d, %d], \"adj\": [%d, %d], \"fwd_us\": %.3f, \"adj_us\": %.3f}%s\n",
+                     kv.first.c_str(), e.ftx, e.fty, e.atx, e.aty, e.fus, e.aus, (++i < m.size()) ? "," : "");
+    }
+    std::fprintf(fp, "}\n");
+    std::fclose(fp);
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+const abc::Tile kTuneCands[] = {{32, 16}, {64, 8}, {16, 32}, {128, 4}, {32, 8}, {16, 16}, {64, 4}, {128, 2},
+                                {16, 8},  {32, 4}, {64, 2},  {8, 16},  {8, 8},  {16, 4},  {32, 2}, {64, 1}};
+
+size_t tune_ws_bytes(int H, int W, int C) {
+    Carve cv(nullptr);
+    const size_t f = (size_t)H * W * C;
+    cv.take<float>(f);
+    cv.take<float>(f);
+    cv.take<float>(2);
+    int maxt = 0;
+    for (const abc::Tile& t : kTuneCands) maxt = std::max(maxt, abc::tile_count(H, W, t));
+    cv.take<double>((size_t)maxt * 2);
+    return cv.used;
+}
+
+
+// Times the forward and adjoint interaction kernels on c0 for every admissible
+// tile shape and returns the fastest of each in *best.  ws: tune_ws_bytes().
+int tune_tiles(const float* c0, int H, int W, int C, const abc_params* p, void* ws, hipStream_t st, TuneEntry* best) {
+    const size_t f = (size_t)H * W * C;
+    Carve cv(ws);
+    float* out = cv.take<float>(f);
+    float* pout = cv.take<float>(f);
+    float* eps = cv.take<float>(2);
+    double* part = nullptr;
+    {
+        int maxt = 0;
+        for (const abc::Tile& t : kTuneCands) maxt = std::max(maxt, abc::tile_count(H, W, t));
+        part = cv.take<double>((size_t)maxt * 2);
+    }
+    const float e2[2] = {p->eps_init, p->eps_init};
+    ABC_HIP(hipMemcpyAsync(eps, e2, sizeof(e2), hipMemcpyHostToDevice, st));
+    ABC_HIP(hipStreamSynchronize(st));
+    const Shape s{H, W, C};
+    const float dts = p->dt * norm_factor(p, s);
+    hipEvent_t ev0, ev1;
+    ABC_HIP(hipEventCreate(&ev0));
+    ABC_HIP(hipEventCreate(&ev1));
+    *best = TuneEntry{0, 0, 0, 0, 1e30, 1e30};
+    constexpr int kReps = 5;
+    int rc = ABC_OK;
+    for (int kind = 0; kind < 2 && rc == ABC_OK; ++kind) {
+        for (const abc::Tile& t : kTuneCands) {
+            if (!abc::tile_ok(C, p->R, t, kind + 1)) continue;
+            auto launch = [&]() -> hipError_t {
+                return kind == 0 ? abc::launch_forward_step(c0, out, eps, 0, H, W, C, p->R, dts, t, st)
+                                 : abc::launch_adjoint_step(c0, c0, pout, eps, 0, H, W, C, p->R, dts, t, part, st);
+            };
+            hipError_t e = launch();  // warm-up (also sets the LDS attribute)
+            if (e != hipSuccess) continue;
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 3 && rc == ABC_OK; ++rep) {
+                hipError_t e1 = hipEventRecord(ev0, st);
+                for (int i = 0; i < kReps && e1 == hipSuccess; ++i) e1 = launch();
+                if (e1 == hipSuccess) e1 = hipEventRecord(ev1, st);
+                if (e1 == hipSuccess) e1 = hipEventSynchronize(ev1);
+                float ms = 0.0f;
+                if (e1 == hipSuccess) e1 = hipEventElapsedTime(&ms, ev0, ev1);
+                if (e1 != hipSuccess) {
+                    rc = fail(ABC_EHIP, std::string("autotune timing: ") + hipGetErrorString(e1));
+                    break;
+                }
+                ms_best = std::min(ms_best, ms);
+            }
+            if (rc) break;
+            const double us = 1e3 * (double)ms_best / kReps;
+            if (kind == 0 && us < best->fus) *best = TuneEntry{t.tx, t.ty, best->atx, best->aty, us, best->aus};
+            if (kind == 1 && us < best->aus) *best = TuneEntry{best->ftx, best->fty, t.tx, t.ty, best->fus, us};
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (rc) return rc;
+    if (best->ftx == 0 || best->atx == 0)
+        return fail(ABC_EINVAL, "no admissible tile for this channel count and radius");
+    return ABC_OK;
+}
+
+std::string gpu_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string arch(prop.gcnArchName);
+    return arch.substr(0, arch.find(':'));
+}
+
+}  // namespace
+
 // ===========================================================================
 // Batched solve: lockstep rounds over many images of different sizes.
 namespace {
@@ -1084,6 +1221,7 @@ struct BatchLane {
     abc::PixJob* pix_jobs;
     abc::RedJob* red_jobs;
     float* q_all;  // n x kPdQuantities
+    int* queue;    // K x 8 tile counters of the persistent sweeps
     hipStream_t st;
 };
 
@@ -1099,6 +1237,7 @@ void carve_batch(Carve& cv, int n, int K, BatchWs& b) {
         l->pix_jobs = cv.take<abc::PixJob>(n);
         l->red_jobs = cv.take<abc::RedJob>(n);
         l->q_all = cv.take<float>((size_t)n * abc::kPdQuantities);
+        l->queue = cv.take<int>((size_t)K * 8);
         l->st = nullptr;
     }
     b.eps_all = cv.take<float>((size_t)n * 3 * K * 2);
@@ -1128,6 +1267,7 @@ struct Batch {
     BatchWs w;
     std::vector<float> eps_host;  // mirror of eps_all
     GraphCache graphs;
+    bool persistent = false;      // sweeps as persistent launches over per-step tile queues
     hipStream_t own_b = nullptr;  // lane b's stream, created for the call
 
     Batch() = default;
@@ -1192,8 +1332,13 @@ struct Batch {
         // a recorded sweep reads the lane's own job table, so the lane is part of the key
         const long lane = &L == &w.b ? 1 : 0;
         return graphs.run(use_graphs, {0, total, nj, lane}, st, [&](hipStream_t s2) -> int {
+            int* q = persistent ? L.queue : nullptr;
+            if (q) {
+                zero_i32_kernel<<<(K * 8 + 255) / 256, 256, 0, s2>>>(q, K * 8);
+                ABC_HIP(hipGetLastError());
+            }
             for (int k = 0; k < K; ++k)
-                ABC_HIP(abc::launch_forward_step_batched(L.step_jobs, nj, total, k, C, p->R, tf, s2));
+                ABC_HIP(abc::launch_forward_step_batched(L.step_jobs, nj, total, k, C, p->R, tf, q, s2));
             return ABC_OK;
         });
     }
@@ -1300,8 +1445,13 @@ struct Batch {
                                    st));
             const int nj = (int)jobs.size();
             int r2 = graphs.run(use_graphs, {1, total, nj, 0}, st, [&](hipStream_t s2) -> int {
+                int* q = persistent ? L.queue : nullptr;
+                if (q) {
+                    zero_i32_kernel<<<(K * 8 + 255) / 256, 256, 0, s2>>>(q, K * 8);
+                    ABC_HIP(hipGetLastError());
+                }
                 for (int k = K - 1; k >= 0; --k)
-                    ABC_HIP(abc::launch_adjoint_step_batched(L.step_jobs, nj, total, k, K, C, p->R, ta, s2));
+                    ABC_HIP(abc::launch_adjoint_step_batched(L.step_jobs, nj, total, k, K, C, p->R, ta, q, s2));
                 ABC_HIP(abc::launch_reduce_jobs_f64(L.red_jobs, nj, K, 2, s2));
                 return ABC_OK;
             });
@@ -1372,6 +1522,18 @@ struct Batch {
     }
 };
 
+// abc_solve_batched tunes its tiles: asked for, with a window, and no tile given.
+bool tunes_batch(const abc_params* p) {
+    return (p->flags & ABC_FLAG_AUTOTUNE) && p->R > 0 && p->tile_x == 0 && p->tile_y == 0 && p->adj_tile_x == 0 &&
+           p->adj_tile_y == 0;
+}
+
+// Tiles tuned by abc_solve_batched, kept for the process: keyed by GPU
+// architecture, channels, radius and size class (the largest image's pixel
+// count rounded up to a power of two).
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tuned;
+
 size_t batch_ws_bytes(const int32_t* H, const int32_t* W, int n, int C, const abc_params* p, abc::Tile ta) {
     Carve cv(nullptr);
     BatchWs bw;
@@ -1401,6 +1563,16 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
     abc::Tile ta;
     if ((rc = pick_tile(p, C, 2, &ta))) return rc;
     *bytes = batch_ws_bytes(H, W, n, C, p, ta);
+    if (tunes_batch(p)) {
+        // the tuner may pick any admissible adjoint tile (the partials depend on it);
+        // it runs in the workspace before the solve carves it
+        int big = 0;
+        for (int i = 1; i < n; ++i)
+            if ((double)H[i] * W[i] > (double)H[big] * W[big]) big = i;
+        *bytes = std::max(*bytes, tune_ws_bytes(H[big], W[big], C));
+        for (const abc::Tile& t : kTuneCands)
+            if (abc::tile_ok(C, p->R, t, 2)) *bytes = std::max(*bytes, batch_ws_bytes(H, W, n, C, p, t));
+    }
     return ABC_OK;
 }
 
@@ -1419,6 +1591,39 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
         if (logs && logs[i].eps_replay && !logs[i].decisions_in)
             return fail(ABC_EINVAL, "eps_replay needs decisions_in");
     }
+    abc_params pt = *p;  // p with the tuned tiles, when the tiles are tuned
+    if (tunes_batch(p)) {
+        int big = 0;
+        for (int i = 1; i < n; ++i)
+            if ((double)Hs[i] * Ws[i] > (double)Hs[big] * Ws[big]) big = i;
+        int cls = 0;
+        while (((int64_t)1 << cls) < (int64_t)Hs[big] * Ws[big]) ++cls;
+        char keybuf[160];
+        std::snprintf(keybuf, sizeof(keybuf), "%s|C=%d|R=%d|px<=2^%d", gpu_arch().c_str(), C, p->R, cls);
+        TuneEntry te{0, 0, 0, 0, 0.0, 0.0};
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tuned.find(keybuf);
+            if (it != g_tuned.end()) {
+                te = it->second;
+                have = true;
+            }
+        }
+        if (!have) {
+            // the workspace is not in use yet: the tuner runs in it, on the largest image
+            if (!ws || ws_bytes < tune_ws_bytes(Hs[big], Ws[big], C))
+                return fail(ABC_EINVAL, "batched workspace too small for the tile tuner");
+            if ((rc = tune_tiles(imgs[big].c0, Hs[big], Ws[big], C, p, ws, (hipStream_t)stream, &te))) return rc;
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tuned[keybuf] = te;
+        }
+        pt.tile_x = te.ftx;
+        pt.tile_y = te.fty;
+        pt.adj_tile_x = te.atx;
+        pt.adj_tile_y = te.aty;
+    }
+    p = &pt;
     Batch B;
     B.n = n;
     B.C = C;
@@ -1433,6 +1638,7 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
     if (!ws || ws_bytes < need) return fail(ABC_EINVAL, "batched workspace too small");
     B.st = (hipStream_t)stream;
     B.use_graphs = !(p->flags & ABC_FLAG_NO_GRAPHS) && p->R > 0;
+    B.persistent = (p->flags & ABC_FLAG_PERSISTENT) != 0;
     const int K = p->K;
     Carve cv(ws);
     carve_batch(cv, n, K, B.w);
@@ -1786,66 +1992,6 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
 
 // ===========================================================================
 // Tile autotuner with a JSON cache.
-namespace {
-
-struct TuneEntry {
-    int ftx, fty, atx, aty;
-    double fus, aus;
-};
-
-std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
-    std::map<std::string, TuneEntry> out;
-    if (!path) return out;
-    FILE* fp = std::fopen(path, "r");
-    if (!fp) return out;
-    char line[1024];
-    while (std::fgets(line, sizeof(line), fp)) {
-        const char* q1 = std::strchr(line, '"');
-        if (!q1) continue;
-        const char* q2 = std::strchr(q1 + 1, '"');
-        if (!q2) continue;
-        TuneEntry e;
-        if (std::sscanf(q2 + 1, ": {\"fwd\": [%d, %d], \"adj\": [%d, %d], \"fwd_us\": %lf, \"adj_us\": %lf}", &e.ftx,
-                        &e.fty, &e.atx, &e.aty, &e.fus, &e.aus) == 6)
-            out[std::string(q1 + 1, q2)] = e;
-    }
-    std::fclose(fp);
-    return out;
-}
-
-bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE* fp = std::fopen(tmp.c_str(), "w");
-    if (!fp) return false;
-    std::fprintf(fp, "{\n");
-    size_t i = 0;
-    for (const auto& kv : m) {
-        const TuneEntry& e = kv.second;
-        std::fprintf(fp, "  \"%s\": {\"fwd\": [%d, %d], \"adj\": [%d, %d], \"fwd_us\": %.3f, \"adj_us\": %.3f}%s\n",
-                     kv.first.c_str(), e.ftx, e.fty, e.atx, e.aty, e.fus, e.aus, (++i < m.size()) ? "," : "");
-    }
-    std::fprintf(fp, "}\n");
-    std::fclose(fp);
-    return std::rename(tmp.c_str(), path) == 0;
-}
-
-const abc::Tile kTuneCands[] = {{32, 16}, {64, 8}, {16, 32}, {128, 4}, {32, 8}, {16, 16}, {64, 4}, {128, 2},
-                                {16, 8},  {32, 4}, {64, 2},  {8, 16},  {8, 8},  {16, 4},  {32, 2}, {64, 1}};
-
-size_t tune_ws_bytes(int H, int W, int C) {
-    Carve cv(nullptr);
-    const size_t f = (size_t)H * W * C;
-    cv.take<float>(f);
-    cv.take<float>(f);
-    cv.take<float>(2);
-    int maxt = 0;
-    for (const abc::Tile& t : kTuneCands) maxt = std::max(maxt, abc::tile_count(H, W, t));
-    cv.take<double>((size_t)maxt * 2);
-    return cv.used;
-}
-
-}  // namespace
-
 extern "C" int abc_autotune(const float* c0, int H, int W, int C, abc_params* p, const char* cache_path, void* ws,
                             size_t ws_bytes, void* stream, double* best_us) {
     int rc = check_params(p);
@@ -1854,14 +2000,8 @@ extern "C" int abc_autotune(const float* c0, int H, int W, int C, abc_params* p,
     if (!c0) return fail(ABC_EINVAL, "c0 must be non-NULL");
     if (best_us) best_us[0] = best_us[1] = 0.0;
     if (p->R == 0) return ABC_OK;
-    int dev = 0;
-    ABC_HIP(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    ABC_HIP(hipGetDeviceProperties(&prop, dev));
-    std::string arch(prop.gcnArchName);
-    arch = arch.substr(0, arch.find(':'));
     char keybuf[160];
-    std::snprintf(keybuf, sizeof(keybuf), "%s|C=%d|R=%d|H=%d|W=%d", arch.c_str(), C, p->R, H, W);
+    std::snprintf(keybuf, sizeof(keybuf), "%s|C=%d|R=%d|H=%d|W=%d", gpu_arch().c_str(), C, p->R, H, W);
     const std::string key(keybuf);
     std::map<std::string, TuneEntry> cache = read_tune_cache(cache_path);
     auto hit = cache.find(key);
@@ -1874,62 +2014,8 @@ extern "C" int abc_autotune(const float* c0, int H, int W, int C, abc_params* p,
         return ABC_OK;
     }
     if (!ws || ws_bytes < tune_ws_bytes(H, W, C)) return fail(ABC_EINVAL, "autotune workspace too small");
-    hipStream_t st = (hipStream_t)stream;
-    const size_t f = (size_t)H * W * C;
-    Carve cv(ws);
-    float* out = cv.take<float>(f);
-    float* pout = cv.take<float>(f);
-    float* eps = cv.take<float>(2);
-    double* part = nullptr;
-    {
-        int maxt = 0;
-        for (const abc::Tile& t : kTuneCands) maxt = std::max(maxt, abc::tile_count(H, W, t));
-        part = cv.take<double>((size_t)maxt * 2);
-    }
-    const float e2[2] = {p->eps_init, p->eps_init};
-    ABC_HIP(hipMemcpyAsync(eps, e2, sizeof(e2), hipMemcpyHostToDevice, st));
-    const Shape s{H, W, C};
-    const float dts = p->dt * norm_factor(p, s);
-    hipEvent_t ev0, ev1;
-    ABC_HIP(hipEventCreate(&ev0));
-    ABC_HIP(hipEventCreate(&ev1));
-    TuneEntry best{0, 0, 0, 0, 1e30, 1e30};
-    constexpr int kReps = 5;
-    for (int kind = 0; kind < 2; ++kind) {
-        for (const abc::Tile& t : kTuneCands) {
-            if (!abc::tile_ok(C, p->R, t, kind + 1)) continue;
-            auto launch = [&]() -> hipError_t {
-                return kind == 0 ? abc::launch_forward_step(c0, out, eps, 0, H, W, C, p->R, dts, t, st)
-                                 : abc::launch_adjoint_step(c0, c0, pout, eps, 0, H, W, C, p->R, dts, t, part, st);
-            };
-            hipError_t e = launch();  // warm-up (also sets the LDS attribute)
-            if (e != hipSuccess) continue;
-            float ms_best = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                ABC_HIP(hipEventRecord(ev0, st));
-                for (int i = 0; i < kReps; ++i) ABC_HIP(launch());
-                ABC_HIP(hipEventRecord(ev1, st));
-                ABC_HIP(hipEventSynchronize(ev1));
-                float ms = 0.0f;
-                ABC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-                ms_best = std::min(ms_best, ms);
-            }
-            const double us = 1e3 * (double)ms_best / kReps;
-            if (kind == 0 && us < best.fus) {
-                best.fus = us;
-                best.ftx = t.tx;
-                best.fty = t.ty;
-            }
-            if (kind == 1 && us < best.aus) {
-                best.aus = us;
-                best.atx = t.tx;
-                best.aty = t.ty;
-            }
-        }
-    }
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    if (best.ftx == 0 || best.atx == 0) return fail(ABC_EINVAL, "no admissible tile for this channel count and radius");
+    TuneEntry best;
+    if ((rc = tune_tiles(c0, H, W, C, p, ws, (hipStream_t)stream, &best))) return rc;
     p->tile_x = best.ftx;
     p->tile_y = best.fty;
     p->adj_tile_x = best.atx;

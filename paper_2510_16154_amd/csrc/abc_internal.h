@@ -115,11 +115,15 @@ constexpr int kPdQuantities = 7;
 hipError_t launch_pd_step(const float* c, const float* c0, float* v, float* mu, int update_mu, int H,
                           int W, int C, float rho, float gamma, float* part, hipStream_t s);
 
-// Multi-image launches (jobs in device memory, sorted by start).
+// Multi-image launches (jobs in device memory, sorted by start).  queue == NULL:
+// one workgroup per tile.  Otherwise the persistent form: persistent_grid()
+// workgroups take the tiles from 8 counters per step, queue[8 k .. 8 k + 7],
+// which must hold 0 when step k starts.  Both forms give the same bits.
+int persistent_grid(int C, int R, Tile t, int fields, int total);
 hipError_t launch_forward_step_batched(const StepJob* jobs, int njobs, int total_tiles, int k, int C, int R, Tile t,
-                                       hipStream_t s);
+                                       int* queue, hipStream_t s);
 hipError_t launch_adjoint_step_batched(const StepJob* jobs, int njobs, int total_tiles, int k, int K, int C, int R,
-                                       Tile t, hipStream_t s);
+                                       Tile t, int* queue, hipStream_t s);
 hipError_t launch_terminal_batched(const PixJob* jobs, int njobs, int total_blocks, int C, float rho, float alpha,
                                    hipStream_t s);
 hipError_t launch_pd_step_batched(const PixJob* jobs, int njobs, int total_blocks, int update_mu, int C, float rho,

@@ -311,7 +311,7 @@ template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxThreads)
 fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps,
                 int k, int H, int W, int C, int Rrt, int tiles_x, float dts, float dx2, float dy2) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int R = RT > 0 ? RT : Rrt;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     fwd_tile<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, R, tile, tiles_x, dts, dx2, dy2,
@@ -332,19 +332,53 @@ __device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs, i
     return lo;
 }
 
-// Forward step k of several images in one launch: the grid covers the tiles of
-// every job, jobs[j].start being the first global tile of job j.
+// Runs body(g) for the global tiles g of a multi-image launch.  Without a
+// queue the grid has one workgroup per tile, handed to the XCDs in contiguous
+// runs.  With a queue (the persistent form: fewer workgroups than tiles) the
+// tiles are split into the same 8 contiguous runs, and each workgroup takes the
+// next tile of run blockIdx.x % 8 from the counter queue[8 k + run] (an atomic
+// add) until the run is used up; no workgroup waits for another, and every one
+// stops once its counter passes the run's end.  A tile's results do not depend
+// on which workgroup computes it.
+template <class Body>
+__device__ __forceinline__ void for_batched_tiles(int* __restrict__ queue, int k, int total, Body&& body) {
+    if (!queue) {
+        body(xcd_tile(blockIdx.x, gridDim.x));
+        return;
+    }
+    // 16 bytes, so that the dynamic LDS placed after the static variables stays
+    // aligned for the 16-byte slot reads
+    __shared__ __align__(16) int next[4];
+    const int x = blockIdx.x % 8;
+    const int per = total / 8, rem = total % 8;
+    const int lo = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    const int n = per + (x < rem ? 1 : 0);
+    const bool first = threadIdx.x == 0 && threadIdx.y == 0;
+    for (;;) {
+        if (first) next[0] = atomicAdd(queue + 8 * k + x, 1);
+        __syncthreads();
+        const int i = next[0];
+        if (i >= n) break;
+        body(lo + i);
+        __syncthreads();  // every thread is done with the tile (and with `next`)
+    }
+}
+
+// Forward step k of several images in one launch: the tiles of every job,
+// jobs[j].start being the first global tile of job j.
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxThreads)
-fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C, int Rrt) {
-    extern __shared__ float lds[];
+fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C, int Rrt, int total,
+                        int* __restrict__ queue) {
+    extern __shared__ __align__(16) float lds[];
     const int R = RT > 0 ? RT : Rrt;
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
-    const StepJob& J = jobs[find_job(jobs, njobs, g)];
-    const size_t f = (size_t)J.H * J.W * C;
-    const float* e = J.eps + 2 * k;
-    fwd_tile<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H, J.W, C, R,
-                     g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
+    for_batched_tiles(queue, k, total, [&](int g) {
+        const StepJob& J = jobs[find_job(jobs, njobs, g)];
+        const size_t f = (size_t)J.H * J.W * C;
+        const float* e = J.eps + 2 * k;
+        fwd_tile<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H, J.W, C,
+                         R, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
+    });
 }
 
 // ----------------------------------------------------------------------------
@@ -490,7 +524,7 @@ __global__ void __launch_bounds__(kMaxThreads)
 adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
                 const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, float dts,
                 float dx2, float dy2, double* __restrict__ part) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
     const int R = RT > 0 ? RT : Rrt;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -503,17 +537,19 @@ adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, floa
 // part receives K x tiles x 2 partials per job.
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxThreads)
-adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C, int Rrt) {
-    extern __shared__ float lds[];
+adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C, int Rrt, int total,
+                        int* __restrict__ queue) {
+    extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
     const int R = RT > 0 ? RT : Rrt;
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
-    const StepJob& J = jobs[find_job(jobs, njobs, g)];
-    const size_t f = (size_t)J.H * J.W * C;
-    const bool even = ((K - 1 - k) & 1) == 0;
-    const float* e = J.eps + 2 * k;
-    adj_tile<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W, C, R,
-                     g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds, red);
+    for_batched_tiles(queue, k, total, [&](int g) {
+        const StepJob& J = jobs[find_job(jobs, njobs, g)];
+        const size_t f = (size_t)J.H * J.W * C;
+        const bool even = ((K - 1 - k) & 1) == 0;
+        const float* e = J.eps + 2 * k;
+        adj_tile<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W, C, R,
+                         g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds, red);
+    });
 }
 
 // ----------------------------------------------------------------------------
@@ -793,7 +829,7 @@ template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxWideThreads)
 fwd_step_wide_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps, int k,
                      int H, int W, int C, int tiles_x, float dts, float dx2, float dy2) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     fwd_tile_wide<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, tile, tiles_x, dts, dx2, dy2,
                           lds);
@@ -801,14 +837,16 @@ fwd_step_wide_kernel(const float* __restrict__ cin, float* __restrict__ cout, co
 
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxWideThreads)
-fwd_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C) {
-    extern __shared__ float lds[];
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
-    const StepJob& J = jobs[find_job(jobs, njobs, g)];
-    const size_t f = (size_t)J.H * J.W * C;
-    const float* e = J.eps + 2 * k;
-    fwd_tile_wide<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H, J.W,
-                          C, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
+fwd_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C, int total,
+                             int* __restrict__ queue) {
+    extern __shared__ __align__(16) float lds[];
+    for_batched_tiles(queue, k, total, [&](int g) {
+        const StepJob& J = jobs[find_job(jobs, njobs, g)];
+        const size_t f = (size_t)J.H * J.W * C;
+        const float* e = J.eps + 2 * k;
+        fwd_tile_wide<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H,
+                              J.W, C, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
+    });
 }
 
 template <int CP, int RT>
@@ -816,7 +854,7 @@ __global__ void __launch_bounds__(kMaxWideThreads)
 adj_step_wide_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
                      const float* __restrict__ eps, int k, int H, int W, int C, int tiles_x, float dts, float dx2,
                      float dy2, double* __restrict__ part) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     adj_tile_wide<CP, RT>(c, pin, pout, eps[2 * k], eps[2 * k + 1], H, W, C, tile, tiles_x, dts, dx2, dy2, part, lds,
@@ -825,16 +863,19 @@ adj_step_wide_kernel(const float* __restrict__ c, const float* __restrict__ pin,
 
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxWideThreads)
-adj_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C) {
-    extern __shared__ float lds[];
+adj_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C, int total,
+                             int* __restrict__ queue) {
+    extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
-    const StepJob& J = jobs[find_job(jobs, njobs, g)];
-    const size_t f = (size_t)J.H * J.W * C;
-    const bool even = ((K - 1 - k) & 1) == 0;
-    const float* e = J.eps + 2 * k;
-    adj_tile_wide<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W, C,
-                          g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds, red);
+    for_batched_tiles(queue, k, total, [&](int g) {
+        const StepJob& J = jobs[find_job(jobs, njobs, g)];
+        const size_t f = (size_t)J.H * J.W * C;
+        const bool even = ((K - 1 - k) & 1) == 0;
+        const float* e = J.eps + 2 * k;
+        adj_tile_wide<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W,
+                              C, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds,
+                              red);
+    });
 }
 
 // ----------------------------------------------------------------------------
@@ -1296,7 +1337,8 @@ hipError_t adj_wide_launch(const float* c, const float* pin, float* pout, const 
 }
 
 template <int CP, int RT>
-hipError_t fwdb_wide_launch(const StepJob* jobs, int njobs, int total, int k, int C, Tile t, hipStream_t s) {
+hipError_t fwdb_wide_launch(const StepJob* jobs, int njobs, int total, int k, int C, Tile t, int* queue,
+                            hipStream_t s) {
     constexpr int G = Wide<CP>::G;
     const size_t lds = tile_lds_bytes(C, RT, t, 1);
     auto fn = fwd_step_batched_wide_kernel<CP, RT>;
@@ -1304,12 +1346,13 @@ hipError_t fwdb_wide_launch(const StepJob* jobs, int njobs, int total, int k, in
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx * G, t.ty), lds, s, jobs, njobs, k, C);
+    const int grid = queue ? persistent_grid(C, RT, t, 1, total) : total;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(t.tx * G, t.ty), lds, s, jobs, njobs, k, C, total, queue);
     return hipGetLastError();
 }
 
 template <int CP, int RT>
-hipError_t adjb_wide_launch(const StepJob* jobs, int njobs, int total, int k, int K, int C, Tile t,
+hipError_t adjb_wide_launch(const StepJob* jobs, int njobs, int total, int k, int K, int C, Tile t, int* queue,
                             hipStream_t s) {
     constexpr int G = Wide<CP>::G;
     const size_t lds = tile_lds_bytes(C, RT, t, 2);
@@ -1318,7 +1361,8 @@ hipError_t adjb_wide_launch(const StepJob* jobs, int njobs, int total, int k, in
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx * G, t.ty), lds, s, jobs, njobs, k, K, C);
+    const int grid = queue ? persistent_grid(C, RT, t, 2, total) : total;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(t.tx * G, t.ty), lds, s, jobs, njobs, k, K, C, total, queue);
     return hipGetLastError();
 }
 
@@ -1371,19 +1415,22 @@ hipError_t adj_launch_r(const float* c, const float* pin, float* pout, const flo
 }
 
 template <int CP, int RT>
-hipError_t fwdb_launch_t(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t, hipStream_t s) {
+hipError_t fwdb_launch_t(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t, int* queue,
+                         hipStream_t s) {
     const size_t lds = tile_lds_bytes(CP, R, t, 1);
     auto fn = fwd_step_batched_kernel<CP, RT>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, jobs, njobs, k, C, R);
+    const int grid = queue ? persistent_grid(C, R, t, 1, total) : total;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, jobs, njobs, k, C, R,
+                       total, queue);
     return hipGetLastError();
 }
 
 template <int CP, int RT>
-hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t,
+hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t, int* queue,
                          hipStream_t s) {
     const size_t lds = tile_lds_bytes(CP, R, t, 2);
     auto fn = adj_step_batched_kernel<CP, RT>;
@@ -1391,54 +1438,56 @@ hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(total), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, jobs, njobs, k, K, C,
-                       R);
+    const int grid = queue ? persistent_grid(C, R, t, 2, total) : total;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, jobs, njobs, k, K, C,
+                       R, total, queue);
     return hipGetLastError();
 }
 
 template <int CP>
-hipError_t fwdb_launch_r(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t, hipStream_t s) {
+hipError_t fwdb_launch_r(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t, int* queue,
+                         hipStream_t s) {
     if constexpr (CP <= 4) {
         switch (R) {
-            case 1: return fwdb_launch_t<CP, 1>(jobs, njobs, total, k, C, R, t, s);
-            case 2: return fwdb_launch_t<CP, 2>(jobs, njobs, total, k, C, R, t, s);
-            case 3: return fwdb_launch_t<CP, 3>(jobs, njobs, total, k, C, R, t, s);
-            case 4: return fwdb_launch_t<CP, 4>(jobs, njobs, total, k, C, R, t, s);
-            case 5: return fwdb_launch_t<CP, 5>(jobs, njobs, total, k, C, R, t, s);
+            case 1: return fwdb_launch_t<CP, 1>(jobs, njobs, total, k, C, R, t, queue, s);
+            case 2: return fwdb_launch_t<CP, 2>(jobs, njobs, total, k, C, R, t, queue, s);
+            case 3: return fwdb_launch_t<CP, 3>(jobs, njobs, total, k, C, R, t, queue, s);
+            case 4: return fwdb_launch_t<CP, 4>(jobs, njobs, total, k, C, R, t, queue, s);
+            case 5: return fwdb_launch_t<CP, 5>(jobs, njobs, total, k, C, R, t, queue, s);
             default: break;
         }
     } else if constexpr (CP >= 16) {
         switch (R) {
-            case 1: return fwdb_wide_launch<CP, 1>(jobs, njobs, total, k, C, t, s);
-            case 2: return fwdb_wide_launch<CP, 2>(jobs, njobs, total, k, C, t, s);
-            case 3: return fwdb_wide_launch<CP, 3>(jobs, njobs, total, k, C, t, s);
+            case 1: return fwdb_wide_launch<CP, 1>(jobs, njobs, total, k, C, t, queue, s);
+            case 2: return fwdb_wide_launch<CP, 2>(jobs, njobs, total, k, C, t, queue, s);
+            case 3: return fwdb_wide_launch<CP, 3>(jobs, njobs, total, k, C, t, queue, s);
             default: break;
         }
     }
-    return fwdb_launch_t<CP, 0>(jobs, njobs, total, k, C, R, t, s);
+    return fwdb_launch_t<CP, 0>(jobs, njobs, total, k, C, R, t, queue, s);
 }
 
 template <int CP>
 hipError_t adjb_launch_r(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t,
-                         hipStream_t s) {
+                         int* queue, hipStream_t s) {
     if constexpr (CP <= 4) {
         switch (R) {
-            case 1: return adjb_launch_t<CP, 1>(jobs, njobs, total, k, K, C, R, t, s);
-            case 2: return adjb_launch_t<CP, 2>(jobs, njobs, total, k, K, C, R, t, s);
-            case 3: return adjb_launch_t<CP, 3>(jobs, njobs, total, k, K, C, R, t, s);
-            case 4: return adjb_launch_t<CP, 4>(jobs, njobs, total, k, K, C, R, t, s);
-            case 5: return adjb_launch_t<CP, 5>(jobs, njobs, total, k, K, C, R, t, s);
+            case 1: return adjb_launch_t<CP, 1>(jobs, njobs, total, k, K, C, R, t, queue, s);
+            case 2: return adjb_launch_t<CP, 2>(jobs, njobs, total, k, K, C, R, t, queue, s);
+            case 3: return adjb_launch_t<CP, 3>(jobs, njobs, total, k, K, C, R, t, queue, s);
+            case 4: return adjb_launch_t<CP, 4>(jobs, njobs, total, k, K, C, R, t, queue, s);
+            case 5: return adjb_launch_t<CP, 5>(jobs, njobs, total, k, K, C, R, t, queue, s);
             default: break;
         }
     } else if constexpr (CP >= 16) {
         switch (R) {
-            case 1: return adjb_wide_launch<CP, 1>(jobs, njobs, total, k, K, C, t, s);
-            case 2: return adjb_wide_launch<CP, 2>(jobs, njobs, total, k, K, C, t, s);
-            case 3: return adjb_wide_launch<CP, 3>(jobs, njobs, total, k, K, C, t, s);
+            case 1: return adjb_wide_launch<CP, 1>(jobs, njobs, total, k, K, C, t, queue, s);
+            case 2: return adjb_wide_launch<CP, 2>(jobs, njobs, total, k, K, C, t, queue, s);
+            case 3: return adjb_wide_launch<CP, 3>(jobs, njobs, total, k, K, C, t, queue, s);
             default: break;
         }
     }
-    return adjb_launch_t<CP, 0>(jobs, njobs, total, k, K, C, R, t, s);
+    return adjb_launch_t<CP, 0>(jobs, njobs, total, k, K, C, R, t, queue, s);
 }
 
 }  // namespace
@@ -1484,6 +1533,24 @@ static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
     const size_t lds = tile_lds_bytes(C, R, t, fields);
     const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
     return std::min(by_lds, 32 / wpb) * wpb;
+}
+
+// Workgroups of a persistent multi-image launch: as many as the GPU holds at
+// once for this tile (LDS and waves per SIMD), a multiple of 8, at most one per
+// tile.
+int persistent_grid(int C, int R, Tile t, int fields, int total) {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cus[dev] = n;
+    }
+    const int wpb = (t.tx * (t.ty / rows_per_thread(C, R)) * wide_lanes(C, R) + kWave - 1) / kWave;
+    const int per_cu = std::max(1, tile_waves_per_cu(C, R, t, fields) / wpb);
+    const int cap = (cus[dev] * per_cu + 7) / 8 * 8;
+    return std::min(total, cap);
 }
 
 // First candidate whose LDS fits in 64 KB (several workgroups per CU).  When
@@ -1559,33 +1626,33 @@ hipError_t launch_reduce_rows_f64(const double* part, int nrows, int nblk, int n
 }
 
 hipError_t launch_forward_step_batched(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t,
-                                       hipStream_t s) {
+                                       int* queue, hipStream_t s) {
     switch (padded_channels(C)) {
-        case 1: return fwdb_launch_r<1>(jobs, njobs, total, k, C, R, t, s);
-        case 2: return fwdb_launch_r<2>(jobs, njobs, total, k, C, R, t, s);
-        case 3: return fwdb_launch_r<3>(jobs, njobs, total, k, C, R, t, s);
-        case 4: return fwdb_launch_r<4>(jobs, njobs, total, k, C, R, t, s);
-        case 8: return fwdb_launch_r<8>(jobs, njobs, total, k, C, R, t, s);
-        case 16: return fwdb_launch_r<16>(jobs, njobs, total, k, C, R, t, s);
-        case 31: return fwdb_launch_r<31>(jobs, njobs, total, k, C, R, t, s);
-        case 32: return fwdb_launch_r<32>(jobs, njobs, total, k, C, R, t, s);
-        case 64: return fwdb_launch_r<64>(jobs, njobs, total, k, C, R, t, s);
+        case 1: return fwdb_launch_r<1>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 2: return fwdb_launch_r<2>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 3: return fwdb_launch_r<3>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 4: return fwdb_launch_r<4>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 8: return fwdb_launch_r<8>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 16: return fwdb_launch_r<16>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 31: return fwdb_launch_r<31>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 32: return fwdb_launch_r<32>(jobs, njobs, total, k, C, R, t, queue, s);
+        case 64: return fwdb_launch_r<64>(jobs, njobs, total, k, C, R, t, queue, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_adjoint_step_batched(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t,
-                                       hipStream_t s) {
+                                       int* queue, hipStream_t s) {
     switch (padded_channels(C)) {
-        case 1: return adjb_launch_r<1>(jobs, njobs, total, k, K, C, R, t, s);
-        case 2: return adjb_launch_r<2>(jobs, njobs, total, k, K, C, R, t, s);
-        case 3: return adjb_launch_r<3>(jobs, njobs, total, k, K, C, R, t, s);
-        case 4: return adjb_launch_r<4>(jobs, njobs, total, k, K, C, R, t, s);
-        case 8: return adjb_launch_r<8>(jobs, njobs, total, k, K, C, R, t, s);
-        case 16: return adjb_launch_r<16>(jobs, njobs, total, k, K, C, R, t, s);
-        case 31: return adjb_launch_r<31>(jobs, njobs, total, k, K, C, R, t, s);
-        case 32: return adjb_launch_r<32>(jobs, njobs, total, k, K, C, R, t, s);
-        case 64: return adjb_launch_r<64>(jobs, njobs, total, k, K, C, R, t, s);
+        case 1: return adjb_launch_r<1>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 2: return adjb_launch_r<2>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 3: return adjb_launch_r<3>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 4: return adjb_launch_r<4>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 8: return adjb_launch_r<8>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 16: return adjb_launch_r<16>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 31: return adjb_launch_r<31>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 32: return adjb_launch_r<32>(jobs, njobs, total, k, K, C, R, t, queue, s);
+        case 64: return adjb_launch_r<64>(jobs, njobs, total, k, K, C, R, t, queue, s);
         default: return hipErrorInvalidValue;
     }
 }

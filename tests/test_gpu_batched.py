@@ -124,3 +124,41 @@ def test_batched_images_match_the_oracle_under_control_replay(orc, C, cost):
         assert g_err.size > 0 and g_err.max() < 1e-4, i
         assert np.all(steps[:, 0] <= 1e-12 * 1100.0), i
         assert np.all(steps[:, 1] <= steps[:, 2] * (1 + 1e-9) + 1e-9), i
+
+
+@pytest.mark.parametrize("C,R,spectra", [(3, 5, False), (31, 2, True), (3, 7, False)])
+def test_persistent_sweeps_equal_one_workgroup_per_tile(C, R, spectra):
+    """ABC_FLAG_PERSISTENT: each Euler step as a grid of as many workgroups as the
+    GPU holds, taking the tiles of all images from per-step counters, gives the
+    same bits as one workgroup per tile (one-lane, lanes-per-pixel and
+    runtime-radius kernels)."""
+    print(f"[case] persistent batched C={C} R={R}", flush=True)
+    shapes = [(96, 130), (33, 57), (150, 41), (64, 64)] if C == 3 else [(40, 57), (33, 70)]
+    imgs = [T(voronoi_image(h, w, C, 4, 0.05 if C == 3 else 0.01, 600 + i, spectra=spectra))
+            for i, (h, w) in enumerate(shapes)]
+    gp = A.Params(K=6, R=R, alpha=20.0, max_outer=2, max_inner=3)
+    a, sa, _ = A.abc_solve_batched(imgs, gp)
+    b, sb, _ = A.abc_solve_batched(imgs, gp.replace(flags=A.ABC_FLAG_PERSISTENT))
+    torch.cuda.synchronize()
+    for i in range(len(imgs)):
+        assert torch.equal(a[i], b[i]), i
+        for key in ("K", "L", "inner_iters", "ls_evals", "outer_iters"):
+            assert sa[i][key] == sb[i][key], (i, key)
+
+
+def test_autotuned_batch_equals_a_solve_with_the_tuned_tiles():
+    """ABC_FLAG_AUTOTUNE: the batched solve times the tile candidates on its largest
+    image and uses the fastest; its results equal the default tiles' bit for bit
+    (each pixel sums its window in a fixed order, so only the time depends on
+    the tile), and the workspace query leaves room for any candidate."""
+    shapes = [(96, 130), (33, 57), (150, 41)]
+    imgs = [T(voronoi_image(h, w, 3, 4, 0.05, 650 + i)) for i, (h, w) in enumerate(shapes)]
+    gp = A.Params(K=5, R=5, alpha=20.0, max_outer=1, max_inner=2)
+    tuned_p = gp.replace(flags=A.ABC_FLAG_AUTOTUNE)
+    assert A.abc_workspace_bytes_batched(shapes, 3, tuned_p) >= A.abc_workspace_bytes_batched(shapes, 3, gp)
+    a, _, _ = A.abc_solve_batched(imgs, tuned_p)
+    again, _, _ = A.abc_solve_batched(imgs, tuned_p)  # the tuned tiles come from the process cache now
+    b, _, _ = A.abc_solve_batched(imgs, gp)
+    torch.cuda.synchronize()
+    for i in range(len(imgs)):
+        assert torch.equal(a[i], b[i]) and torch.equal(again[i], b[i]), i
