@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "abc_internal.h"
@@ -90,6 +91,24 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     const int per = nb / 8, rem = nb % 8;
     const int x = bid % 8, idx = bid / 8;
     return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+// The interaction tile of a workgroup in a one-image launch, whose grid is
+// (64 bh, strips) with bh = ceil(tiles_y / 8): the 8 XCDs take the workgroups
+// round-robin in linear order, so XCD x = blockIdx.x % 8 gets band x of bh tile
+// rows, and within its band visits column strips kStrip tiles wide
+// (blockIdx.y), each row by row from the top ((blockIdx.x / 8) % kStrip is the
+// column in the strip, blockIdx.x / 64 the row in the band).  The tile below a
+// tile then comes kStrip tiles later and finds the halo rows they share in the
+// XCD's L2; in row-major order it came a whole tile row later, too late on wide
+// images.  Shifts and masks only: integer division costs tens of instructions
+// per wave.  Returns false for workgroups past the last tile row or column.
+constexpr int kStrip = 8;
+__device__ __forceinline__ bool strip_tile(int tiles_x, int tiles_y, int& tcol, int& trow) {
+    const int bh = (tiles_y + 7) >> 3;
+    tcol = blockIdx.y * kStrip + ((blockIdx.x >> 3) & (kStrip - 1));
+    trow = (blockIdx.x & 7) * bh + (blockIdx.x >> 6);
+    return tcol < tiles_x && trow < tiles_y;
 }
 
 // LDS slot of one pixel: CP channels, then the inside mask, in whole 16-byte
@@ -271,12 +290,12 @@ __device__ __forceinline__ void fwd_window(const float* me, int LW, int R, const
 // (the workgroup is TX x TY/NP threads for a TX x TY tile).
 template <int CP, int RT>
 __device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* __restrict__ cout, float exh,
-                                         float ech, int H, int W, int C, int R, int tile, int tiles_x, float dts,
+                                         float ech, int H, int W, int C, int R, int tcol, int trow, float dts,
                                          float dx2, float dy2, float* lds) {
     constexpr int CS = Slot<CP>::CS;
     constexpr int NP = RowsPerThread<CP>::value;
     const int TX = blockDim.x, TY = NP * blockDim.y;
-    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int x0 = tcol * TX, y0 = trow * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
     float* omt = lds + LW * LH * CS;
@@ -310,11 +329,12 @@ __device__ __forceinline__ void fwd_tile(const float* __restrict__ cin, float* _
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxThreads)
 fwd_step_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps,
-                int k, int H, int W, int C, int Rrt, int tiles_x, float dts, float dx2, float dy2) {
+                int k, int H, int W, int C, int Rrt, int tiles_x, int tiles_y, float dts, float dx2, float dy2) {
     extern __shared__ __align__(16) float lds[];
     const int R = RT > 0 ? RT : Rrt;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    fwd_tile<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, R, tile, tiles_x, dts, dx2, dy2,
+    int tcol, trow;
+    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
+    fwd_tile<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, R, tcol, trow, dts, dx2, dy2,
                      lds);
 }
 
@@ -376,8 +396,9 @@ fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
         const StepJob& J = jobs[find_job(jobs, njobs, g)];
         const size_t f = (size_t)J.H * J.W * C;
         const float* e = J.eps + 2 * k;
+        const int tile = g - J.start, trow = tile / J.tiles_x;
         fwd_tile<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H, J.W, C,
-                         R, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
+                         R, tile - trow * J.tiles_x, trow, J.dts, J.dx2, J.dy2, lds);
     });
 }
 
@@ -458,17 +479,17 @@ __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int
 }
 
 // One interaction tile of a transposed step (NP pixels per thread, as in the
-// forward step); part[2*tile + {0,1}] receives the workgroup's FP64 sums of
-// the two control-gradient integrands.
+// forward step); part[2*tile + {0,1}], tile = trow * tiles_x + tcol (row-major),
+// receives the workgroup's FP64 sums of the two control-gradient integrands.
 template <int CP, int RT>
 __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const float* __restrict__ pin,
                                          float* __restrict__ pout, float ex, float ec, int H, int W, int C, int R,
-                                         int tile, int tiles_x, float dts, float dx2, float dy2,
+                                         int tcol, int trow, int tiles_x, float dts, float dx2, float dy2,
                                          double* __restrict__ part, float* lds, double* red) {
     constexpr int CS = Slot<CP>::CS;
     constexpr int NP = RowsPerThread<CP>::value;
     const int TX = blockDim.x, TY = NP * blockDim.y;
-    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int x0 = tcol * TX, y0 = trow * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
     float* ldc = lds;
@@ -514,6 +535,7 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
     const double bx = block_sum_f64(tsx, red);
     const double bc = block_sum_f64(tsc, red);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const int tile = trow * tiles_x + tcol;
         part[2 * tile + 0] = bx;
         part[2 * tile + 1] = bc;
     }
@@ -522,14 +544,15 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxThreads)
 adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
-                const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, float dts,
-                float dx2, float dy2, double* __restrict__ part) {
+                const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, int tiles_y,
+                float dts, float dx2, float dy2, double* __restrict__ part) {
     extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
     const int R = RT > 0 ? RT : Rrt;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    adj_tile<CP, RT>(c, pin, pout, eps[2 * k], eps[2 * k + 1], H, W, C, R, tile, tiles_x, dts, dx2, dy2, part, lds,
-                     red);
+    int tcol, trow;
+    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
+    adj_tile<CP, RT>(c, pin, pout, eps[2 * k], eps[2 * k + 1], H, W, C, R, tcol, trow, tiles_x, dts, dx2, dy2, part,
+                     lds, red);
 }
 
 // Transposed step k of several images in one launch.  p^{k+1} is read from
@@ -547,8 +570,10 @@ adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
         const size_t f = (size_t)J.H * J.W * C;
         const bool even = ((K - 1 - k) & 1) == 0;
         const float* e = J.eps + 2 * k;
+        const int tile = g - J.start, trow = tile / J.tiles_x;
         adj_tile<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W, C, R,
-                         g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds, red);
+                         tile - trow * J.tiles_x, trow, J.tiles_x, J.dts, J.dx2, J.dy2,
+                         J.part + (size_t)k * J.tiles * 2, lds, red);
     });
 }
 
@@ -693,11 +718,11 @@ __device__ __forceinline__ void fwd_window_wide(const float* me, int LW, const f
 
 template <int CP, int RT>
 __device__ __forceinline__ void fwd_tile_wide(const float* __restrict__ cin, float* __restrict__ cout, float exh,
-                                              float ech, int H, int W, int C, int tile, int tiles_x, float dts,
+                                              float ech, int H, int W, int C, int tcol, int trow, float dts,
                                               float dx2, float dy2, float* lds) {
     constexpr int G = Wide<CP>::G;
     const int TX = blockDim.x / G, TY = blockDim.y;
-    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int x0 = tcol * TX, y0 = trow * TY;
     const int LW = TX + 2 * RT, LH = TY + 2 * RT;
     const int pf = wide_plane_floats(LW, LH);
     const bool interior = x0 >= RT && y0 >= RT && x0 + TX + RT <= W && y0 + TY + RT <= H;
@@ -777,11 +802,11 @@ __device__ __forceinline__ void adj_window_wide(const float* mc, const float* mp
 template <int CP, int RT>
 __device__ __forceinline__ void adj_tile_wide(const float* __restrict__ c, const float* __restrict__ pin,
                                               float* __restrict__ pout, float ex, float ec, int H, int W, int C,
-                                              int tile, int tiles_x, float dts, float dx2, float dy2,
+                                              int tcol, int trow, int tiles_x, float dts, float dx2, float dy2,
                                               double* __restrict__ part, float* lds, double* red) {
     constexpr int G = Wide<CP>::G;
     const int TX = blockDim.x / G, TY = blockDim.y;
-    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int x0 = tcol * TX, y0 = trow * TY;
     const int LW = TX + 2 * RT, LH = TY + 2 * RT;
     const int pf = wide_plane_floats(LW, LH);
     const bool interior = x0 >= RT && y0 >= RT && x0 + TX + RT <= W && y0 + TY + RT <= H;
@@ -820,6 +845,7 @@ __device__ __forceinline__ void adj_tile_wide(const float* __restrict__ c, const
     const double bx = block_sum_f64((double)sx, red);
     const double bc = block_sum_f64((double)sc, red);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const int tile = trow * tiles_x + tcol;
         part[2 * tile + 0] = bx;
         part[2 * tile + 1] = bc;
     }
@@ -828,10 +854,11 @@ __device__ __forceinline__ void adj_tile_wide(const float* __restrict__ c, const
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxWideThreads)
 fwd_step_wide_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps, int k,
-                     int H, int W, int C, int tiles_x, float dts, float dx2, float dy2) {
+                     int H, int W, int C, int tiles_x, int tiles_y, float dts, float dx2, float dy2) {
     extern __shared__ __align__(16) float lds[];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    fwd_tile_wide<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, tile, tiles_x, dts, dx2, dy2,
+    int tcol, trow;
+    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
+    fwd_tile_wide<CP, RT>(cin, cout, 0.5f * eps[2 * k], 0.5f * eps[2 * k + 1], H, W, C, tcol, trow, dts, dx2, dy2,
                           lds);
 }
 
@@ -844,21 +871,23 @@ fwd_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k,
         const StepJob& J = jobs[find_job(jobs, njobs, g)];
         const size_t f = (size_t)J.H * J.W * C;
         const float* e = J.eps + 2 * k;
+        const int tile = g - J.start, trow = tile / J.tiles_x;
         fwd_tile_wide<CP, RT>(J.traj + (size_t)k * f, J.traj + (size_t)(k + 1) * f, 0.5f * e[0], 0.5f * e[1], J.H,
-                              J.W, C, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, lds);
+                              J.W, C, tile - trow * J.tiles_x, trow, J.dts, J.dx2, J.dy2, lds);
     });
 }
 
 template <int CP, int RT>
 __global__ void __launch_bounds__(kMaxWideThreads)
 adj_step_wide_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
-                     const float* __restrict__ eps, int k, int H, int W, int C, int tiles_x, float dts, float dx2,
-                     float dy2, double* __restrict__ part) {
+                     const float* __restrict__ eps, int k, int H, int W, int C, int tiles_x, int tiles_y, float dts,
+                     float dx2, float dy2, double* __restrict__ part) {
     extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    adj_tile_wide<CP, RT>(c, pin, pout, eps[2 * k], eps[2 * k + 1], H, W, C, tile, tiles_x, dts, dx2, dy2, part, lds,
-                          red);
+    int tcol, trow;
+    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
+    adj_tile_wide<CP, RT>(c, pin, pout, eps[2 * k], eps[2 * k + 1], H, W, C, tcol, trow, tiles_x, dts, dx2, dy2,
+                          part, lds, red);
 }
 
 template <int CP, int RT>
@@ -872,9 +901,10 @@ adj_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k,
         const size_t f = (size_t)J.H * J.W * C;
         const bool even = ((K - 1 - k) & 1) == 0;
         const float* e = J.eps + 2 * k;
+        const int tile = g - J.start, trow = tile / J.tiles_x;
         adj_tile_wide<CP, RT>(J.traj + (size_t)k * f, even ? J.pa : J.pb, even ? J.pb : J.pa, e[0], e[1], J.H, J.W,
-                              C, g - J.start, J.tiles_x, J.dts, J.dx2, J.dy2, J.part + (size_t)k * J.tiles * 2, lds,
-                              red);
+                              C, tile - trow * J.tiles_x, trow, J.tiles_x, J.dts, J.dx2, J.dy2,
+                              J.part + (size_t)k * J.tiles * 2, lds, red);
     });
 }
 
@@ -1266,11 +1296,20 @@ hipError_t by_channels(int C, Fn&& fn) {
     }
 }
 
+// Grid of a one-image interaction launch, in the layout strip_tile decodes.
+bool strip_grid(int tiles_x, int tiles_y, dim3& grid) {
+    const long bh = (tiles_y + 7) / 8, strips = (tiles_x + kStrip - 1) / kStrip;
+    if (64 * bh > INT_MAX || strips > 65535) return false;
+    grid = dim3((unsigned)(64 * bh), (unsigned)strips);
+    return true;
+}
+
 template <int CP, int RT>
 hipError_t fwd_launch_t(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
                         float dts, Tile t, hipStream_t s) {
-    const int tiles_x = (W + t.tx - 1) / t.tx;
-    const int nb = tile_count(H, W, t);
+    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
+    dim3 grid;
+    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(CP, R, t, 1);
     auto fn = fwd_step_kernel<CP, RT>;
     if (lds > 64 * 1024) {
@@ -1278,16 +1317,17 @@ hipError_t fwd_launch_t(const float* cin, float* cout, const float* eps, int k, 
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, cin, cout, eps, k, H, W,
-                       C, R, tiles_x, dts, dx2, dy2);
+    hipLaunchKernelGGL(fn, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, cin, cout, eps, k, H, W, C,
+                       R, tiles_x, tiles_y, dts, dx2, dy2);
     return hipGetLastError();
 }
 
 template <int CP, int RT>
 hipError_t adj_launch_t(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
                         int C, int R, float dts, Tile t, double* part, hipStream_t s) {
-    const int tiles_x = (W + t.tx - 1) / t.tx;
-    const int nb = tile_count(H, W, t);
+    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
+    dim3 grid;
+    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(CP, R, t, 2);
     auto fn = adj_step_kernel<CP, RT>;
     if (lds > 64 * 1024) {
@@ -1295,8 +1335,8 @@ hipError_t adj_launch_t(const float* c, const float* pin, float* pout, const flo
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, c, pin, pout, eps, k, H,
-                       W, C, R, tiles_x, dts, dx2, dy2, part);
+    hipLaunchKernelGGL(fn, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, c, pin, pout, eps, k, H, W,
+                       C, R, tiles_x, tiles_y, dts, dx2, dy2, part);
     return hipGetLastError();
 }
 
@@ -1304,8 +1344,9 @@ template <int CP, int RT>
 hipError_t fwd_wide_launch(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, float dts,
                            Tile t, hipStream_t s) {
     constexpr int G = Wide<CP>::G;
-    const int tiles_x = (W + t.tx - 1) / t.tx;
-    const int nb = tile_count(H, W, t);
+    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
+    dim3 grid;
+    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(C, RT, t, 1);
     auto fn = fwd_step_wide_kernel<CP, RT>;
     if (lds > 64 * 1024) {
@@ -1313,8 +1354,8 @@ hipError_t fwd_wide_launch(const float* cin, float* cout, const float* eps, int 
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx * G, t.ty), lds, s, cin, cout, eps, k, H, W, C, tiles_x, dts, dx2,
-                       dy2);
+    hipLaunchKernelGGL(fn, grid, dim3(t.tx * G, t.ty), lds, s, cin, cout, eps, k, H, W, C, tiles_x, tiles_y, dts,
+                       dx2, dy2);
     return hipGetLastError();
 }
 
@@ -1322,8 +1363,9 @@ template <int CP, int RT>
 hipError_t adj_wide_launch(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
                            int C, float dts, Tile t, double* part, hipStream_t s) {
     constexpr int G = Wide<CP>::G;
-    const int tiles_x = (W + t.tx - 1) / t.tx;
-    const int nb = tile_count(H, W, t);
+    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
+    dim3 grid;
+    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(C, RT, t, 2);
     auto fn = adj_step_wide_kernel<CP, RT>;
     if (lds > 64 * 1024) {
@@ -1331,8 +1373,8 @@ hipError_t adj_wide_launch(const float* c, const float* pin, float* pout, const 
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(t.tx * G, t.ty), lds, s, c, pin, pout, eps, k, H, W, C, tiles_x, dts, dx2,
-                       dy2, part);
+    hipLaunchKernelGGL(fn, grid, dim3(t.tx * G, t.ty), lds, s, c, pin, pout, eps, k, H, W, C, tiles_x, tiles_y,
+                       dts, dx2, dy2, part);
     return hipGetLastError();
 }
 
