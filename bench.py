@@ -45,9 +45,9 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "76a0de6c940cddfd0b0d8e78f0305e398bd15bd6e6dd6be3413d7aad2700974b",
-    "adj_step_kernel<3,5>": 11.56e6,
-    "adj_step_wide_kernel<31,2>": 2079.54e6,
+    "kernel_sha256": "cda3415547de939ca32165bc85fc0ebbec670e480c07e4c4581c70f1f8206bb4",
+    "adj_step_kernel<3,5>": 11.53e6,
+    "adj_step_wide_kernel<31,2>": 1607.64e6,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")
 
