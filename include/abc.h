@@ -399,9 +399,12 @@ int abc_segment_workspace_bytes(int H, int W, int C, size_t* bytes);
  *     watershed (theta and labels_out are then unused), or NULL.
  *   labels_out: device H x W int32 watershed labels, or NULL.
  *   stats: host output.
+ * The per-label sums behind IRV and IRC are fixed-point integer sums, so
+ * the scores are the same bits on every run.
  * Returns ABC_OK, ABC_EINVAL (bad argument, small workspace, label out of
- * range) or ABC_EHIP.  Synchronises the stream (several times: the forest is
- * built in rounds whose count is read back). */
+ * range), ABC_ENONFINITE (c or c0 holds a NaN or an infinity; nothing is
+ * labelled) or ABC_EHIP.  Synchronises the stream (several times: the forest
+ * is built in rounds whose count is read back). */
 int abc_segment(const float* c, const float* c0, int H, int W, int C, float theta, const int32_t* labels_in,
                 int32_t* labels_out, abc_seg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 

@@ -27,8 +27,14 @@
 // two, so the labels do not depend on timing.  Marked components never
 // pick, so every unmarked pixel ends in the tree of exactly one marker.
 //
-// Per-label sums for the scores use FP64 atomics (their order, and so the
-// last bits of IRV and IRC, can vary between runs; the labels cannot).
+// Per-label sums for the scores are fixed-point integers: each value, scaled
+// by a power of two S chosen from the largest |value| in the image so that no
+// sum can exceed 2^92, is split as hi * 2^32 + lo (lo an integer in
+// [0, 2^32]), and hi and lo are added into separate 64-bit integers with
+// atomics.  Integer addition is associative, so the sums, and IRV and IRC,
+// are the same bits on every run whatever the order of the adds; the
+// quantum 1/S is about 2^-92 of the largest possible sum, far below FP64
+// rounding of the same sums.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,7 +55,7 @@ constexpr int kRun = 16;  // pixels per thread in the per-label accumulations
 constexpr unsigned long long kNoEdge = ~0ull;
 
 enum Flag { kChanged = 0, kMarkers = 1, kActive = 2, kBadLabel = 3, kMaxLabel = 4, kNonEmpty = 5, kCount = 6,
-            kFlags = 8 };
+            kAbsMax = 7, kFlags = 8 };
 
 int nblocks(size_t n) { return (int)((n + kT - 1) / kT); }
 
@@ -304,102 +310,178 @@ check_labels_kernel(const int* __restrict__ lab, size_t N, int* __restrict__ fla
         atomicMax(&flags[kMaxLabel], l);
 }
 
+template <class T>
 __global__ void __launch_bounds__(kT)
-zero_kernel(double* __restrict__ x, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) x[i] = 0.0;
+zero_kernel(T* __restrict__ x, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) x[i] = T(0);
 }
 
-// Per-label pixel count and channel sums of c0 and c, one run of kRun pixels
-// per thread, flushed with FP64 atomics whenever the label changes.
+// Bit pattern of the largest |value| of c and c0 (as an int: the bits of a
+// non-negative float order like integers, and those of NaN above infinity).
+__global__ void __launch_bounds__(kT)
+absmax_kernel(const float* __restrict__ c, const float* __restrict__ c0, size_t n, int* __restrict__ flags) {
+    int m = 0;
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+        m = max(m, __float_as_int(fabsf(c[i])));
+        m = max(m, __float_as_int(fabsf(c0[i])));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(&flags[kAbsMax], m);
+}
+
+constexpr int kFxBits = 92;  // every sum stays below 2^kFxBits after scaling
+
+// Scale 2^e with bound * 2^e < 2^kFxBits, bound = mult * (largest |value|);
+// 0 when that value is not finite (the call then fails, see abc_segment).
+__device__ __forceinline__ double fx_scale(const int* __restrict__ flags, double mult) {
+    const float a = __int_as_float(flags[kAbsMax]);
+    if (!(a <= 3.402823466e38f)) return 0.0;
+    const double b = mult * (double)a;
+    if (!(b > 0.0)) return 1.0;
+    int e;
+    (void)frexp(b, &e);  // b < 2^e
+    return ldexp(1.0, kFxBits - e);
+}
+
+// Adds the scaled value v = x S as hi * 2^32 + lo: hi = floor(v / 2^32) and
+// lo = v - hi 2^32 rounded to an integer in [0, 2^32].
+__device__ __forceinline__ void fx_add(double v, long long& hi, unsigned long long& lo) {
+    const double h = floor(v * 0x1p-32);
+    hi += (long long)h;
+    lo += (unsigned long long)rint(fma(h, -0x1p32, v));
+}
+
+__device__ __forceinline__ void fx_flush(unsigned long long* __restrict__ dst, long long hi, unsigned long long lo) {
+    atomicAdd(dst, (unsigned long long)hi);  // two's complement: the wrapped sum is the signed one
+    atomicAdd(dst + 1, lo);
+}
+
+// Value of a fixed-point sum, still scaled by S.
+__device__ __forceinline__ double fx_value(const unsigned long long* __restrict__ x) {
+    return fma((double)(long long)x[0], 0x1p32, (double)x[1]);
+}
+
+// Per-label pixel count (FP64 integer sums, exact) and fixed-point channel
+// sums of c0 and c (pairs hi, lo at s0[2 (label C + ch)]), one run of kRun
+// pixels per thread, flushed with atomics whenever the label changes.
 __global__ void __launch_bounds__(kT)
 label_sums_kernel(const float* __restrict__ c, const float* __restrict__ c0, const int* __restrict__ lab, size_t N,
-                  int C, double* __restrict__ cnt, double* __restrict__ s0, double* __restrict__ s1) {
+                  int C, const int* __restrict__ flags, double* __restrict__ cnt, unsigned long long* __restrict__ s0,
+                  unsigned long long* __restrict__ s1) {
     const size_t p0 = ((size_t)blockIdx.x * kT + threadIdx.x) * kRun;
-    if (p0 >= N) return;
-    const size_t p1 = p0 + kRun < N ? p0 + kRun : N;
-    for (int ch = -1; ch < C; ++ch) {
-        int cur = lab[p0];
-        double a = 0.0, b = 0.0;
-        for (size_t i = p0; i < p1; ++i) {
-            const int l = lab[i];
-            if (l != cur) {
-                if (ch < 0) {
-                    atomicAdd(&cnt[cur], a);
-                } else {
-                    atomicAdd(&s0[(size_t)cur * C + ch], a);
-                    atomicAdd(&s1[(size_t)cur * C + ch], b);
-                }
-                cur = l;
-                a = b = 0.0;
-            }
-            if (ch < 0) {
-                a += 1.0;
-            } else {
-                a += (double)c0[i * C + ch];
-                b += (double)c[i * C + ch];
-            }
-        }
-        if (ch < 0) {
-            atomicAdd(&cnt[cur], a);
-        } else {
-            atomicAdd(&s0[(size_t)cur * C + ch], a);
-            atomicAdd(&s1[(size_t)cur * C + ch], b);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kT)
-label_means_kernel(const double* __restrict__ cnt, double* __restrict__ s0, double* __restrict__ s1, int k, int C,
-                   int* __restrict__ flags) {
-    const int j = blockIdx.x * kT + threadIdx.x;
-    if (j >= k) return;
-    const double n = cnt[j];
-    if (n > 0.0) {
-        atomicAdd(&flags[kNonEmpty], 1);
-        for (int ch = 0; ch < C; ++ch) {
-            s0[(size_t)j * C + ch] /= n;
-            s1[(size_t)j * C + ch] /= n;
-        }
-    }
-}
-
-// Squared deviations of c0 from its label means.
-__global__ void __launch_bounds__(kT)
-label_dev_kernel(const float* __restrict__ c0, const int* __restrict__ lab, size_t N, int C,
-                 const double* __restrict__ m0, double* __restrict__ dev) {
-    const size_t p0 = ((size_t)blockIdx.x * kT + threadIdx.x) * kRun;
-    if (p0 >= N) return;
+    const double S = fx_scale(flags, (double)N);
+    if (p0 >= N || S == 0.0) return;
     const size_t p1 = p0 + kRun < N ? p0 + kRun : N;
     int cur = lab[p0];
-    double a = 0.0;
+    double n = 0.0;
     for (size_t i = p0; i < p1; ++i) {
         const int l = lab[i];
         if (l != cur) {
-            atomicAdd(&dev[cur], a);
+            atomicAdd(&cnt[cur], n);
             cur = l;
-            a = 0.0;
+            n = 0.0;
         }
-        for (int ch = 0; ch < C; ++ch) {
-            const double d = (double)c0[i * C + ch] - m0[(size_t)l * C + ch];
-            a = fma(d, d, a);
-        }
+        n += 1.0;
     }
-    atomicAdd(&dev[cur], a);
+    atomicAdd(&cnt[cur], n);
+    for (int ch = 0; ch < C; ++ch) {
+        cur = lab[p0];
+        long long h0 = 0, h1 = 0;
+        unsigned long long l0 = 0, l1 = 0;
+        for (size_t i = p0; i < p1; ++i) {
+            const int l = lab[i];
+            if (l != cur) {
+                fx_flush(s0 + 2 * ((size_t)cur * C + ch), h0, l0);
+                fx_flush(s1 + 2 * ((size_t)cur * C + ch), h1, l1);
+                cur = l;
+                h0 = h1 = 0;
+                l0 = l1 = 0;
+            }
+            fx_add((double)c0[i * C + ch] * S, h0, l0);
+            fx_add((double)c[i * C + ch] * S, h1, l1);
+        }
+        fx_flush(s0 + 2 * ((size_t)cur * C + ch), h0, l0);
+        fx_flush(s1 + 2 * ((size_t)cur * C + ch), h1, l1);
+    }
 }
 
-// IRV = sum_j dev_j / N by one workgroup in a fixed order.
+// Label means m0, m1 of c0 and c from the fixed-point sums.
 __global__ void __launch_bounds__(kT)
-irv_kernel(const double* __restrict__ dev, int k, double invN, double* __restrict__ out) {
-    __shared__ double s[kT];
-    double a = 0.0;
-    for (int j = threadIdx.x; j < k; j += kT) a += dev[j];
-    s[threadIdx.x] = a;
+label_means_kernel(const double* __restrict__ cnt, const unsigned long long* __restrict__ s0,
+                   const unsigned long long* __restrict__ s1, size_t N, int k, int C, int* __restrict__ flags,
+                   double* __restrict__ m0, double* __restrict__ m1) {
+    const int j = blockIdx.x * kT + threadIdx.x;
+    if (j >= k) return;
+    const double S = fx_scale(flags, (double)N);
+    const double n = cnt[j];
+    if (n > 0.0 && S != 0.0) {
+        atomicAdd(&flags[kNonEmpty], 1);
+        for (int ch = 0; ch < C; ++ch) {
+            const size_t e = (size_t)j * C + ch;
+            m0[e] = fx_value(s0 + 2 * e) / S / n;
+            m1[e] = fx_value(s1 + 2 * e) / S / n;
+        }
+    }
+}
+
+// Squared deviations of c0 from its label means, per label in fixed point
+// (pairs hi, lo), with the bound 4 C (largest |value|)^2 per pixel.
+__global__ void __launch_bounds__(kT)
+label_dev_kernel(const float* __restrict__ c0, const int* __restrict__ lab, size_t N, int C,
+                 const int* __restrict__ flags, const double* __restrict__ m0, unsigned long long* __restrict__ dev) {
+    const size_t p0 = ((size_t)blockIdx.x * kT + threadIdx.x) * kRun;
+    const float a = __int_as_float(flags[kAbsMax]);
+    const double S = fx_scale(flags, 4.0 * (double)N * (double)C * (double)a);
+    if (p0 >= N || S == 0.0) return;
+    const size_t p1 = p0 + kRun < N ? p0 + kRun : N;
+    int cur = lab[p0];
+    long long h = 0;
+    unsigned long long lo = 0;
+    for (size_t i = p0; i < p1; ++i) {
+        const int l = lab[i];
+        if (l != cur) {
+            fx_flush(dev + 2 * (size_t)cur, h, lo);
+            cur = l;
+            h = 0;
+            lo = 0;
+        }
+        double t = 0.0;
+        for (int ch = 0; ch < C; ++ch) {
+            const double d = (double)c0[i * C + ch] - m0[(size_t)l * C + ch];
+            t = fma(d, d, t);
+        }
+        fx_add(t * S, h, lo);
+    }
+    fx_flush(dev + 2 * (size_t)cur, h, lo);
+}
+
+// IRV = sum_j dev_j / N: integer sums of the hi and lo words over the labels
+// by one workgroup (exact, so their order is immaterial), then one conversion.
+__global__ void __launch_bounds__(kT)
+irv_kernel(const unsigned long long* __restrict__ dev, int k, size_t N, int C, const int* __restrict__ flags,
+           double* __restrict__ out) {
+    __shared__ unsigned long long s[2][kT];
+    unsigned long long h = 0, lo = 0;
+    for (int j = threadIdx.x; j < k; j += kT) {
+        h += dev[2 * (size_t)j];
+        lo += dev[2 * (size_t)j + 1];
+    }
+    s[0][threadIdx.x] = h;
+    s[1][threadIdx.x] = lo;
     __syncthreads();
     for (int off = kT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        if (threadIdx.x < off) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + off];
+            s[1][threadIdx.x] += s[1][threadIdx.x + off];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = s[0] * invN;
+    if (threadIdx.x == 0) {
+        const float a = __int_as_float(flags[kAbsMax]);
+        const double S = fx_scale(flags, 4.0 * (double)N * (double)C * (double)a);
+        const unsigned long long t[2] = {s[0][0], s[1][0]};
+        *out = S == 0.0 ? NAN : fx_value(t) / S / (double)N;
+    }
 }
 
 // IRC: least distance between the mean colours of two non-empty labels.
@@ -448,9 +530,11 @@ struct SegWs {
     unsigned long long* best;
     unsigned long long* keys;  // [0] min (g2, index) key, [1] IRC bits
     double* cnt;
-    double* s0;
-    double* s1;
-    double* dev;
+    unsigned long long* s0;  // fixed-point pairs (hi, lo) per label and channel
+    unsigned long long* s1;
+    double* m0;              // label means
+    double* m1;
+    unsigned long long* dev;  // fixed-point pairs per label
     double* irv;
     size_t bytes;
 };
@@ -478,9 +562,11 @@ SegWs carve(void* base, int H, int W, int C) {
     w.best = (unsigned long long*)take(N * sizeof(unsigned long long));
     w.keys = (unsigned long long*)take(2 * sizeof(unsigned long long));
     w.cnt = (double*)take(N * sizeof(double));
-    w.s0 = (double*)take(N * (size_t)C * sizeof(double));
-    w.s1 = (double*)take(N * (size_t)C * sizeof(double));
-    w.dev = (double*)take(N * sizeof(double));
+    w.s0 = (unsigned long long*)take(2 * N * (size_t)C * sizeof(unsigned long long));
+    w.s1 = (unsigned long long*)take(2 * N * (size_t)C * sizeof(unsigned long long));
+    w.m0 = (double*)take(N * (size_t)C * sizeof(double));
+    w.m1 = (double*)take(N * (size_t)C * sizeof(double));
+    w.dev = (unsigned long long*)take(2 * N * sizeof(unsigned long long));
     w.irv = (double*)take(sizeof(double));
     w.bytes = o;
     return w;
@@ -571,6 +657,13 @@ int abc_segment(const float* c, const float* c0, int H, int W, int C, float thet
     const int* lab = labels_in;
     int k = 0;
     SEG_LAUNCH(clear_flags_kernel, 1, w.flags, (int)kFlags);
+    const int ab = (int)std::min<size_t>((size_t)nblocks(N * C), 2048);
+    SEG_LAUNCH(absmax_kernel, ab, c, c0, N * C, w.flags);
+    if ((rc = read_flags(f, w.flags, st)) != ABC_OK) return rc;
+    if (f[kAbsMax] >= 0x7f800000) {
+        set_last_error("abc_segment: c or c0 holds a NaN or an infinity");
+        return ABC_ENONFINITE;
+    }
     if (!labels_in) {
         SEG_LAUNCH(set_u64_kernel, 1, w.keys, kNoEdge);
         SEG_LAUNCH(relief_kernel, nb, c, H, W, C, theta * theta, w.g2, w.mk, w.par, w.keys, w.flags);
@@ -641,21 +734,24 @@ int abc_segment(const float* c, const float* c0, int H, int W, int C, float thet
     out.k = k;
     // scores
     const int zb = 1024;
-    SEG_LAUNCH(zero_kernel, zb, w.cnt, (size_t)k);
-    SEG_LAUNCH(zero_kernel, zb, w.s0, (size_t)k * C);
-    SEG_LAUNCH(zero_kernel, zb, w.s1, (size_t)k * C);
-    SEG_LAUNCH(zero_kernel, zb, w.dev, (size_t)k);
+    SEG_LAUNCH(zero_kernel<double>, zb, w.cnt, (size_t)k);
+    SEG_LAUNCH(zero_kernel<unsigned long long>, zb, w.s0, 2 * (size_t)k * C);
+    SEG_LAUNCH(zero_kernel<unsigned long long>, zb, w.s1, 2 * (size_t)k * C);
+    SEG_LAUNCH(zero_kernel<unsigned long long>, zb, w.dev, 2 * (size_t)k);
     SEG_LAUNCH(clear_flags_kernel, 1, w.flags, (int)kFlags);
     SEG_LAUNCH(set_u64_kernel, 1, w.keys + 1, kNoEdge);
+    SEG_LAUNCH(absmax_kernel, ab, c, c0, N * C, w.flags);  // the fixed-point scales
     const int nr = nblocks((N + kRun - 1) / kRun);
-    SEG_LAUNCH(label_sums_kernel, nr, c, c0, lab, N, C, w.cnt, w.s0, w.s1);
-    SEG_LAUNCH(label_means_kernel, nblocks((size_t)k), (const double*)w.cnt, w.s0, w.s1, k, C, w.flags);
-    SEG_LAUNCH(label_dev_kernel, nr, c0, lab, N, C, (const double*)w.s0, w.dev);
-    hipLaunchKernelGGL(irv_kernel, dim3(1), dim3(kT), 0, st, (const double*)w.dev, k, 1.0 / (double)N, w.irv);
+    SEG_LAUNCH(label_sums_kernel, nr, c, c0, lab, N, C, (const int*)w.flags, w.cnt, w.s0, w.s1);
+    SEG_LAUNCH(label_means_kernel, nblocks((size_t)k), (const double*)w.cnt, (const unsigned long long*)w.s0,
+               (const unsigned long long*)w.s1, N, k, C, w.flags, w.m0, w.m1);
+    SEG_LAUNCH(label_dev_kernel, nr, c0, lab, N, C, (const int*)w.flags, (const double*)w.m0, w.dev);
+    hipLaunchKernelGGL(irv_kernel, dim3(1), dim3(kT), 0, st, (const unsigned long long*)w.dev, k, N, C,
+                       (const int*)w.flags, w.irv);
     SEG_HIP(hipGetLastError());
     const size_t pairs = (size_t)k * k;
     const int gb = (int)std::min<size_t>(std::max<size_t>((pairs + kT - 1) / kT, 1), 8192);
-    SEG_LAUNCH(irc_kernel, gb, (const double*)w.cnt, (const double*)w.s1, k, C, w.keys + 1);
+    SEG_LAUNCH(irc_kernel, gb, (const double*)w.cnt, (const double*)w.m1, k, C, w.keys + 1);
     unsigned long long ircbits = 0;
     double irv = 0.0;
     SegReadback* pin = seg_readback();

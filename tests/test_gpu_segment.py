@@ -1,7 +1,7 @@
 """GPU parity of the segmentation scores of Sec. 4.4: watershed labels bit for
 bit against the oracle (both sides take every comparison on the same FP32
-relief), IRV / IRC / VS within 1e-10 relative (FP64 on both sides; the GPU
-adds per-label sums with atomics in a varying order)."""
+relief), IRV / IRC / VS within 1e-10 relative (the oracle sums in FP64, the
+GPU in 2^-92-scaled fixed-point integers, the same bits on every run)."""
 import numpy as np
 import pytest
 
@@ -95,11 +95,47 @@ def test_out_of_range_labels_are_rejected():
         A.abc_segment(T(img), T(img), labels=bad)
 
 
-def test_repeat_calls_give_identical_labels():
+def test_repeat_calls_give_identical_labels_and_score_bits():
     c = voronoi_image(150, 170, 3, 10, 0.02, 2011)
-    a, _ = A.abc_segment(T(c), T(c))
-    b, _ = A.abc_segment(T(c), T(c))
-    assert torch.equal(a, b)
+    c0 = voronoi_image(150, 170, 3, 9, 0.05, 2012)
+    a, sa = A.abc_segment(T(c), T(c0))
+    for _ in range(3):
+        b, sb = A.abc_segment(T(c), T(c0))
+        assert torch.equal(a, b)
+        for key in ("irv", "irc", "vs"):
+            assert np.float64(sa[key]).tobytes() == np.float64(sb[key]).tobytes(), key
+    # many small labels, so that many runs of pixels add into each label sum
+    lab = (np.arange(150 * 170).reshape(150, 170) // 7 % 211).astype(np.int32)
+    L = torch.as_tensor(lab, device="cuda")
+    _, s1 = A.abc_segment(T(c), T(c0), labels=L)
+    _, s2 = A.abc_segment(T(c), T(c0), labels=L)
+    assert np.float64(s1["irv"]).tobytes() == np.float64(s2["irv"]).tobytes()
+    assert np.float64(s1["irc"]).tobytes() == np.float64(s2["irc"]).tobytes()
+    check_scores(s1, O.seg_metrics(c, c0, lab))
+
+
+def test_values_far_from_one_keep_the_tolerance():
+    # the fixed-point scale follows the largest |value|: images scaled by 2^40 and 2^-40
+    # give the scores scaled by the same powers (IRV by the square), to the same tolerance
+    c = voronoi_image(60, 70, 3, 6, 0.02, 2013)
+    c0 = voronoi_image(60, 70, 3, 6, 0.05, 2014)
+    for f in (2.0 ** 40, 2.0 ** -40):
+        cs, c0s = (c * f).astype(np.float32), (c0 * f).astype(np.float32)
+        lab, st = A.abc_segment(T(cs), T(c0s), 0.02 * f)
+        ref = O.segment(cs, c0s, 0.02 * f)
+        np.testing.assert_array_equal(lab.cpu().numpy(), ref["labels"])
+        check_scores(st, ref)
+
+
+@pytest.mark.parametrize("where", ["c", "c0"])
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_input_is_rejected(where, bad):
+    c = voronoi_image(20, 24, 3, 4, 0.02, 2015)
+    c0 = c.copy()
+    (c if where == "c" else c0)[5, 7, 1] = bad
+    with pytest.raises(A.AbcError) as e:
+        A.abc_segment(T(c), T(c0))
+    assert e.value.code == A.ABC_ENONFINITE
 
 
 def test_solver_output_at_full_size():
