@@ -353,46 +353,49 @@ __device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs, i
 }
 
 // Runs body(g) for the global tiles g of a multi-image launch.  Without a
-// queue the grid has one workgroup per tile, handed to the XCDs in contiguous
-// runs.  With a queue (the persistent form: fewer workgroups than tiles) the
-// tiles are split into the same 8 contiguous runs, and each workgroup takes the
-// next tile of run blockIdx.x % 8 from the counter queue[8 k + run] (an atomic
-// add) until the run is used up; no workgroup waits for another, and every one
-// stops once its counter passes the run's end.  A tile's results do not depend
-// on which workgroup computes it.
-template <class Body>
+// queue (PQ false) the grid has one workgroup per tile, handed to the XCDs in
+// contiguous runs.  With a queue (PQ true, the persistent form: fewer
+// workgroups than tiles) the tiles are split into the same 8 contiguous runs,
+// and each workgroup takes the next tile of run blockIdx.x % 8 from the counter
+// queue[8 k + run] (an atomic add) until the run is used up; no workgroup waits
+// for another, and every one stops once its counter passes the run's end.  A
+// tile's results do not depend on which workgroup computes it.  The two forms
+// are separate kernels: the loop raises the register count of the transposed
+// step (161 to 225 VGPRs at C = 3, R = 5), which would cost the one-tile form
+// a wave per SIMD.
+template <bool PQ, class Body>
 __device__ __forceinline__ void for_batched_tiles(int* __restrict__ queue, int k, int total, Body&& body) {
-    if (!queue) {
+    if constexpr (!PQ) {
         body(xcd_tile(blockIdx.x, gridDim.x));
-        return;
-    }
-    // 16 bytes, so that the dynamic LDS placed after the static variables stays
-    // aligned for the 16-byte slot reads
-    __shared__ __align__(16) int next[4];
-    const int x = blockIdx.x % 8;
-    const int per = total / 8, rem = total % 8;
-    const int lo = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
-    const int n = per + (x < rem ? 1 : 0);
-    const bool first = threadIdx.x == 0 && threadIdx.y == 0;
-    for (;;) {
-        if (first) next[0] = atomicAdd(queue + 8 * k + x, 1);
-        __syncthreads();
-        const int i = next[0];
-        if (i >= n) break;
-        body(lo + i);
-        __syncthreads();  // every thread is done with the tile (and with `next`)
+    } else {
+        // 16 bytes, so that the dynamic LDS placed after the static variables
+        // stays aligned for the 16-byte slot reads
+        __shared__ __align__(16) int next[4];
+        const int x = blockIdx.x % 8;
+        const int per = total / 8, rem = total % 8;
+        const int lo = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+        const int n = per + (x < rem ? 1 : 0);
+        const bool first = threadIdx.x == 0 && threadIdx.y == 0;
+        for (;;) {
+            if (first) next[0] = atomicAdd(queue + 8 * k + x, 1);
+            __syncthreads();
+            const int i = next[0];
+            if (i >= n) break;
+            body(lo + i);
+            __syncthreads();  // every thread is done with the tile (and with `next`)
+        }
     }
 }
 
 // Forward step k of several images in one launch: the tiles of every job,
 // jobs[j].start being the first global tile of job j.
-template <int CP, int RT>
+template <int CP, int RT, bool PQ>
 __global__ void __launch_bounds__(kMaxThreads)
 fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C, int Rrt, int total,
                         int* __restrict__ queue) {
     extern __shared__ __align__(16) float lds[];
     const int R = RT > 0 ? RT : Rrt;
-    for_batched_tiles(queue, k, total, [&](int g) {
+    for_batched_tiles<PQ>(queue, k, total, [&](int g) {
         const StepJob& J = jobs[find_job(jobs, njobs, g)];
         const size_t f = (size_t)J.H * J.W * C;
         const float* e = J.eps + 2 * k;
@@ -558,14 +561,14 @@ adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, floa
 // Transposed step k of several images in one launch.  p^{k+1} is read from
 // pa when K-1-k is even, else from pb, and p^k goes to the other buffer;
 // part receives K x tiles x 2 partials per job.
-template <int CP, int RT>
+template <int CP, int RT, bool PQ>
 __global__ void __launch_bounds__(kMaxThreads)
 adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C, int Rrt, int total,
                         int* __restrict__ queue) {
     extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
     const int R = RT > 0 ? RT : Rrt;
-    for_batched_tiles(queue, k, total, [&](int g) {
+    for_batched_tiles<PQ>(queue, k, total, [&](int g) {
         const StepJob& J = jobs[find_job(jobs, njobs, g)];
         const size_t f = (size_t)J.H * J.W * C;
         const bool even = ((K - 1 - k) & 1) == 0;
@@ -862,12 +865,12 @@ fwd_step_wide_kernel(const float* __restrict__ cin, float* __restrict__ cout, co
                           lds);
 }
 
-template <int CP, int RT>
+template <int CP, int RT, bool PQ>
 __global__ void __launch_bounds__(kMaxWideThreads)
 fwd_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int C, int total,
                              int* __restrict__ queue) {
     extern __shared__ __align__(16) float lds[];
-    for_batched_tiles(queue, k, total, [&](int g) {
+    for_batched_tiles<PQ>(queue, k, total, [&](int g) {
         const StepJob& J = jobs[find_job(jobs, njobs, g)];
         const size_t f = (size_t)J.H * J.W * C;
         const float* e = J.eps + 2 * k;
@@ -890,13 +893,13 @@ adj_step_wide_kernel(const float* __restrict__ c, const float* __restrict__ pin,
                           part, lds, red);
 }
 
-template <int CP, int RT>
+template <int CP, int RT, bool PQ>
 __global__ void __launch_bounds__(kMaxWideThreads)
 adj_step_batched_wide_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C, int total,
                              int* __restrict__ queue) {
     extern __shared__ __align__(16) float lds[];
     __shared__ double red[16];
-    for_batched_tiles(queue, k, total, [&](int g) {
+    for_batched_tiles<PQ>(queue, k, total, [&](int g) {
         const StepJob& J = jobs[find_job(jobs, njobs, g)];
         const size_t f = (size_t)J.H * J.W * C;
         const bool even = ((K - 1 - k) & 1) == 0;
@@ -1383,7 +1386,7 @@ hipError_t fwdb_wide_launch(const StepJob* jobs, int njobs, int total, int k, in
                             hipStream_t s) {
     constexpr int G = Wide<CP>::G;
     const size_t lds = tile_lds_bytes(C, RT, t, 1);
-    auto fn = fwd_step_batched_wide_kernel<CP, RT>;
+    auto fn = queue ? fwd_step_batched_wide_kernel<CP, RT, true> : fwd_step_batched_wide_kernel<CP, RT, false>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1398,7 +1401,7 @@ hipError_t adjb_wide_launch(const StepJob* jobs, int njobs, int total, int k, in
                             hipStream_t s) {
     constexpr int G = Wide<CP>::G;
     const size_t lds = tile_lds_bytes(C, RT, t, 2);
-    auto fn = adj_step_batched_wide_kernel<CP, RT>;
+    auto fn = queue ? adj_step_batched_wide_kernel<CP, RT, true> : adj_step_batched_wide_kernel<CP, RT, false>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1460,7 +1463,7 @@ template <int CP, int RT>
 hipError_t fwdb_launch_t(const StepJob* jobs, int njobs, int total, int k, int C, int R, Tile t, int* queue,
                          hipStream_t s) {
     const size_t lds = tile_lds_bytes(CP, R, t, 1);
-    auto fn = fwd_step_batched_kernel<CP, RT>;
+    auto fn = queue ? fwd_step_batched_kernel<CP, RT, true> : fwd_step_batched_kernel<CP, RT, false>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1475,7 +1478,7 @@ template <int CP, int RT>
 hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K, int C, int R, Tile t, int* queue,
                          hipStream_t s) {
     const size_t lds = tile_lds_bytes(CP, R, t, 2);
-    auto fn = adj_step_batched_kernel<CP, RT>;
+    auto fn = queue ? adj_step_batched_kernel<CP, RT, true> : adj_step_batched_kernel<CP, RT, false>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
