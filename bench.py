@@ -45,8 +45,8 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "cda3415547de939ca32165bc85fc0ebbec670e480c07e4c4581c70f1f8206bb4",
-    "adj_step_kernel<3,5>": 11.53e6,
+    "kernel_sha256": "3fe76b25c4648403a9ae9bad0063d4537c33d02600f8c8005454a59029d27760",
+    "adj_step_kernel<3,5>": 11.51e6,
     "adj_step_wide_kernel<31,2>": 1607.64e6,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")

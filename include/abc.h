@@ -45,7 +45,20 @@ extern "C" {
 #define ABC_ENOCONV 1       /* warning: caps reached before tol_alm; outputs valid */
 
 #define ABC_MAX_CHANNELS 64
+/* Largest window radius of the LDS-tiled interaction kernels.  Larger radii
+ * (up to ABC_MAX_DIRECT_RADIUS) run direct kernels that read each pixel's
+ * window from global memory: O(N (2R+1)^2) work per step, meant for small
+ * images, among them the un-windowed sum of eq. MAsystem (a window that
+ * covers the image, with s = 1/N). */
 #define ABC_MAX_RADIUS 16
+#define ABC_MAX_DIRECT_RADIUS 32767
+/* abc_params.R value asking for the radius of the kernel's support: the
+ * library takes, for each image, R* of abc_support_radius() with eps_x at the
+ * box's lower bound eps_min[0].  Every pair with phi(r_ij) > 0 for any
+ * control in the box then lies inside the window, so the window sum is the
+ * un-windowed sum of eq. MAsystem for every admissible control.  Not taken by
+ * abc_solve_batched. */
+#define ABC_RADIUS_SUPPORT (-1)
 
 /* Solver parameters.  abc_default_params() fills the paper's values
  * (Sec. 3.2: dt = 0.25, E = [2,1100]^2, eps0 = 57, sigma0 = 1, b = 1/2,
@@ -53,7 +66,8 @@ extern "C" {
 typedef struct abc_params {
     int32_t K;           /* explicit Euler steps (horizon T = K dt)                 */
     float dt;            /* time step                                               */
-    int32_t R;           /* interaction window radius in pixels (square window)     */
+    int32_t R;           /* interaction window radius in pixels (square window), in
+                            [0, ABC_MAX_DIRECT_RADIUS], or ABC_RADIUS_SUPPORT        */
     float inv_norm;      /* s scaling the interaction sum; 0 => 1/min(N,(2R+1)^2)  */
     float eps_min[2];    /* control box E = [eps_min, eps_max] per component       */
     float eps_max[2];
@@ -143,6 +157,16 @@ int abc_default_params(abc_params* p);
 /* Bytes of device workspace the entry point `kind` (ABC_WS_*) needs for an
  * H x W x C image under *p.  Host only; launches nothing. */
 int abc_workspace_bytes(int kind, int H, int W, int C, const abc_params* p, size_t* bytes);
+
+/* Radius of the kernel's support on an H x W image (Sec. 2, the ellipsoid of
+ * influence; eq. kernel vanishes for r >= 1): r_ij <= 1 needs
+ * eps_x/2 |x_j - x_i|^2 <= 1, i.e. a distance of at most sqrt(2 / eps_x) in
+ * the unit square, so
+ *   *R = min(ceil(sqrt(2 / eps_x_min) max(H, W)), max(H, W) - 1)
+ * (the whole image when eps_x_min = 0).  Pixel spacing is 1/W across and 1/H
+ * down, as in abc_forward_dynamics.  Returns ABC_EINVAL for H or W < 1, a
+ * negative or NaN eps_x_min, or a NULL R.  Host only. */
+int abc_support_radius(int H, int W, float eps_x_min, int32_t* R);
 
 /* Number of trajectory slots abc_forward_dynamics writes: K + 1 when
  * p->ckpt_every == 0, else ceil(K / ckpt_every) + 1 (slot m holds the state

@@ -23,6 +23,9 @@ ABC_WS_TUNE = 4
 ABC_FLAG_NO_GRAPHS = 1
 ABC_FLAG_AUTOTUNE = 2
 ABC_FLAG_PERSISTENT = 4
+ABC_MAX_RADIUS = 16  # largest radius of the LDS-tiled kernels; larger ones run the direct kernels
+ABC_MAX_DIRECT_RADIUS = 32767
+ABC_RADIUS_SUPPORT = -1  # Params.R asking for the support radius of each image (abc_support_radius)
 
 
 class AbcParams(ct.Structure):
@@ -163,6 +166,7 @@ def lib():
     L.abc_version.restype = ct.c_int
     L.abc_last_error.restype = ct.c_char_p
     L.abc_default_params.argtypes = [ct.POINTER(AbcParams)]
+    L.abc_support_radius.argtypes = [ct.c_int, ct.c_int, ct.c_float, ct.POINTER(ct.c_int32)]
     L.abc_workspace_bytes.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.POINTER(AbcParams),
                                       ct.POINTER(ct.c_size_t)]
     L.abc_traj_slots.argtypes = [ct.POINTER(AbcParams), ct.POINTER(ct.c_int)]
@@ -238,6 +242,14 @@ def _ptr_i32(t):
 # ------------------------------------------------------------------ host-only calls
 def abc_version() -> int:
     return lib().abc_version()
+
+
+def abc_support_radius(H: int, W: int, eps_x_min: float) -> int:
+    """Window radius that holds the kernel's support on an H x W image for every
+    eps_x >= eps_x_min (whole image when that is smaller)."""
+    r = ct.c_int32(0)
+    _check(lib().abc_support_radius(H, W, ct.c_float(eps_x_min), ct.byref(r)))
+    return r.value
 
 
 def abc_default_params() -> Params:

@@ -173,7 +173,8 @@ int check_shape(int H, int W, int C) {
 int check_params(const abc_params* p) {
     if (!p) return fail(ABC_EINVAL, "params is NULL");
     if (p->K < 1) return fail(ABC_EINVAL, "K must be >= 1");
-    if (p->R < 0 || p->R > ABC_MAX_RADIUS) return fail(ABC_EINVAL, "R must be in [0, 16]");
+    if ((p->R < 0 || p->R > ABC_MAX_DIRECT_RADIUS) && p->R != ABC_RADIUS_SUPPORT)
+        return fail(ABC_EINVAL, "R must be in [0, 32767] or ABC_RADIUS_SUPPORT");
     if (!(p->dt > 0.0f) || !std::isfinite(p->dt)) return fail(ABC_EINVAL, "dt must be > 0");
     if (!(p->inv_norm >= 0.0f)) return fail(ABC_EINVAL, "inv_norm must be >= 0");
     for (int m = 0; m < 2; ++m) {
@@ -194,6 +195,17 @@ int check_params(const abc_params* p) {
     if (!(p->stop_K >= 0.0)) return fail(ABC_EINVAL, "stop_K must be >= 0");
     if (!(p->tol_gap >= 0.0)) return fail(ABC_EINVAL, "tol_gap must be >= 0");
     return ABC_OK;
+}
+
+// p with R resolved for an H x W image when it asks for the support radius
+// (ABC_RADIUS_SUPPORT), p itself otherwise.  Call after check_params.
+const abc_params* with_radius(const abc_params* p, int H, int W, abc_params& tmp) {
+    if (p->R != ABC_RADIUS_SUPPORT) return p;
+    tmp = *p;
+    int32_t r = 0;
+    (void)abc_support_radius(H, W, p->eps_min[0], &r);
+    tmp.R = r;
+    return &tmp;
 }
 
 int pick_tile(const abc_params* p, int C, int fields, abc::Tile* t) {
@@ -465,6 +477,15 @@ extern "C" {
 
 int abc_version(void) { return 100; }
 
+int abc_support_radius(int H, int W, float eps_x_min, int32_t* R) {
+    if (!R || H < 1 || W < 1 || !(eps_x_min >= 0.0f))
+        return fail(ABC_EINVAL, "abc_support_radius: H, W >= 1, eps_x_min >= 0 and non-NULL R required");
+    const int whole = std::max(H, W) - 1;
+    const double r = std::ceil(std::sqrt(2.0 / (double)eps_x_min) * (double)std::max(H, W));
+    *R = (eps_x_min == 0.0f || !(r < (double)whole)) ? whole : (int32_t)r;
+    return ABC_OK;
+}
+
 const char* abc_last_error(void) { return g_last_error.c_str(); }
 
 int abc_default_params(abc_params* p) {
@@ -505,6 +526,8 @@ int abc_workspace_bytes(int kind, int H, int W, int C, const abc_params* p, size
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
+    abc_params pr;
+    p = with_radius(p, H, W, pr);
     if (!bytes) return fail(ABC_EINVAL, "bytes is NULL");
     if (kind < ABC_WS_SOLVE || kind > ABC_WS_TUNE) return fail(ABC_EINVAL, "unknown workspace kind");
     if (kind == ABC_WS_TUNE) {
@@ -524,6 +547,8 @@ int abc_forward_dynamics(const float* c0, int H, int W, int C, const float* eps,
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
     if (!c0 || !eps || !traj) return fail(ABC_EINVAL, "c0, eps and traj must be non-NULL");
+    abc_params pr;
+    p = with_radius(p, H, W, pr);
     const Shape s{H, W, C};
     abc::Tile t;
     if ((rc = pick_tile(p, C, 1, &t))) return rc;
@@ -565,6 +590,8 @@ int abc_adjoint_dynamics_noalloc(const float* traj, int H, int W, int C, const f
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
+    abc_params pr;
+    p = with_radius(p, H, W, pr);
     abc::Tile tf, ta;
     if ((rc = pick_tile(p, C, 1, &tf))) return rc;
     if ((rc = pick_tile(p, C, 2, &ta))) return rc;
@@ -588,6 +615,8 @@ int adjoint_dynamics_impl(const float* traj, int H, int W, int C, const float* e
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
     if (!traj || !eps || !gK || !g0 || !geps) return fail(ABC_EINVAL, "traj, eps, gK, g0, geps must be non-NULL");
+    abc_params pr;
+    p = with_radius(p, H, W, pr);
     const Shape s{H, W, C};
     abc::Tile tf, ta;
     if ((rc = pick_tile(p, C, 1, &tf))) return rc;
@@ -690,6 +719,8 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
+    abc_params pr;
+    p = with_radius(p, H, W, pr);
     if (!c0 || !c_out) return fail(ABC_EINVAL, "c0 and c_out must be non-NULL");
     if (p->ckpt_every != 0) return fail(ABC_EINVAL, "abc_solve stores full trajectories; set ckpt_every = 0");
     const double* decisions_in = log ? log->decisions_in : nullptr;
@@ -1557,6 +1588,7 @@ extern "C" {
 int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C, const abc_params* p, size_t* bytes) {
     int rc = check_params(p);
     if (rc) return rc;
+    if (p->R < 0 || p->R > ABC_MAX_RADIUS) return fail(ABC_EINVAL, "the batched solve takes R in [0, 16]");
     if (!H || !W || !bytes || n < 1) return fail(ABC_EINVAL, "H, W, bytes must be non-NULL and n >= 1");
     for (int i = 0; i < n; ++i)
         if ((rc = check_shape(H[i], W[i], C))) return rc;
@@ -1580,6 +1612,7 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
                       void* stream, abc_stats* st, double* finish_ms, const abc_solve_log* logs) {
     int rc = check_params(p);
     if (rc) return rc;
+    if (p->R < 0 || p->R > ABC_MAX_RADIUS) return fail(ABC_EINVAL, "the batched solve takes R in [0, 16]");
     if (!imgs || n < 1) return fail(ABC_EINVAL, "imgs must be non-NULL and n >= 1");
     if (p->ckpt_every != 0) return fail(ABC_EINVAL, "abc_solve_batched stores full trajectories; set ckpt_every = 0");
     std::vector<int32_t> Hs(n), Ws(n);
@@ -1997,6 +2030,17 @@ extern "C" int abc_autotune(const float* c0, int H, int W, int C, abc_params* p,
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
+    if (p->R == ABC_RADIUS_SUPPORT) {
+        // tune for the resolved radius; p keeps asking for the support radius
+        abc_params pr;
+        pr = *with_radius(p, H, W, pr);
+        if ((rc = abc_autotune(c0, H, W, C, &pr, cache_path, ws, ws_bytes, stream, best_us))) return rc;
+        p->tile_x = pr.tile_x;
+        p->tile_y = pr.tile_y;
+        p->adj_tile_x = pr.adj_tile_x;
+        p->adj_tile_y = pr.adj_tile_y;
+        return ABC_OK;
+    }
     if (!c0) return fail(ABC_EINVAL, "c0 must be non-NULL");
     if (best_us) best_us[0] = best_us[1] = 0.0;
     if (p->R == 0) return ABC_OK;

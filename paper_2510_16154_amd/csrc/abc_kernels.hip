@@ -26,6 +26,7 @@
 #include <climits>
 #include <type_traits>
 
+#include "../../include/abc.h"
 #include "abc_internal.h"
 
 namespace abc {
@@ -578,6 +579,150 @@ adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
                          tile - trow * J.tiles_x, trow, J.tiles_x, J.dts, J.dx2, J.dy2,
                          J.part + (size_t)k * J.tiles * 2, lds, red);
     });
+}
+
+// ----------------------------------------------------------------------------
+// Direct interaction steps, for radii beyond the tiled kernels' halos
+// (R > ABC_MAX_RADIUS) up to the whole image: with R at least the support
+// radius of eq. kernel (r_ij <= 1 needs eps_x/2 |x_j - x_i|^2 <= 1), or R
+// covering the image and s = 1/N, the window sum is the un-windowed sum of
+// eq. MAsystem.  Same grid and partial slots as the tiled kernels (NP pixels
+// per thread); each pixel reads its neighbours straight from global memory (a
+// small image stays in L2), clips its window to the image, which leaves out
+// only zero terms, and sums it in the (a, b) order with the tiled kernels'
+// operations (squares of the offsets taken in float, exact up to 4096 and
+// free of integer overflow for any radius).  O(N (2R+1)^2) work per step:
+// meant for small images.
+template <int CP>
+__device__ __forceinline__ void load_global_px(const float* __restrict__ p, int C, float (&v)[CP]) {
+#pragma unroll
+    for (int ch = 0; ch < CP; ++ch) v[ch] = ch < C ? p[ch] : 0.0f;
+}
+
+template <int CP>
+__global__ void __launch_bounds__(kMaxThreads)
+fwd_direct_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps, int k,
+                  int H, int W, int C, int R, int tiles_x, int tiles_y, float dts, float dx2, float dy2) {
+    constexpr int NP = RowsPerThread<CP>::value;
+    int tcol, trow;
+    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
+    const int gx = tcol * blockDim.x + threadIdx.x;
+    if (gx >= W) return;
+    const float exh = 0.5f * eps[2 * k], ech = 0.5f * eps[2 * k + 1];
+    const float Ax = exh * dx2, Ay = exh * dy2;
+    const int b0 = max(-R, -gx), b1 = min(R, W - 1 - gx);
+    for (int m = 0; m < NP; ++m) {
+        const int gy = (trow * blockDim.y + threadIdx.y) * NP + m;
+        if (gy >= H) break;
+        float ci[CP], acc[CP];
+        load_global_px<CP>(cin + ((size_t)gy * W + gx) * C, C, ci);
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
+        const int a0 = max(-R, -gy), a1 = min(R, H - 1 - gy);
+        for (int a = a0; a <= a1; ++a) {
+            const float* row = cin + ((size_t)(gy + a) * W + gx) * C;
+            const float oma = fmaf(-Ay, ((float)a * (float)a), 1.0f);
+            for (int b = b0; b <= b1; ++b) {
+                if (a == 0 && b == 0) continue;
+                float cj[CP], d[CP];
+                load_global_px<CP>(row + (ptrdiff_t)b * C, C, cj);
+                float n2 = 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    d[ch] = cj[ch] - ci[ch];
+                    n2 = fmaf(d[ch], d[ch], n2);
+                }
+                const float t = clamp01(fmaf(-ech, n2, fmaf(-Ax, ((float)b * (float)b), oma)));
+                const float t2 = t * t;
+                const float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(w, d[ch], acc[ch]);
+            }
+        }
+        float* o = cout + ((size_t)gy * W + gx) * C;
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch)
+            if (ch < C) o[ch] = fmaf(dts, acc[ch], ci[ch]);
+    }
+}
+
+// Transposed step in the direct form; part[2*tile + {0,1}] as in adj_tile (the
+// integrands summed over each pixel's whole window).
+template <int CP>
+__global__ void __launch_bounds__(kMaxThreads)
+adj_direct_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
+                  const float* __restrict__ eps, int k, int H, int W, int C, int R, int tiles_x, int tiles_y,
+                  float dts, float dx2, float dy2, double* __restrict__ part) {
+    constexpr int NP = RowsPerThread<CP>::value;
+    __shared__ double red[16];
+    int tcol, trow;
+    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
+    const int gx = tcol * blockDim.x + threadIdx.x;
+    const float ex = eps[2 * k], ec = eps[2 * k + 1];
+    const float exh = 0.5f * ex, ech = 0.5f * ec, ec20 = 20.0f * ec;
+    const float Ax = exh * dx2, Ay = exh * dy2;
+    const int b0 = max(-R, -gx), b1 = min(R, W - 1 - gx);
+    double tsx = 0.0, tsc = 0.0;
+    for (int m = 0; m < NP; ++m) {
+        const int gy = (trow * blockDim.y + threadIdx.y) * NP + m;
+        if (gx >= W || gy >= H) break;
+        float ci[CP], pi[CP], acc[CP], accq[CP];
+        load_global_px<CP>(c + ((size_t)gy * W + gx) * C, C, ci);
+        load_global_px<CP>(pin + ((size_t)gy * W + gx) * C, C, pi);
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch) acc[ch] = accq[ch] = 0.0f;
+        float sx = 0.0f, sc = 0.0f;
+        const int a0 = max(-R, -gy), a1 = min(R, H - 1 - gy);
+        for (int a = a0; a <= a1; ++a) {
+            const size_t rbase = ((size_t)(gy + a) * W + gx) * C;
+            const float oma = fmaf(-Ay, ((float)a * (float)a), 1.0f);
+            const float d2a = dy2 * ((float)a * (float)a);
+            for (int b = b0; b <= b1; ++b) {
+                if (a == 0 && b == 0) continue;
+                float cj[CP], pj[CP], d[CP], dp[CP];
+                load_global_px<CP>(c + rbase + (ptrdiff_t)b * C, C, cj);
+                load_global_px<CP>(pin + rbase + (ptrdiff_t)b * C, C, pj);
+                const float d2 = fmaf(dx2, ((float)b * (float)b), d2a);
+                float n2 = 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    d[ch] = cj[ch] - ci[ch];
+                    n2 = fmaf(d[ch], d[ch], n2);
+                }
+                const float t = clamp01(fmaf(-ech, n2, fmaf(-Ax, ((float)b * (float)b), oma)));
+                const float t3 = (t * t) * t;
+                const float u = fmaf(t3, t, -t3);
+                const float w = fmaf(u, fmaf(-4.0f, t, 1.0f), t3);
+                float ddp = 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    dp[ch] = pj[ch] - pi[ch];
+                    ddp = fmaf(d[ch], dp[ch], ddp);
+                }
+                const float q = u * ddp;
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    acc[ch] = fmaf(w, dp[ch], acc[ch]);
+                    accq[ch] = fmaf(q, d[ch], accq[ch]);
+                }
+                sx = fmaf(d2, q, sx);
+                sc = fmaf(n2, q, sc);
+            }
+        }
+        float* o = pout + ((size_t)gy * W + gx) * C;
+#pragma unroll
+        for (int ch = 0; ch < CP; ++ch)
+            if (ch < C) o[ch] = fmaf(dts, fmaf(ec20, accq[ch], acc[ch]), pi[ch]);
+        tsx += (double)sx;
+        tsc += (double)sc;
+    }
+    const double bx = block_sum_f64(tsx, red);
+    const double bc = block_sum_f64(tsc, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const int tile = trow * tiles_x + tcol;
+        part[2 * tile + 0] = bx;
+        part[2 * tile + 1] = bc;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1411,11 +1556,36 @@ hipError_t adjb_wide_launch(const StepJob* jobs, int njobs, int total, int k, in
     return hipGetLastError();
 }
 
+template <int CP>
+hipError_t fwd_direct_launch(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
+                             float dts, Tile t, hipStream_t s) {
+    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
+    dim3 grid;
+    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
+    const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
+    hipLaunchKernelGGL(fwd_direct_kernel<CP>, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value), 0, s, cin, cout,
+                       eps, k, H, W, C, R, tiles_x, tiles_y, dts, dx2, dy2);
+    return hipGetLastError();
+}
+
+template <int CP>
+hipError_t adj_direct_launch(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
+                             int C, int R, float dts, Tile t, double* part, hipStream_t s) {
+    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
+    dim3 grid;
+    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
+    const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
+    hipLaunchKernelGGL(adj_direct_kernel<CP>, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value), 0, s, c, pin,
+                       pout, eps, k, H, W, C, R, tiles_x, tiles_y, dts, dx2, dy2, part);
+    return hipGetLastError();
+}
+
 // Compile-time radii for the small-channel kernels (full unroll of the window);
 // wider channel counts and other radii use the runtime-radius kernel.
 template <int CP>
 hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
                         float dts, Tile t, hipStream_t s) {
+    if (R > ABC_MAX_RADIUS) return fwd_direct_launch<CP>(cin, cout, eps, k, H, W, C, R, dts, t, s);
     if constexpr (CP <= 4) {
         switch (R) {
             case 1: return fwd_launch_t<CP, 1>(cin, cout, eps, k, H, W, C, R, dts, t, s);
@@ -1439,6 +1609,7 @@ hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, 
 template <int CP>
 hipError_t adj_launch_r(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
                         int C, int R, float dts, Tile t, double* part, hipStream_t s) {
+    if (R > ABC_MAX_RADIUS) return adj_direct_launch<CP>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
     if constexpr (CP <= 4) {
         switch (R) {
             case 1: return adj_launch_t<CP, 1>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
@@ -1548,6 +1719,7 @@ int wide_lanes(int C, int R) {
 size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     const int cp = padded_channels(C);
     if (cp < 0) return (size_t)-1;
+    if (R > ABC_MAX_RADIUS) return 0;  // the direct kernels stage nothing
     const int G = wide_lanes(C, R);
     if (G > 1) return (size_t)fields * G * wide_plane_floats(t.tx + 2 * R, t.ty + 2 * R) * sizeof(float);
     const int nv = (cp + 1 + 3) / 4;

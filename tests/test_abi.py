@@ -49,7 +49,7 @@ def test_workspace_sizes_and_slots():
     assert A.abc_traj_slots(p.replace(K=95, ckpt_every=10)) == 11
 
 
-@pytest.mark.parametrize("bad", [dict(K=0), dict(R=-1), dict(R=17), dict(dt=0.0), dict(rho=0.0),
+@pytest.mark.parametrize("bad", [dict(K=0), dict(R=-2), dict(R=32768), dict(dt=0.0), dict(rho=0.0),
                                  dict(eps_min=(5.0, 2.0), eps_max=(4.0, 1100.0)), dict(max_ls=0),
                                  dict(armijo_b=1.0), dict(ckpt_every=-1), dict(tile_x=7, tile_y=3)])
 def test_invalid_parameters_are_rejected_on_the_host(bad):
@@ -96,6 +96,30 @@ def test_null_pointers_are_rejected():
     assert L.abc_solve(None, 8, 8, 3, ct.byref(p), None, None, None, None, None, 0, None, None,
                        None) == A.ABC_EINVAL
     assert L.abc_pd_step(None, None, 8, 8, 3, ct.byref(p), None, None, 1, None, None, 0, None) == A.ABC_EINVAL
+
+
+def test_support_radius_on_the_host():
+    # R* = min(ceil(sqrt(2 / eps_x_min) max(H, W)), max(H, W) - 1)
+    assert A.abc_support_radius(512, 512, 1100.0) == 22  # 21.83 rounded up
+    assert A.abc_support_radius(512, 512, 2.0) == 511  # the whole image
+    assert A.abc_support_radius(40, 56, 20.0) == 18
+    assert A.abc_support_radius(56, 40, 20.0) == 18  # square window: the longer side
+    assert A.abc_support_radius(7, 3, 0.0) == 6
+    assert A.abc_support_radius(1, 1, 57.0) == 0
+    for bad in [(0, 8, 2.0), (8, 0, 2.0), (8, 8, -1.0), (8, 8, float("nan"))]:
+        with pytest.raises(A.AbcError) as e:
+            A.abc_support_radius(*bad)
+        assert e.value.code == A.ABC_EINVAL
+    # the support mode sizes workspaces as the radius it resolves to; radii past 16 stage nothing
+    p = A.Params(K=4, R=A.ABC_RADIUS_SUPPORT, eps_min=(20.0, 2.0))
+    for kind in (A.ABC_WS_SOLVE, A.ABC_WS_ADJOINT):
+        assert A.abc_workspace_bytes(kind, 40, 56, 3, p) == A.abc_workspace_bytes(kind, 40, 56, 3, p.replace(R=18))
+    assert A.abc_workspace_bytes(A.ABC_WS_SOLVE, 40, 40, 3, A.Params(K=4, R=200, tile_x=32, tile_y=16)) > 0
+    # the batched solve keeps to the tiled kernels
+    for R in (A.ABC_RADIUS_SUPPORT, 17):
+        with pytest.raises(A.AbcError) as e:
+            A.abc_workspace_bytes_batched([(32, 32), (40, 48)], 3, A.Params(K=4, R=R))
+        assert e.value.code == A.ABC_EINVAL
 
 
 def test_segment_entry_points_check_arguments_on_the_host():

@@ -456,6 +456,47 @@ def test_unwindowed_paper_sum_matches_oracle(orc, C):
 
 
 
+@pytest.mark.parametrize("H,W,C,emin", [(40, 56, 3, 20.0), (24, 20, 1, 2.0), (24, 20, 5, 2.0),
+                                         (30, 33, 31, 6.0)])
+def test_support_radius_mode_matches_oracle(orc, H, W, C, emin):
+    """R = ABC_RADIUS_SUPPORT: the library takes the window of the kernel's support at
+    the box's lower bound eps_x >= emin (eq. kernel vanishes for r >= 1), here beyond the
+    tiled kernels' radius 16, so the direct kernels run; at emin = 2 the window is the
+    whole image.  With s = 1/N that is the un-windowed sum of eq. MAsystem."""
+    R = A.abc_support_radius(H, W, emin)
+    assert R > A.ABC_MAX_RADIUS
+    print(f"support radius case H={H} W={W} C={C} emin={emin} R={R}", flush=True)
+    c0 = voronoi_image(H, W, C, 4, 0.05, 90 + C)
+    eps = rand_eps(5, 91, lo=emin, hi=300.0)
+    gp = A.Params(K=5, R=A.ABC_RADIUS_SUPPORT, inv_norm=1.0 / (H * W), eps_min=(emin, 2.0))
+    op = orc.Params(K=5, R=R, s=1.0 / (H * W))
+    traj = A.abc_forward_dynamics(T(c0), T(eps), gp)
+    want = orc.forward_sweep(c0, op, eps)
+    assert relinf(N(traj), want) < FIELD_TOL / 10
+    gK = np.random.default_rng(92).normal(size=c0.shape)
+    g0, geps = A.abc_adjoint_dynamics(traj, T(eps), gp, T(gK))
+    p0, ge = orc.adjoint_sweep(want, op, gK, eps)
+    assert relinf(N(g0), p0) < FIELD_TOL and rel2(N(geps), ge) < FIELD_TOL
+    # the same radius given explicitly runs the same kernels: the same bits
+    traj2 = A.abc_forward_dynamics(T(c0), T(eps), gp.replace(R=R))
+    assert torch.equal(traj, traj2)
+
+
+def test_support_radius_solve_matches_oracle(orc):
+    """A short solve with R = ABC_RADIUS_SUPPORT on a 20 x 20 image with the paper's box
+    (eps_x >= 2: the window is the whole image, s = 1/N by the default rule) against the
+    oracle at that radius, controls replayed."""
+    H = W = 20
+    c0 = voronoi_image(H, W, 3, 4, 0.05, 93)
+    gp, op = both_params(orc, H, W, K=8, R=A.ABC_RADIUS_SUPPORT, alpha=50.0, max_outer=2, max_inner=3)
+    op.R = A.abc_support_radius(H, W, gp.eps_min[0])
+    assert op.R == 19
+    ref = orc.solve(c0, op)
+    out = A.abc_solve(T(c0), gp, decisions=ref["decisions"], eps_replay=ref["eps_log"])
+    assert relinf(N(out["c"]), ref["c"]) < FIELD_TOL
+    assert abs(out["stats"]["K"] - ref["stats"]["K"]) <= 1e-5 * abs(ref["stats"]["K"])
+
+
 def test_gap_stop_matches_oracle(orc):
     """The Lagrangian-gap stop (Sec. 4.1) ends the GPU solve at the same multiplier
     iteration as the oracle's when the controls are replayed."""

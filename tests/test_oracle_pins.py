@@ -68,6 +68,26 @@ def test_whole_image_window_is_the_papers_sum(orc):
     assert np.max(np.abs(got - want)) < 1e-14
 
 
+def test_support_radius_window_is_the_papers_sum(orc):
+    """The window radius of the kernel's support (eq. kernel vanishes for r >= 1, so every
+    interacting pair has eps_x/2 |x_j - x_i|^2 <= 1; the library's abc_support_radius, a
+    host-only call) makes the windowed step the un-windowed sum of eq. MAsystem for every
+    eps_x above the bound, on a nearly flat image where the pairs near the support's edge
+    interact; two pixels less and it is not."""
+    import paper_2510_16154_amd as A
+    H, W, C = 9, 11, 2
+    c = 0.5 + 1e-3 * _rng(21).uniform(size=(H, W, C))
+    emin = 40.0
+    R = A.abc_support_radius(H, W, emin)
+    assert R == 3  # ceil(sqrt(2 / 40) * 11)
+    for ex in (emin, 60.0):
+        got = orc.forward_step(c, _P(orc, K=1, R=R, s=1.0 / (H * W)), ex, 30.0)
+        want = brute.euler_allpairs(c, ex, 30.0, 0.25)
+        assert np.max(np.abs(got - want)) < 1e-14
+    short = orc.forward_step(c, _P(orc, K=1, R=R - 2, s=1.0 / (H * W)), emin, 30.0)
+    assert np.max(np.abs(short - brute.euler_allpairs(c, emin, 30.0, 0.25))) > 1e-7
+
+
 def test_forward_window_is_square_and_clipped(orc):
     H, W, C, R = 7, 6, 2, 2
     c = _rng(11).uniform(0, 1, size=(H, W, C))
