@@ -16,12 +16,15 @@
 // Loss per batch: mean over pixels of |mu0 - mu*|^2 + w_eps * mean over (image, k, m) of (e - e*)^2,
 // e* = (eps* - eps_min) / (eps_max - eps_min).
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: one wavefront owns a
-// 16 (pixels) x 16 (output channels) tile and walks K = 9 Cin in steps of 32, gathering
-// its operand fragments straight from the NHWC activations (zero outside the image).
-// The data gradient is the same kernel on the output gradient with the taps flipped
-// and the weight matrix transposed; the weight gradient contracts over pixels in
-// chunks whose partial sums are added in a fixed order by a second kernel.
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16.  A workgroup of four
+// wavefronts owns a 16 x 4 pixel tile and every output channel: the 6 x 18 pixel input
+// patch is staged in LDS as BF16 with the channels padded to a multiple of 8, so that
+// the 8 k of an A fragment (8 channels of one tap) are one 16-byte LDS read, and the
+// weights are laid out once per call as BF16 rows WT[n][k] (k = tap x padded channels,
+// zero-padded to a multiple of 32), so that a B fragment is one 16-byte read.  The
+// data gradient is the same kernel on the output gradient with the taps flipped and
+// the weight matrix transposed; the weight gradient contracts over pixels in chunks
+// whose partial sums are added in a fixed order by a second kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +41,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;       // threads of the elementwise kernels
-constexpr int kChunk = 1024;  // pixels per weight-gradient partial
+constexpr int kChunk = 1024;    // pixels per weight-gradient partial
+constexpr int kColChunk = 256;  // rows per column-sum partial (bias gradients, global pooling)
 
 thread_local std::string g_net_error;
 
@@ -56,50 +60,132 @@ int nfail(int code, const std::string& m) {
 // ---------------------------------------------------------------------------
 // Kernels.
 
-// Y[b, p, yoff + co] = act(bias[co] + sum_{t, ci} bf16(X[b, p + off(t), ci]) * Wb[t * Cin + ci][co]).
-// Grid (ceil(HW / 16), ceil(Cout / 16), B), one wavefront per workgroup.
-__global__ void __launch_bounds__(64) conv3x3_kernel(const float* __restrict__ X, int Cin, const __bf16* __restrict__ Wb,
-                                                     const float* __restrict__ bias, float* __restrict__ Y, int Cout,
-                                                     int ystride, int yoff, int H, int W, int relu) {
-    const int l = threadIdx.x;
-    const int b = blockIdx.z;
-    const int HW = H * W;
-    const int Ktot = 9 * Cin;
-    const float* Xb = X + (size_t)b * HW * Cin;
-    const int prow = blockIdx.x * 16 + (l & 15);
-    const int py = prow / W, px = prow - (prow / W) * W;
-    const int col = blockIdx.y * 16 + (l & 15);
-    const int kg = (l >> 4) * 8;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int kc = 0; kc < Ktot; kc += 32) {
-        bf16x8 a, w;
+// Y[b, p, yoff + n] = act(bias[n] + sum_k A[p][k] WT[n][k]) with A[p][t CINP + c] the
+// input at pixel p + off(t) (taps t row major, dy = t / 3 - 1, dx = t % 3 - 1), channel c,
+// rounded to BF16; zero outside the image, for channels past the input's, and for k >= 9
+// CINP up to Kp.  The input is X (Cin channels), or with X2 given the concatenation of X
+// upsampled 2x by nearest neighbour (Cin channels, an H/2 x W/2 field) and X2 (C2
+// channels, H x W), read straight into the staged patch.
+// Grid (ceil(W / 16), ceil(H / 8), B), 256 threads: the workgroup stages the 10 x 18 x
+// CINP patch of a 16 x 8 pixel tile, four channels per load where the input's channels
+// come in fours, and wave w computes rows 2w and 2w + 1 of it, 16 pixels x nt blocks of
+// 16 output channels each (nt <= 5), so every B fragment serves two MFMAs.
+template <int CINP>
+__global__ void __launch_bounds__(256) conv3x3_tile_kernel(const float* __restrict__ X, int Cin,
+                                                           const float* __restrict__ X2, int C2,
+                                                           const __bf16* __restrict__ WT, int Kp,
+                                                           const float* __restrict__ bias, float* __restrict__ Y,
+                                                           int Nout, int nt, int ystride, int yoff, int H, int W,
+                                                           int relu) {
+    constexpr int RPW = 2, PW = 18, PH = 4 * RPW + 2, Q = CINP / 4;
+    __shared__ __align__(16) __bf16 patch[PH * PW * CINP];
+    const int b = blockIdx.z, x0 = blockIdx.x * 16, y0 = blockIdx.y * (4 * RPW);
+    const int Ctot = Cin + (X2 ? C2 : 0);
+    // whole fours of channels from one source: one 16-byte load per quad
+    const bool quads = Ctot == CINP && (Cin % 4) == 0 && (!X2 || (C2 % 4) == 0);
+    for (int e = threadIdx.x; e < PH * PW * Q; e += 256) {
+        const int c = 4 * (e % Q), cell = e / Q;
+        const int r = cell / PW, q = cell - r * PW;
+        const int yy = y0 - 1 + r, xx = x0 - 1 + q;
+        const bool in = (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (in && quads) {
+            const float* src = !X2 ? X + (((size_t)b * H + yy) * W + xx) * Cin + c
+                               : c < Cin ? X + (((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Cin + c
+                                         : X2 + (((size_t)b * H + yy) * W + xx) * C2 + (c - Cin);
+            const float4 f = *reinterpret_cast<const float4*>(src);
+            v[0] = f.x;
+            v[1] = f.y;
+            v[2] = f.z;
+            v[3] = f.w;
+        } else if (in) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = kc + kg + j;
-            float xv = 0.0f, wv = 0.0f;
-            if (k < Ktot) {
-                const int t = k / Cin, ci = k - t * Cin;
-                const int yy = py + t / 3 - 1, xx = px + t % 3 - 1;
-                if (prow < HW && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
-                    xv = Xb[((size_t)yy * W + xx) * Cin + ci];
-                if (col < Cout) wv = (float)Wb[(size_t)k * Cout + col];
+            for (int u = 0; u < 4; ++u) {
+                const int cu = c + u;
+                if (cu >= Ctot) break;
+                if (!X2)
+                    v[u] = X[(((size_t)b * H + yy) * W + xx) * Cin + cu];
+                else if (cu < Cin)
+                    v[u] = X[(((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Cin + cu];
+                else
+                    v[u] = X2[(((size_t)b * H + yy) * W + xx) * C2 + (cu - Cin)];
             }
-            a[j] = (__bf16)xv;
-            w[j] = (__bf16)wv;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc, 0, 0, 0);
-    }
-    if (col >= Cout) return;
-    const float bv = bias ? bias[col] : 0.0f;
+        __bf16* d = &patch[cell * CINP + c];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int p = blockIdx.x * 16 + (l >> 4) * 4 + i;
-        if (p < HW) {
-            float v = acc[i] + bv;
-            if (relu) v = fmaxf(v, 0.0f);
-            Y[((size_t)b * HW + p) * ystride + yoff + col] = v;
+        for (int u = 0; u < 4; ++u) d[u] = (__bf16)v[u];
+    }
+    __syncthreads();
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = l & 15, kg = (l >> 4) * 8;
+    f32x4 acc[RPW][5];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc[rr][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kc = 0; kc < Kp; kc += 32) {
+        const int k0 = kc + kg;
+        const int t = k0 / CINP, c0 = k0 - t * CINP;
+        bf16x8 a[RPW];
+        if (t < 9) {
+            const int dy = t / 3, dx = t - 3 * dy;
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr)
+                a[rr] = *reinterpret_cast<const bf16x8*>(&patch[((RPW * w + rr + dy) * PW + m + dx) * CINP + c0]);
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a[rr][j] = (__bf16)0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            if (j < nt) {
+                const bf16x8 bw = *reinterpret_cast<const bf16x8*>(WT + (size_t)(j * 16 + m) * Kp + k0);
+#pragma unroll
+                for (int rr = 0; rr < RPW; ++rr)
+                    acc[rr][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rr], bw, acc[rr][j], 0, 0, 0);
+            }
         }
     }
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+        const int py = y0 + RPW * w + rr;
+        if (py >= H) break;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int col = j * 16 + m;
+            if (j >= nt || col >= Nout) continue;
+            const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = x0 + (l >> 4) * 4 + i;
+                if (px < W) {
+                    float v = acc[rr][j][i] + bv;
+                    if (relu) v = fmaxf(v, 0.0f);
+                    Y[(((size_t)b * H + py) * W + px) * ystride + yoff + col] = v;
+                }
+            }
+        }
+    }
+}
+
+// BF16 weight rows for conv3x3_tile_kernel, WT[n][k] for n < npad, k < Kp, k = t inp + c:
+//   flip = 0 (forward):       W[t Cin + c][n]        for t < 9, c < Cin, n < Cout;
+//   flip = 1 (data gradient): W[(8 - t) Cin + n][c]  for t < 9, c < Cout, n < Cin;
+// 0 elsewhere.  W is [9 Cin][Cout] FP32.
+__global__ void __launch_bounds__(kT) prep_wt_kernel(const float* __restrict__ Wt, int Cin, int Cout, int flip,
+                                                     int inp, int Kp, int npad, __bf16* __restrict__ WT) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad * Kp) return;
+    const int n = i / Kp, k = i - n * Kp;
+    const int t = k / inp, c = k - t * inp;
+    float v = 0.0f;
+    if (t < 9) {
+        if (!flip && c < Cin && n < Cout) v = Wt[(size_t)(t * Cin + c) * Cout + n];
+        if (flip && c < Cout && n < Cin) v = Wt[(size_t)((8 - t) * Cin + n) * Cout + c];
+    }
+    WT[i] = (__bf16)v;
 }
 
 // part[c][k][co] = sum over pixels q of chunk c (flattened over the batch) of
@@ -174,28 +260,42 @@ __device__ __forceinline__ float bsum(float v, float* red) {
     return s;
 }
 
-// out[co] = sum over rows r of X[r * C + co]   (bias gradient; one block per channel).
-__global__ void __launch_bounds__(kT) colsum_kernel(const float* __restrict__ X, size_t rows, int C,
-                                                    float* __restrict__ out) {
-    __shared__ float red[4];
-    const int co = blockIdx.x;
-    float s = 0.0f;
-    for (size_t r = threadIdx.x; r < rows; r += kT) s += X[r * C + co];
-    s = bsum(s, red);
-    if (threadIdx.x == 0) out[co] = s;
+// Column sums of row chunks: part[(b nchunks + c) C + col] = sum over rows r of chunk c
+// (kColChunk rows, the last one shorter) of X[b rows + r][col], for C <= 64.  Grid (nchunks, B),
+// 256 threads: thread (g, col) sums rows g, g + 4, ... of the chunk in order, then the four
+// row groups are added in order, so the sums have a fixed order.
+__global__ void __launch_bounds__(kT) colsum_chunks_kernel(const float* __restrict__ X, size_t rows, int C,
+                                                           float* __restrict__ part) {
+    __shared__ float red[4][64];
+    const int col = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const size_t r0 = (size_t)blockIdx.x * kColChunk;
+    const size_t r1 = min(r0 + kColChunk, rows);
+    const float* Xb = X + (size_t)blockIdx.y * rows * C;
+    float acc = 0.0f;
+    if (col < C)
+        for (size_t r = r0 + g; r < r1; r += 4) acc += Xb[r * C + col];
+    red[g][col] = acc;
+    __syncthreads();
+    if (g == 0 && col < C)
+        part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * C + col] =
+            ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
 }
 
-// Out[b][t' * Cout + co][ci] = bf16(W[(8 - t') * Cin + ci][co]) and Wb = bf16(W).
-__global__ void __launch_bounds__(kT) weights_bf16_kernel(const float* __restrict__ Wt, int Cin, int Cout,
-                                                          __bf16* __restrict__ Wb, __bf16* __restrict__ Wf) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = 9 * Cin * Cout;
-    if (i >= n) return;
-    const int co = i % Cout, k = i / Cout;
-    const int t = k / Cin, ci = k % Cin;
-    const __bf16 v = (__bf16)Wt[i];
-    Wb[i] = v;
-    Wf[((size_t)(8 - t) * Cout + co) * Cin + ci] = v;
+// out[b C + col] = scale * sum over chunks c of part[(b nchunks + c) C + col]: one block per
+// output, thread t summing chunks t, t + 256, ... in order, then a fixed tree.
+__global__ void __launch_bounds__(kT) finish_colsum_kernel(const float* __restrict__ part, int nchunks, int C,
+                                                           float scale, float* __restrict__ out) {
+    __shared__ float red[kT];
+    const int i = blockIdx.x, b = i / C, col = i - b * C;
+    float acc = 0.0f;
+    for (int c = threadIdx.x; c < nchunks; c += kT) acc += part[((size_t)b * nchunks + c) * C + col];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kT / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = scale * red[0];
 }
 
 __global__ void __launch_bounds__(kT) avgpool2_kernel(const float* __restrict__ A, int H, int W, int C, int B,
@@ -309,18 +409,6 @@ __global__ void __launch_bounds__(kT) mu_head_kernel(const float* __restrict__ z
     if (threadIdx.x == 0) part[blockIdx.x] = lsum;
 }
 
-// g[b][c] = mean over the pixels of image b of A[., c]  (grid (B, C)).
-__global__ void __launch_bounds__(kT) gpool_kernel(const float* __restrict__ A, size_t npix, int C,
-                                                   float* __restrict__ g) {
-    __shared__ float red[4];
-    const int b = blockIdx.x, c = blockIdx.y;
-    const float* a = A + (size_t)b * npix * C + c;
-    float s = 0.0f;
-    for (size_t p = threadIdx.x; p < npix; p += kT) s += a[p * C];
-    s = bsum(s, red);
-    if (threadIdx.x == 0) g[b * C + c] = s / (float)npix;
-}
-
 // Control head of one image (one block per image, blockDim >= n_out):
 // e = sigmoid(bl + g Wl); with a target: loss partial, dWl / dbl per image, dg.
 __global__ void __launch_bounds__(kT) eps_head_kernel(const float* __restrict__ g, int C, const float* __restrict__ Wl,
@@ -414,13 +502,28 @@ NetShape net_shape(int K) {
 }
 
 struct NetWs {
-    float *a1, *p1, *a2, *a3, *cat, *a4, *z, *g, *e;
+    float *a1, *p1, *a2, *a3, *cat, *a4, *z, *g, *e, *cpart;
     float *d1, *dp1, *d2, *d3, *dcat, *d4, *dz, *dg, *dWl_part, *dbl_part, *wpart, *lpart, *lout;
-    __bf16 *wb, *wf;
+    __bf16 *wt, *wtf;  // BF16 weight rows of the five layers: forward, and flipped for the data gradient
     size_t used;
 };
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// Shape of a layer's BF16 weight rows for conv3x3_tile_kernel: input channels padded to
+// a multiple of 8 (inp), K = 9 inp padded to a multiple of 32, npad output rows.
+struct WtRows {
+    int inp, Kp, npad;
+    size_t elems() const { return (size_t)npad * Kp; }
+};
+WtRows wt_rows(const Layer& L, bool flip) {
+    const int in = flip ? L.cout : L.cin, out = flip ? L.cin : L.cout;
+    WtRows r;
+    r.inp = (in + 7) / 8 * 8;
+    r.Kp = (9 * r.inp + 31) / 32 * 32;
+    r.npad = (out + 15) / 16 * 16;
+    return r;
+}
 
 NetWs carve_net(void* base, int B, int H, int W, const NetShape& s, bool train) {
     NetWs w;
@@ -437,16 +540,20 @@ NetWs carve_net(void* base, int B, int H, int W, const NetShape& s, bool train) 
     w.p1 = (float*)take(P2 * 16 * 4);
     w.a2 = (float*)take(P2 * 32 * 4);
     w.a3 = (float*)take(P2 * 64 * 4);
-    w.cat = (float*)take(P * 80 * 4);
+    w.cat = train ? (float*)take(P * 80 * 4) : nullptr;  // inference reads a3 and a1 directly
     w.a4 = (float*)take(P * 32 * 4);
     w.z = (float*)take(P * 6 * 4);
     w.g = (float*)take((size_t)B * 64 * 4);
     w.e = (float*)take((size_t)B * s.nout * 4);
-    size_t nw = 0;
-    for (int i = 0; i < 5; ++i) nw += (size_t)9 * s.L[i].cin * s.L[i].cout;
-    w.wb = (__bf16*)take(nw * 2);
-    w.wf = (__bf16*)take(nw * 2);
+    size_t nw = 0, nwf = 0;
+    for (int i = 0; i < 5; ++i) {
+        nw += wt_rows(s.L[i], false).elems();
+        nwf += wt_rows(s.L[i], true).elems();
+    }
+    w.wt = (__bf16*)take(nw * 2);
+    w.wtf = (__bf16*)take(nwf * 2);
     w.lpart = (float*)take((P / kT + 2 + B) * 4);
+    w.cpart = (float*)take(((P + kColChunk - 1) / kColChunk + B) * 64 * 4);  // chunk partials of column sums
     w.lout = (float*)take(4 * 4);
     if (train) {
         w.d1 = (float*)take(P * 16 * 4);
@@ -484,33 +591,42 @@ struct Net {
     hipStream_t st;
     const float* prm;
 
-    __bf16* wb(int i) const {
+    __bf16* wt(int i, bool flip) const {
         size_t off = 0;
-        for (int j = 0; j < i; ++j) off += (size_t)9 * s.L[j].cin * s.L[j].cout;
-        return w.wb + off;
-    }
-    __bf16* wf(int i) const {
-        size_t off = 0;
-        for (int j = 0; j < i; ++j) off += (size_t)9 * s.L[j].cin * s.L[j].cout;
-        return w.wf + off;
+        for (int j = 0; j < i; ++j) off += wt_rows(s.L[j], flip).elems();
+        return (flip ? w.wtf : w.wt) + off;
     }
 
-    int conv(int i, const float* X, int h, int wd, float* Y, int ystride, int yoff, bool relu) {
+    // Y (ystride channels per pixel, from channel yoff) = act(conv(X) + bias) with the
+    // rows of layer i, forward or flipped
+    // (X2: the input is [upsample2(X), X2] with X of the layer's input channels less C2)
+    int conv_rows(int i, bool flip, const float* X, int h, int wd, const float* bias, float* Y, int ystride, int yoff,
+                  bool relu, const float* X2 = nullptr, int C2 = 0) {
         const Layer& L = s.L[i];
-        dim3 grid((h * wd + 15) / 16, (L.cout + 15) / 16, B);
-        hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(64), 0, st, X, L.cin, wb(i), prm + L.b, Y, L.cout, ystride, yoff, h,
-                           wd, relu ? 1 : 0);
+        const WtRows r = wt_rows(L, flip);
+        const int cin = (flip ? L.cout : L.cin) - (X2 ? C2 : 0), nout = flip ? L.cin : L.cout;
+        dim3 grid((wd + 15) / 16, (h + 7) / 8, B);
+        auto launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, X, cin, X2, C2, (const __bf16*)wt(i, flip), r.Kp, bias, Y,
+                               nout, r.npad / 16, ystride, yoff, h, wd, relu ? 1 : 0);
+        };
+        switch (r.inp) {
+            case 8: launch(conv3x3_tile_kernel<8>); break;
+            case 16: launch(conv3x3_tile_kernel<16>); break;
+            case 32: launch(conv3x3_tile_kernel<32>); break;
+            case 64: launch(conv3x3_tile_kernel<64>); break;
+            case 80: launch(conv3x3_tile_kernel<80>); break;
+            default: return nfail(ABC_EINVAL, "no convolution kernel for this channel count");
+        }
         NET_HIP(hipGetLastError());
         return ABC_OK;
+    }
+    int conv(int i, const float* X, int h, int wd, float* Y, int ystride, int yoff, bool relu) {
+        return conv_rows(i, false, X, h, wd, prm + s.L[i].b, Y, ystride, yoff, relu);
     }
     // dX = conv^T(dY) for layer i (flipped, transposed weights, no bias)
     int conv_t(int i, const float* dY, int h, int wd, float* dX) {
-        const Layer& L = s.L[i];
-        dim3 grid((h * wd + 15) / 16, (L.cin + 15) / 16, B);
-        hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(64), 0, st, dY, L.cout, wf(i), nullptr, dX, L.cin, L.cin, 0, h, wd,
-                           0);
-        NET_HIP(hipGetLastError());
-        return ABC_OK;
+        return conv_rows(i, true, dY, h, wd, nullptr, dX, s.L[i].cin, 0, false);
     }
     int wgrad(int i, const float* X, const float* dY, int h, int wd, float* grad) {
         const Layer& L = s.L[i];
@@ -523,22 +639,33 @@ struct Net {
         const int n = Kt * L.cout;
         hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb(n)), dim3(kT), 0, st, w.wpart, chunks, n, grad + L.w);
         NET_HIP(hipGetLastError());
-        hipLaunchKernelGGL(colsum_kernel, dim3(L.cout), dim3(kT), 0, st, dY, P, L.cout, grad + L.b);
+        return colsum(dY, P, L.cout, 1, 1.0f, grad + L.b);
+    }
+    // out[b C + c] = scale * sum over the rows of batch b of X[., c] (C <= 64), in a fixed order
+    int colsum(const float* X, size_t rows, int C, int nbatch, float scale, float* out) {
+        const int chunks = (int)((rows + kColChunk - 1) / kColChunk);
+        hipLaunchKernelGGL(colsum_chunks_kernel, dim3(chunks, nbatch), dim3(kT), 0, st, X, rows, C, w.cpart);
+        NET_HIP(hipGetLastError());
+        hipLaunchKernelGGL(finish_colsum_kernel, dim3(nbatch * C), dim3(kT), 0, st, (const float*)w.cpart, chunks, C,
+                           scale, out);
         NET_HIP(hipGetLastError());
         return ABC_OK;
     }
 
     int prepare_weights() {
-        for (int i = 0; i < 5; ++i) {
-            const int n = 9 * s.L[i].cin * s.L[i].cout;
-            hipLaunchKernelGGL(weights_bf16_kernel, dim3(nb(n)), dim3(kT), 0, st, prm + s.L[i].w, s.L[i].cin, s.L[i].cout,
-                               wb(i), wf(i));
-            NET_HIP(hipGetLastError());
-        }
+        for (int i = 0; i < 5; ++i)
+            for (int flip = 0; flip < 2; ++flip) {
+                const WtRows r = wt_rows(s.L[i], flip != 0);
+                hipLaunchKernelGGL(prep_wt_kernel, dim3(nb(r.elems())), dim3(kT), 0, st, prm + s.L[i].w, s.L[i].cin,
+                                   s.L[i].cout, flip, r.inp, r.Kp, r.npad, wt(i, flip != 0));
+                NET_HIP(hipGetLastError());
+            }
         return ABC_OK;
     }
 
-    int forward(const float* x) {
+    // with train the concatenation is kept for the weight gradient; without, the fourth
+    // layer reads a3 (upsampled) and a1 straight into its staged patch
+    int forward(const float* x, bool train) {
         int rc;
         const int h2 = H / 2, w2 = W / 2;
         const size_t P = (size_t)B * H * W;
@@ -548,13 +675,15 @@ struct Net {
         NET_HIP(hipGetLastError());
         if ((rc = conv(1, w.p1, h2, w2, w.a2, 32, 0, true))) return rc;
         if ((rc = conv(2, w.a2, h2, w2, w.a3, 64, 0, true))) return rc;
-        hipLaunchKernelGGL(up_concat_kernel, dim3(nb(P * 80)), dim3(kT), 0, st, w.a3, 64, w.a1, 16, H, W, B, w.cat);
-        NET_HIP(hipGetLastError());
-        if ((rc = conv(3, w.cat, H, W, w.a4, 32, 0, true))) return rc;
+        if (train) {
+            hipLaunchKernelGGL(up_concat_kernel, dim3(nb(P * 80)), dim3(kT), 0, st, w.a3, 64, w.a1, 16, H, W, B, w.cat);
+            NET_HIP(hipGetLastError());
+            if ((rc = conv(3, w.cat, H, W, w.a4, 32, 0, true))) return rc;
+        } else {
+            if ((rc = conv_rows(3, false, w.a3, H, W, prm + s.L[3].b, w.a4, 32, 0, true, w.a1, 16))) return rc;
+        }
         if ((rc = conv(4, w.a4, H, W, w.z, 6, 0, false))) return rc;
-        hipLaunchKernelGGL(gpool_kernel, dim3(B, 64), dim3(kT), 0, st, w.a3, (size_t)h2 * w2, 64, w.g);
-        NET_HIP(hipGetLastError());
-        return ABC_OK;
+        return colsum(w.a3, (size_t)h2 * w2, 64, B, 1.0f / (float)((size_t)h2 * w2), w.g);
     }
 };
 
@@ -593,7 +722,7 @@ int abc_wsnet_forward(const float* params, const float* x, int B, int H, int W, 
     net.W = W;
     net.st = (hipStream_t)stream;
     net.prm = params;
-    if ((rc = net.forward(x))) return rc;
+    if ((rc = net.forward(x, false))) return rc;
     const size_t P = (size_t)B * H * W;
     hipLaunchKernelGGL(mu_head_kernel, dim3(nb(P)), dim3(kT), 0, net.st, net.w.z, nullptr, P, 0.0f, mu0, nullptr,
                        nullptr);
@@ -635,7 +764,7 @@ int abc_wsnet_loss_grad(const float* params, const float* x, const float* mu_t, 
     const NetShape& s = net.s;
     const int h2 = H / 2, w2 = W / 2;
     const size_t P = (size_t)B * H * W, P2 = P / 4;
-    if ((rc = net.forward(x))) return rc;
+    if ((rc = net.forward(x, true))) return rc;
     // normalised control targets e* = (eps* - eps_min) / (eps_max - eps_min), staged through w.e's tail
     std::vector<float> et((size_t)B * s.nout);
     NET_HIP(hipMemcpyAsync(et.data(), eps_t, et.size() * sizeof(float), hipMemcpyDeviceToHost, st));
