@@ -4,6 +4,7 @@
 // of Alg. 1).  Decisions of the line search are taken in FP64 on the host from
 // FP32 device reductions.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <array>
@@ -35,6 +36,15 @@ int fail(int code, const std::string& msg) {
         if (e_ != hipSuccess)                                                                  \
             return fail(ABC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
     } while (0)
+
+// A named range on the profiler's marker trace (rocprofv3 --marker-trace) for the
+// lifetime of the object; without a profiler the calls return at once.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 constexpr size_t kAlign = 256;
 
@@ -543,6 +553,7 @@ int abc_workspace_bytes(int kind, int H, int W, int C, const abc_params* p, size
 
 int abc_forward_dynamics(const float* c0, int H, int W, int C, const float* eps, const abc_params* p, float* traj,
                          void* ws, size_t ws_bytes, void* stream) {
+    Range range("abc_forward_dynamics");
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
@@ -611,6 +622,7 @@ namespace {
 
 int adjoint_dynamics_impl(const float* traj, int H, int W, int C, const float* eps, const abc_params* p,
                           const float* gK, float* g0, float* geps, void* ws, size_t ws_bytes, void* stream) {
+    Range range("abc_adjoint_dynamics");
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
@@ -716,6 +728,7 @@ int abc_pd_step(const float* cK, const float* c0, int H, int W, int C, const abc
 
 int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* eps, float* mu, float* v_out,
               float* c_out, void* ws, size_t ws_bytes, void* stream, abc_stats* stats, abc_solve_log* log) {
+    Range range("abc_solve");
     int rc = check_params(p);
     if (rc) return rc;
     if ((rc = check_shape(H, W, C))) return rc;
@@ -815,6 +828,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     // Armijo trial into buffer `trial`: eps(tau), forward sweep, Phi(tau), test.
     double K_try = 0.0;  // TV energy of the last trial's final field
     auto run_trial = [&](const std::vector<double>& G, double tau, double phi0, double* phit, bool* ok) -> int {
+        Range trial_range("Armijo trial");
         project(G, tau, e_try);
         int r2 = upload(e_try, w.eps[trial]);
         if (r2) return r2;
@@ -862,7 +876,9 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     const int n_outer = quad ? std::min(M, 1) : (done0 ? 0 : M);
     if (done0) E = E0;
     for (int j = 0; j < n_outer; ++j) {
+        Range outer_range("multiplier iteration");
         for (int it = 0; it < P; ++it) {
+            Range inner_range("DAL iteration");
             const size_t slot = (size_t)j * P + it;
             // terminal condition and objective at the accepted controls, queued; read
             // together with the control gradient after the adjoint sweep
@@ -1610,6 +1626,7 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
 
 int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, void* ws, size_t ws_bytes,
                       void* stream, abc_stats* st, double* finish_ms, const abc_solve_log* logs) {
+    Range range("abc_solve_batched");
     int rc = check_params(p);
     if (rc) return rc;
     if (p->R < 0 || p->R > ABC_MAX_RADIUS) return fail(ABC_EINVAL, "the batched solve takes R in [0, 16]");
@@ -1768,6 +1785,7 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
     };
     std::vector<double> phi_s, K_s;
     for (;;) {
+        Range round_range("batched round");
         std::vector<int> act = in_phase(kPhGrad);
         std::vector<int> search = in_phase(kPhSearch);
         std::vector<int> pdset = in_phase(kPhPd);
