@@ -205,24 +205,44 @@ __global__ void __launch_bounds__(64) conv3x3_wgrad_kernel(const float* __restri
     const int q_begin = blockIdx.x * kChunk;
     const int q_end = min(q_begin + kChunk, B * HW);
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    // the lane's pixel q0 + kg as (image b, row y, column x), advanced by 32 pixels per
+    // step and by one pixel within a step without divisions
+    int qs = q_begin + kg;
+    int b = qs / HW, p = qs - b * HW;
+    int y = p / W, x = p - y * W;
     for (int q0 = q_begin; q0 < q_end; q0 += 32) {
         bf16x8 a, g;
+        int bj = b, yj = y, xj = x;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int q = q0 + kg + j;
             float xv = 0.0f, gv = 0.0f;
             if (q < q_end) {
-                const int b = q / HW, p = q - (q / HW) * HW;
-                const int y = p / W, x = p - (p / W) * W;
-                const int yy = y + dy, xx = x + dx;
+                const int yy = yj + dy, xx = xj + dx;
                 if (krow < Ktot && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
-                    xv = X[(((size_t)b * H + yy) * W + xx) * Cin + ci];
+                    xv = X[(((size_t)bj * H + yy) * W + xx) * Cin + ci];
                 if (col < Cout) gv = dY[(size_t)q * Cout + col];
             }
             a[j] = (__bf16)xv;
             g[j] = (__bf16)gv;
+            if (++xj == W) {
+                xj = 0;
+                if (++yj == H) {
+                    yj = 0;
+                    ++bj;
+                }
+            }
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, g, acc, 0, 0, 0);
+        // advance the step's first pixel by 32 (at most 32 rows at W = 1)
+        x += 32;
+        while (x >= W) {
+            x -= W;
+            if (++y == H) {
+                y = 0;
+                ++b;
+            }
+        }
     }
     if (col >= Cout) return;
 #pragma unroll
