@@ -162,3 +162,26 @@ def test_autotuned_batch_equals_a_solve_with_the_tuned_tiles():
     torch.cuda.synchronize()
     for i in range(len(imgs)):
         assert torch.equal(a[i], b[i]) and torch.equal(again[i], b[i]), i
+
+
+def test_full_batch_in_the_bench_configuration_equals_sampled_solves():
+    """The 64-image batch at its full size (sides 128-1024, 20 Mpx, R = 5, K = 50,
+    5 x 10 schedule) in the configuration the batched line times (persistent
+    sweeps, tuned tiles): the smallest, the largest and a middle image equal their
+    own abc_solve bit for bit, with the same iteration counts."""
+    from paper_2510_16154_amd.workloads import BATCH64 as wb
+    print("[case] full 64-image batch, persistent and tuned", flush=True)
+    host = wb.images()
+    imgs = [T(x) for x in host]
+    gp = wb.params(flags=A.ABC_FLAG_PERSISTENT | A.ABC_FLAG_AUTOTUNE)
+    outs, stats, fin = A.abc_solve_batched(imgs, gp)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(fin)) and np.all(fin > 0)
+    sizes = [x.shape[0] * x.shape[1] for x in host]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), len(host) // 2})
+    for i in picks:
+        print(f"[case] image {i} of the batch, {host[i].shape}", flush=True)
+        ref = A.abc_solve(imgs[i], wb.params())
+        assert torch.equal(outs[i], ref["c"]), i
+        for key in ("K", "L", "r_rel", "inner_iters", "ls_evals", "outer_iters"):
+            assert stats[i][key] == ref["stats"][key], (i, key)
