@@ -340,7 +340,7 @@ def time_to_converged(c0, wl, oracle_sweep_s, tol_dal: float, with_oracle: bool)
         finally:
             O.set_num_threads(n_all)
     out["cfg0"] = cfg0
-    out["warm_start"] = warm_start_rows(2)
+    out["warm_start"] = warm_start_rows(4)
     return out
 
 
