@@ -45,10 +45,11 @@ extern "C" {
 #define ABC_ENOCONV 1       /* warning: caps reached before tol_alm; outputs valid */
 
 #define ABC_MAX_CHANNELS 64
-/* Largest window radius of the LDS-tiled interaction kernels.  Larger radii
- * (up to ABC_MAX_DIRECT_RADIUS) run direct kernels that read each pixel's
- * window from global memory: O(N (2R+1)^2) work per step, meant for small
- * images, among them the un-windowed sum of eq. MAsystem (a window that
+/* Radius up to which a tile must fit the LDS (ABC_EINVAL otherwise).  Past it
+ * (up to ABC_MAX_DIRECT_RADIUS) a tile whose halo still fits runs the LDS-tiled
+ * kernels, and one whose halo does not runs direct kernels that read each
+ * pixel's window from global memory: O(N (2R+1)^2) work per step, meant for
+ * small images, among them the un-windowed sum of eq. MAsystem (a window that
  * covers the image, with s = 1/N). */
 #define ABC_MAX_RADIUS 16
 #define ABC_MAX_DIRECT_RADIUS 32767

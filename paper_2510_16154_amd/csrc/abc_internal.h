@@ -75,8 +75,13 @@ int rows_per_thread(int C, int R);
 
 // True when the (C, R, tile) combination fits the hardware limits: ty a
 // multiple of rows_per_thread, a whole number of 64-lane waves, at most 256
-// threads (1024 for the wide kernels) and the LDS budget.
+// threads (1024 for the wide kernels) and the LDS budget (past ABC_MAX_RADIUS a
+// tile whose halo does not fit runs the direct kernels instead).
 bool tile_ok(int C, int R, Tile t, int fields);
+
+// True when a step of radius R with this tile runs the direct kernels: R past
+// ABC_MAX_RADIUS and the tile's halo too large for the LDS.
+bool direct_step(int C, int R, Tile t, int fields);
 
 // One explicit Euler step of the agent dynamics: cout = cin + dts * F(cin, eps^k).
 // eps points to the K x 2 device control array; step k reads eps[2k], eps[2k+1].

@@ -582,8 +582,8 @@ adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 }
 
 // ----------------------------------------------------------------------------
-// Direct interaction steps, for radii beyond the tiled kernels' halos
-// (R > ABC_MAX_RADIUS) up to the whole image: with R at least the support
+// Direct interaction steps, for radii past ABC_MAX_RADIUS whose tile halo no
+// longer fits the LDS, up to the whole image: with R at least the support
 // radius of eq. kernel (r_ij <= 1 needs eps_x/2 |x_j - x_i|^2 <= 1), or R
 // covering the image and s = 1/N, the window sum is the un-windowed sum of
 // eq. MAsystem.  Same grid and partial slots as the tiled kernels (NP pixels
@@ -1585,7 +1585,7 @@ hipError_t adj_direct_launch(const float* c, const float* pin, float* pout, cons
 template <int CP>
 hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
                         float dts, Tile t, hipStream_t s) {
-    if (R > ABC_MAX_RADIUS) return fwd_direct_launch<CP>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+    if (direct_step(C, R, t, 1)) return fwd_direct_launch<CP>(cin, cout, eps, k, H, W, C, R, dts, t, s);
     if constexpr (CP <= 4) {
         switch (R) {
             case 1: return fwd_launch_t<CP, 1>(cin, cout, eps, k, H, W, C, R, dts, t, s);
@@ -1609,7 +1609,7 @@ hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, 
 template <int CP>
 hipError_t adj_launch_r(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
                         int C, int R, float dts, Tile t, double* part, hipStream_t s) {
-    if (R > ABC_MAX_RADIUS) return adj_direct_launch<CP>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+    if (direct_step(C, R, t, 2)) return adj_direct_launch<CP>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
     if constexpr (CP <= 4) {
         switch (R) {
             case 1: return adj_launch_t<CP, 1>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
@@ -1719,7 +1719,6 @@ int wide_lanes(int C, int R) {
 size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     const int cp = padded_channels(C);
     if (cp < 0) return (size_t)-1;
-    if (R > ABC_MAX_RADIUS) return 0;  // the direct kernels stage nothing
     const int G = wide_lanes(C, R);
     if (G > 1) return (size_t)fields * G * wide_plane_floats(t.tx + 2 * R, t.ty + 2 * R) * sizeof(float);
     const int nv = (cp + 1 + 3) / 4;
@@ -1741,7 +1740,11 @@ bool tile_ok(int C, int R, Tile t, int fields) {
     const int threads = t.tx * (t.ty / NP) * G;
     if (threads > (G > 1 ? kMaxWideThreads : kMaxThreads)) return false;
     if (threads % kWave != 0) return false;
-    return tile_lds_bytes(C, R, t, fields) <= kMaxLds;
+    return tile_lds_bytes(C, R, t, fields) <= kMaxLds || R > ABC_MAX_RADIUS;
+}
+
+bool direct_step(int C, int R, Tile t, int fields) {
+    return R > ABC_MAX_RADIUS && tile_lds_bytes(C, R, t, fields) > kMaxLds;
 }
 
 // Waves one CU can hold for a tile, limited by LDS and by 8 waves per SIMD.

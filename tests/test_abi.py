@@ -110,7 +110,8 @@ def test_support_radius_on_the_host():
         with pytest.raises(A.AbcError) as e:
             A.abc_support_radius(*bad)
         assert e.value.code == A.ABC_EINVAL
-    # the support mode sizes workspaces as the radius it resolves to; radii past 16 stage nothing
+    # the support mode sizes workspaces as the radius it resolves to; a tile too large for the LDS past radius 16
+    # runs the direct kernels
     p = A.Params(K=4, R=A.ABC_RADIUS_SUPPORT, eps_min=(20.0, 2.0))
     for kind in (A.ABC_WS_SOLVE, A.ABC_WS_ADJOINT):
         assert A.abc_workspace_bytes(kind, 40, 56, 3, p) == A.abc_workspace_bytes(kind, 40, 56, 3, p.replace(R=18))
