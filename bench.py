@@ -45,7 +45,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "3fe76b25c4648403a9ae9bad0063d4537c33d02600f8c8005454a59029d27760",
+    "kernel_sha256": "cefa489ae354ff4f3a8efb8a16616bc868a5a3a8482889c92c3654c2f28759f8",
     "adj_step_kernel<3,5>": 11.51e6,
     "adj_step_wide_kernel<31,2>": 1607.64e6,
 }
