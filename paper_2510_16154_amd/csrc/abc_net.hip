@@ -17,7 +17,7 @@
 // e* = (eps* - eps_min) / (eps_max - eps_min).
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16.  A workgroup of four
-// wavefronts owns a 16 x 4 pixel tile and every output channel: the 6 x 18 pixel input
+// wavefronts owns a 16 x 8 pixel tile and every output channel: the 10 x 18 pixel input
 // patch is staged in LDS as BF16 with the channels padded to a multiple of 8, so that
 // the 8 k of an A fragment (8 channels of one tap) are one 16-byte LDS read, and the
 // weights are laid out once per call as BF16 rows WT[n][k] (k = tap x padded channels,

@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["voronoi_image", "voronoi_labels", "batch_shapes", "wsnet_init"]
+__all__ = ["voronoi_image", "voronoi_labels", "batch_shapes", "wsnet_init", "hashed_block", "patched_block"]
 
 
 def _nearest_site(H: int, W: int, sites: np.ndarray) -> np.ndarray:
@@ -123,3 +123,52 @@ def wsnet_init(K: int, seed: int) -> np.ndarray:
     parts.append(rng.normal(0.0, 0.125, size=64 * 2 * K))
     parts.append(np.zeros(2 * K))
     return np.concatenate(parts).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Images too large to hold on the host (up to 4e9 elements): every element is a
+# function of its index, so any rectangle can be made on its own, on the GPU for
+# the whole image or on the CPU for a small crop, with the same bits.
+#   element (y, x, ch) of an image W wide with C channels has index
+#   e = (y W + x) C + ch;  u = hash32(lo32(e) ^ hash32(hi32(e) + seed)) >> 8, a
+#   24-bit integer, and the value is lo + (hi - lo) u / 2^24 in FP32.
+# hash32 is the two-round xor-shift-multiply integer mixer (multiplier 0x45d9f3b),
+# evaluated in int64 with every product below 2^63, so CPU and GPU agree exactly.
+
+_MASK32 = 0xFFFFFFFF
+
+
+def _hash32(x):
+    x = ((x >> 16) ^ x) * 0x45D9F3B & _MASK32
+    x = ((x >> 16) ^ x) * 0x45D9F3B & _MASK32
+    return (x >> 16) ^ x
+
+
+def hashed_block(y0: int, h: int, x0: int, w: int, W: int, C: int, seed: int, lo: float = -1.0, hi: float = 1.0,
+                 device="cpu"):
+    """Rows y0..y0+h-1, columns x0..x0+w-1 (all channels) of the hashed image
+    of width W: an ``h x w x C`` FP32 torch tensor on ``device`` with values in
+    [lo, hi)."""
+    import torch
+    ys = torch.arange(y0, y0 + h, dtype=torch.int64, device=device).view(h, 1, 1)
+    xs = torch.arange(x0, x0 + w, dtype=torch.int64, device=device).view(1, w, 1)
+    cs = torch.arange(C, dtype=torch.int64, device=device).view(1, 1, C)
+    e = (ys * W + xs) * C + cs
+    u = _hash32((e & _MASK32) ^ _hash32((e >> 32) + (seed & _MASK32))) >> 8
+    return (lo + (hi - lo) * (u.to(torch.float64) / float(1 << 24))).to(torch.float32)
+
+
+def patched_block(y0: int, h: int, x0: int, w: int, W: int, C: int, seed: int, patches, background: float = 0.5,
+                  amp: float = 0.5, device="cpu"):
+    """The same rectangle of an image that is ``background`` everywhere except in
+    the square patches ``(py, px, side)``, where it takes the hashed values in
+    [background - amp, background + amp) (``hashed_block`` with ``seed``)."""
+    import torch
+    out = torch.full((h, w, C), background, dtype=torch.float32, device=device)
+    for py, px, side in patches:
+        ya, yb = max(py, y0), min(py + side, y0 + h)
+        xa, xb = max(px, x0), min(px + side, x0 + w)
+        if ya < yb and xa < xb:
+            out[ya - y0:yb - y0, xa - x0:xb - x0] = hashed_block(ya, yb - ya, xa, xb - xa, W, C, seed, background - amp,
+                                                                 background + amp, device)
+    return out
