@@ -317,8 +317,9 @@ typedef struct abc_image {
 int abc_autotune(const float* c0, int H, int W, int C, abc_params* p, const char* cache_path, void* ws,
                  size_t ws_bytes, void* stream, double* best_us);
 
-/* Bytes of device workspace abc_solve_batched needs for n images of sizes
- * H[i] x W[i] x C.  Host only. */
+/* Bytes of device workspace abc_solve_batched needs for n >= 1 images of
+ * sizes H[i] x W[i] x C (ABC_EINVAL for n < 1 or a shape abc_solve would
+ * reject).  Host only. */
 int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C, const abc_params* p,
                                 size_t* bytes);
 
@@ -339,8 +340,9 @@ int abc_workspace_bytes_batched(const int32_t* H, const int32_t* W, int n, int C
  *   logs: host array of n record / replay logs, one per image, with the
  *     meaning and sizes abc_solve gives them (may be NULL, and so may each
  *     array in them); outer_out's times are ms since this call began.
- * Returns ABC_OK, or ABC_ENOCONV when some image did not reach tol_alm.
- * Synchronises the stream before returning. */
+ * Returns ABC_OK, or ABC_ENOCONV when some image did not reach tol_alm;
+ * ABC_EINVAL before any launch for n < 1, a NULL imgs, or an image whose
+ * shape abc_solve would reject.  Synchronises the stream before returning. */
 int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, void* ws, size_t ws_bytes,
                       void* stream, abc_stats* st, double* finish_ms, const abc_solve_log* logs);
 

@@ -98,6 +98,20 @@ def test_null_pointers_are_rejected():
     assert L.abc_pd_step(None, None, 8, 8, 3, ct.byref(p), None, None, 1, None, None, 0, None) == A.ABC_EINVAL
 
 
+def test_batched_entry_points_reject_an_empty_batch_and_bad_images():
+    L = B.lib()
+    p = A.Params(K=4, R=2).to_c()
+    nb = ct.c_size_t(0)
+    H, W = (ct.c_int32 * 1)(8), (ct.c_int32 * 1)(8)
+    assert L.abc_workspace_bytes_batched(H, W, 0, 3, ct.byref(p), ct.byref(nb)) == A.ABC_EINVAL
+    assert L.abc_solve_batched(None, 0, 3, ct.byref(p), None, 0, None, None, None, None) == A.ABC_EINVAL
+    assert "n >= 1" in L.abc_last_error().decode()
+    for shapes in ([(32, 32), (0, 8)], [(32, 32), (8, -1)], [(70000, 70000)]):
+        with pytest.raises(A.AbcError) as e:
+            A.abc_workspace_bytes_batched(shapes, 3, A.Params(K=4, R=2))
+        assert e.value.code == A.ABC_EINVAL
+
+
 def test_support_radius_on_the_host():
     # R* = min(ceil(sqrt(2 / eps_x_min) max(H, W)), max(H, W) - 1)
     assert A.abc_support_radius(512, 512, 1100.0) == 22  # 21.83 rounded up
