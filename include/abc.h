@@ -354,7 +354,9 @@ int abc_solve_batched(const abc_image* imgs, int n, int C, const abc_params* p, 
  *   3->16 (full res), 2x2 average pool, 16->32, 32->64 (half res),
  *   2x nearest upsample concatenated with the first layer's output (80),
  *   80->32, 32->6 (full res); mu0 = z / max(1, |z|);
- *   eps0 = eps_min + (eps_max - eps_min) sigmoid(Wl mean(64-ch features) + bl).
+ *   eps0 = eps_min (eps_max / eps_min)^e, e = sigmoid(Wl mean(64-ch features) + bl)
+ *   (the box E read on a log scale; calls return ABC_EINVAL unless
+ *   0 < eps_min <= eps_max < inf).
  * Weights are an FP32 blob (layout: per conv layer W[9 Cin][Cout] with row
  * (kh*3 + kw)*Cin + ci, then b[Cout]; then Wl[64][2K], bl[2K]).  Convolutions
  * run as BF16 x BF16 -> FP32 on the matrix cores (operands rounded to BF16).
@@ -371,8 +373,11 @@ int abc_wsnet_forward(const float* params, const float* x, int B, int H, int W, 
                       float* mu0, float* eps0, void* ws, size_t ws_bytes, void* stream);
 
 /* Loss = mean_pixels |mu0 - mu_t|^2 + w_eps mean (e - e_t)^2 (e, e_t the controls
- * mapped to [0,1] by E) and its gradient in the parameters (grad, same layout
- * as params; overwritten).  loss (host) may be NULL; otherwise synchronises. */
+ * mapped to [0,1] by E on a log scale: e_t = log(eps_t / eps_min) /
+ * log(eps_max / eps_min)) and its gradient in the parameters (grad, same
+ * layout as params; overwritten).  Every eps_t must be positive and finite
+ * (ABC_EINVAL before any launch).  loss (host) may be NULL; otherwise
+ * synchronises. */
 int abc_wsnet_loss_grad(const float* params, const float* x, const float* mu_t, const float* eps_t, int B, int H,
                         int W, int K, const abc_params* p, float w_eps, float* grad, double* loss, void* ws,
                         size_t ws_bytes, void* stream);

@@ -89,9 +89,10 @@ def forward(params, x, K, eps_min, eps_max, bf16=True):
     mu = z / np.maximum(1.0, nz)
     g = a3.mean(axis=(1, 2))
     e = 1.0 / (1.0 + np.exp(-(g @ Wl + bl)))
+    # the box E on a log scale: eps = eps_min (eps_max / eps_min)^e
     lo = np.tile(np.asarray(eps_min, dtype=np.float64), K)
     hi = np.tile(np.asarray(eps_max, dtype=np.float64), K)
-    eps = lo + (hi - lo) * e
+    eps = lo * np.exp(e * np.log(hi / lo))
     cache = dict(x=x, a1=a1, p1=p1, a2=a2, a3=a3, cat=cat, a4=a4, z=z, nz=nz, mu=mu, g=g, e=e, lo=lo, hi=hi)
     return mu, eps.reshape(-1, K, 2), cache
 
@@ -103,7 +104,7 @@ def loss_grad(params, x, mu_t, eps_t, K, eps_min, eps_max, w_eps, bf16=True):
     r = bf16_round if bf16 else (lambda a: a)
     B, H, W, _ = c["x"].shape
     P = B * H * W
-    et = (np.asarray(eps_t, dtype=np.float64).reshape(B, 2 * K) - c["lo"]) / (c["hi"] - c["lo"])
+    et = np.log(np.asarray(eps_t, dtype=np.float64).reshape(B, 2 * K) / c["lo"]) / np.log(c["hi"] / c["lo"])
     diff = mu - np.asarray(mu_t, dtype=np.float64)
     loss = np.sum(diff ** 2) / P + w_eps * np.mean((c["e"] - et) ** 2)
     grads = [None] * 5, [None] * 5

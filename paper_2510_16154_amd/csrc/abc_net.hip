@@ -12,9 +12,10 @@
 //   z  = conv3x3(a4; 32 -> 6)                       H   x W
 //   mu0 = z / max(1, |z|)      (per pixel, the 6 = 2 x 3 components: inside the unit ball)
 //   e  = sigmoid(Wl mean(a3) + bl)                  per image, 2K values
-//   eps0 = eps_min + (eps_max - eps_min) e
+//   eps0 = eps_min (eps_max / eps_min)^e            (E on a log scale: solved controls span
+//                                                    orders of magnitude inside [2, 1100])
 // Loss per batch: mean over pixels of |mu0 - mu*|^2 + w_eps * mean over (image, k, m) of (e - e*)^2,
-// e* = (eps* - eps_min) / (eps_max - eps_min).
+// e* = log(eps* / eps_min) / log(eps_max / eps_min).
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16.  A workgroup of four
 // wavefronts owns a 16 x 8 pixel tile and every output channel: the 10 x 18 pixel input
@@ -604,6 +605,26 @@ int check_net_args(int B, int H, int W, int K) {
     return ABC_OK;
 }
 
+// The control head reads the box E on a log scale, so it needs 0 < eps_min <= eps_max.
+int check_box(const abc_params* p) {
+    for (int m = 0; m < 2; ++m)
+        if (!(p->eps_min[m] > 0.0f) || !(p->eps_max[m] >= p->eps_min[m]) || !std::isfinite(p->eps_max[m]))
+            return nfail(ABC_EINVAL, "the control head needs a box with 0 < eps_min <= eps_max < inf");
+    return ABC_OK;
+}
+
+// eps0 = eps_min (eps_max / eps_min)^e, per component m = i % 2 (in double on the host).
+float box_from_unit(const abc_params* p, int m, float e) {
+    const double lo = p->eps_min[m], hi = p->eps_max[m];
+    return (float)(lo * std::exp((double)e * std::log(hi / lo)));
+}
+
+// e* = log(eps* / eps_min) / log(eps_max / eps_min) (0 for a box of one point).
+float unit_from_box(const abc_params* p, int m, float eps) {
+    const double lo = p->eps_min[m], hi = p->eps_max[m];
+    return hi > lo ? (float)(std::log((double)eps / lo) / std::log(hi / lo)) : 0.0f;
+}
+
 struct Net {
     NetShape s;
     NetWs w;
@@ -732,6 +753,7 @@ int abc_wsnet_forward(const float* params, const float* x, int B, int H, int W, 
     int rc = check_net_args(B, H, W, K);
     if (rc) return rc;
     if (!params || !x || !p || !mu0 || !eps0) return nfail(ABC_EINVAL, "params, x, p, mu0, eps0 must be non-NULL");
+    if ((rc = check_box(p))) return rc;
     Net net;
     net.s = net_shape(K);
     if (!ws || ws_bytes < carve_net(nullptr, B, H, W, net.s, false).used)
@@ -750,14 +772,11 @@ int abc_wsnet_forward(const float* params, const float* x, int B, int H, int W, 
     hipLaunchKernelGGL(eps_head_kernel, dim3(B), dim3(kT), 0, net.st, net.w.g, 64, params + net.s.wl, params + net.s.bl,
                        net.s.nout, nullptr, 0.0f, net.w.e, nullptr, nullptr, nullptr, nullptr);
     NET_HIP(hipGetLastError());
-    // eps0 = eps_min + (eps_max - eps_min) e, on the host side of the tiny array
+    // eps0 = eps_min (eps_max / eps_min)^e, on the host side of the tiny array
     std::vector<float> e((size_t)B * net.s.nout);
     NET_HIP(hipMemcpyAsync(e.data(), net.w.e, e.size() * sizeof(float), hipMemcpyDeviceToHost, net.st));
     NET_HIP(hipStreamSynchronize(net.st));
-    for (size_t i = 0; i < e.size(); ++i) {
-        const int m = (int)(i % 2);
-        e[i] = p->eps_min[m] + (p->eps_max[m] - p->eps_min[m]) * e[i];
-    }
+    for (size_t i = 0; i < e.size(); ++i) e[i] = box_from_unit(p, (int)(i % 2), e[i]);
     NET_HIP(hipMemcpyAsync(eps0, e.data(), e.size() * sizeof(float), hipMemcpyHostToDevice, net.st));
     NET_HIP(hipStreamSynchronize(net.st));
     return ABC_OK;
@@ -769,15 +788,25 @@ int abc_wsnet_loss_grad(const float* params, const float* x, const float* mu_t, 
     int rc = check_net_args(B, H, W, K);
     if (rc) return rc;
     if (!params || !x || !mu_t || !eps_t || !p || !grad) return nfail(ABC_EINVAL, "null argument");
+    if ((rc = check_box(p))) return rc;
     Net net;
     net.s = net_shape(K);
     if (!ws || ws_bytes < carve_net(nullptr, B, H, W, net.s, true).used)
         return nfail(ABC_EINVAL, "wsnet workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    // normalised control targets e* = log(eps* / eps_min) / log(eps_max / eps_min), checked
+    // before anything is launched
+    std::vector<float> et((size_t)B * net.s.nout);
+    NET_HIP(hipMemcpyAsync(et.data(), eps_t, et.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    NET_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < et.size(); ++i) {
+        if (!(et[i] > 0.0f) || !std::isfinite(et[i])) return nfail(ABC_EINVAL, "control targets must be positive");
+        et[i] = unit_from_box(p, (int)(i % 2), et[i]);
+    }
     net.w = carve_net(ws, B, H, W, net.s, true);
     net.B = B;
     net.H = H;
     net.W = W;
-    hipStream_t st = (hipStream_t)stream;
     net.st = st;
     net.prm = params;
     const NetWs& w = net.w;
@@ -785,15 +814,6 @@ int abc_wsnet_loss_grad(const float* params, const float* x, const float* mu_t, 
     const int h2 = H / 2, w2 = W / 2;
     const size_t P = (size_t)B * H * W, P2 = P / 4;
     if ((rc = net.forward(x, true))) return rc;
-    // normalised control targets e* = (eps* - eps_min) / (eps_max - eps_min), staged through w.e's tail
-    std::vector<float> et((size_t)B * s.nout);
-    NET_HIP(hipMemcpyAsync(et.data(), eps_t, et.size() * sizeof(float), hipMemcpyDeviceToHost, st));
-    NET_HIP(hipStreamSynchronize(st));
-    for (size_t i = 0; i < et.size(); ++i) {
-        const int m = (int)(i % 2);
-        const float span = p->eps_max[m] - p->eps_min[m];
-        et[i] = span > 0.0f ? (et[i] - p->eps_min[m]) / span : 0.0f;
-    }
     // heads with targets; the normalised control targets are staged in dcat, which stays
     // free until the data gradient of layer 4 (stream order: the head reads them first)
     const float mu_scale = 1.0f / (float)P;

@@ -43,9 +43,15 @@ def main(argv=None):
     ap.add_argument("--target-inner", type=int, default=10, help="DAL iterations per multiplier iteration")
     ap.add_argument("--target-tol-alm", type=float, default=0.0,
                     help="ALM residual stop of the target solves (0: run --target-outer iterations)")
+    ap.add_argument("--target-tol-gap", type=float, default=0.0,
+                    help="Lagrangian-gap stop of the target solves (0: off); with --target-outer 20 and "
+                         "--target-inner 10 the targets come from the evaluation's own stopping rule")
+    ap.add_argument("--solve-batch", type=int, default=64, help="images per batched target solve")
     ap.add_argument("--chunk", type=int, default=256, help="images solved per data chunk (one progress line each)")
     ap.add_argument("--warm-eps", action="store_true",
                     help="warm solves start from the predicted controls too (default: predicted multiplier only)")
+    ap.add_argument("--eval-both", action="store_true",
+                    help="also evaluate the other warm-start mode (with / without the predicted controls)")
     args = ap.parse_args(argv)
 
     import torch
@@ -57,7 +63,7 @@ def main(argv=None):
 
     os.makedirs(args.out, exist_ok=True)
     params = B.Params(K=VORONOI512.K, R=VORONOI512.R, max_outer=args.target_outer, max_inner=args.target_inner,
-                      alpha=VORONOI512.alpha, tol_alm=args.target_tol_alm)
+                      alpha=VORONOI512.alpha, tol_alm=args.target_tol_alm, tol_gap=args.target_tol_gap)
     ws = WarmStart(params.K, params, seed=7)
     logs, t_data = [], 0.0
     if args.weights:
@@ -67,7 +73,8 @@ def main(argv=None):
     xs, mus, epss = [], [], []
     chunk = args.chunk
     for s in range(0, args.n_train, chunk):
-        x, mu, eps = make_dataset(min(chunk, args.n_train - s), args.size, args.train_seed + s, params)
+        x, mu, eps = make_dataset(min(chunk, args.n_train - s), args.size, args.train_seed + s, params,
+                                  batch=args.solve_batch)
         xs.append(x)
         mus.append(mu)
         epss.append(eps)
@@ -100,16 +107,28 @@ def main(argv=None):
                      "warm_outer": warm["outer_iters"], "warm_s": warm["seconds"], "warm_K": warm["K"],
                      "fallback": warm["fallback"], "ideal_outer": ideal["outer_iters"], "ideal_s": ideal["seconds"],
                      "ideal_K": ideal["K"], "cold_outer_log": cold["outer_log"]})
+        if args.eval_both:
+            other = ws.solve(img, pe, cold=cold, use_eps=not args.warm_eps)
+            rows[-1].update(other_outer=other["outer_iters"], other_s=other["seconds"], other_K=other["K"],
+                            other_fallback=other["fallback"])
         print(f"[eval] {i + 1}/{args.n_eval} " + json.dumps(rows[-1]), flush=True)
     sp = [r["cold_s"] / r["warm_s"] for r in rows]
     it = [r["cold_outer"] / max(r["warm_outer"], 1) for r in rows]
     summary = {"train": {"n": args.n_train, "size": args.size, "epochs": args.epochs, "batch": args.batch,
-                         "lr": args.lr, "losses": logs, "data_seconds": t_data},
+                         "lr": args.lr, "losses": logs, "data_seconds": t_data,
+                         "targets": {"max_outer": args.target_outer, "max_inner": args.target_inner,
+                                     "tol_alm": args.target_tol_alm, "tol_gap": args.target_tol_gap}},
                "eval": {"n": args.n_eval, "size": args.eval_size, "rows": rows,
                         "speedup_time_median": float(np.median(sp)), "speedup_time_geomean": float(np.exp(np.mean(np.log(sp)))),
                         "speedup_iters_median": float(np.median(it)),
                         "ideal_speedup_time_median": float(np.median([r["cold_s"] / r["ideal_s"] for r in rows])),
                         "fallbacks": int(sum(r["fallback"] for r in rows))}}
+    if args.eval_both:
+        so = [r["cold_s"] / r["other_s"] for r in rows]
+        summary["eval"].update(other_mode="multiplier only" if args.warm_eps else "multiplier and controls",
+                               other_speedup_time_median=float(np.median(so)),
+                               other_speedup_time_geomean=float(np.exp(np.mean(np.log(so)))),
+                               other_fallbacks=int(sum(r["other_fallback"] for r in rows)))
     json.dump(summary, open(os.path.join(args.out, "summary.json"), "w"), indent=1)
     print("[summary] " + json.dumps({k: v for k, v in summary["eval"].items() if k != "rows"}), flush=True)
     return 0

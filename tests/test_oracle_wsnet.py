@@ -73,3 +73,24 @@ def test_mu_head_stays_in_the_unit_ball():
     mu, eps, _ = O.forward(params, x, K, (2.0, 2.0), (1100.0, 1100.0))
     assert np.all(np.sqrt(np.sum(mu ** 2, axis=3)) <= 1.0 + 1e-12)
     assert np.all((eps >= 2.0) & (eps <= 1100.0))
+
+
+def test_control_head_reads_the_box_on_a_log_scale():
+    """With the head's weights at zero, e = sigmoid(b) per output: b = 0 gives the
+    geometric mean of the box, a large |b| its ends; a target at the geometric
+    mean then costs nothing, and one at eps_max costs (1 - 1/2)^2 w_eps."""
+    K = 2
+    x = np.random.default_rng(7).uniform(size=(1, 6, 8, 3))
+    params = wsnet_init(K, 8).astype(np.float64)
+    offs, wl, bl, n = O.layout(K)
+    params[wl:bl] = 0.0
+    lo, hi = (2.0, 3.0), (1100.0, 300.0)
+    for b, want in ((0.0, np.sqrt(np.multiply(lo, hi))), (60.0, np.array(hi)), (-60.0, np.array(lo))):
+        params[bl:n] = b
+        _, eps, _ = O.forward(params, x, K, lo, hi)
+        assert np.allclose(eps.reshape(K, 2), want[None, :], rtol=1e-12)
+    params[bl:n] = 0.0
+    mu, _, _ = O.forward(params, x, K, lo, hi, bf16=False)
+    for eps_t, cost in ((np.sqrt(np.multiply(lo, hi)), 0.0), (np.array(hi), 0.25)):
+        loss, _ = O.loss_grad(params, x, mu, np.tile(eps_t, (1, K, 1)), K, lo, hi, w_eps=0.5, bf16=False)
+        assert loss == pytest.approx(0.5 * cost, abs=1e-12)
