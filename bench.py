@@ -45,8 +45,8 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "cefa489ae354ff4f3a8efb8a16616bc868a5a3a8482889c92c3654c2f28759f8",
-    "adj_step_kernel<3,5>": 11.51e6,
+    "kernel_sha256": "5477ad8bd0a2cf6e933f33901b5c84864d154159667a1913ba3ad00d327fd936",
+    "adj_step_kernel<3,5>": 11.53e6,
     "adj_step_wide_kernel<31,2>": 1607.64e6,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_16154_amd", "csrc", "abc_kernels.hip")
@@ -88,13 +88,15 @@ def main() -> int:
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
                     help="repeat the oracle's full forward+adjoint sweep until this much time has passed")
     ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512", "hyper2048", "warmstart1024", "converge512",
-                             "transfer1024"],
+                             "transfer1024", "quadratic512", "support128"],
                     help="voronoi512: the headline line (default); batch64: the batched form; segment512: "
                          "watershed labels and IRV/IRC/VS scores of a solved 512 x 512 image; hyper2048: the "
                          "differentiable form on 2048 x 2048 x 31 (checkpointed forward + backward); warmstart1024: "
                          "time to a converged solve of held-out 1024 x 1024 images, plain against the packaged "
                          "learned warm start; converge512: time to solve the 512 x 512 image to ALM residual 1e-5; "
-                         "transfer1024: controls of the 512 x 512 solve applied to its 2x finer version")
+                         "transfer1024: controls of the 512 x 512 solve applied to its 2x finer version; "
+                         "quadratic512: the DAL with the quadratic cost J (Def. 3.2) on the 512 x 512 image; "
+                         "support128: the un-windowed sum (window from the kernel's support) on 128 x 128")
     ap.add_argument("--images", type=int, default=4, help="warmstart1024: held-out images to solve")
     ap.add_argument("--no-converge", action="store_true",
                     help="voronoi512: skip the time-to-converged part (converged solves, 32 x 32 solve, warm start)")
@@ -114,7 +116,8 @@ def main() -> int:
     args = ap.parse_args()
     # (steps, warmup) per workload when not given: the longer workloads time whole solves.
     defaults = {"voronoi512": (50, 100), "batch64": (3, 1), "segment512": (20, 3), "hyper2048": (5, 2),
-                "warmstart1024": (0, 1), "converge512": (1, 1), "transfer1024": (20, 5)}
+                "warmstart1024": (0, 1), "converge512": (1, 1), "transfer1024": (20, 5), "quadratic512": (3, 1),
+                "support128": (5, 2)}
     d_steps, d_warm = defaults[args.workload]
     if args.steps is None:
         args.steps = d_steps
@@ -149,6 +152,10 @@ def main() -> int:
         return bench_converge(args)
     if args.workload == "transfer1024":
         return bench_transfer(args)
+    if args.workload == "quadratic512":
+        return bench_quadratic(args)
+    if args.workload == "support128":
+        return bench_support(args)
 
     import paper_2510_16154_amd as A
     from paper_2510_16154_amd.workloads import VORONOI512 as wl
@@ -561,6 +568,129 @@ def bench_transfer(args) -> int:
            "roofline": {"kernel": f"fwd_step_kernel<3,{ph.R if ph.R <= 5 else 0}>", "bound": "alu",
                         "achieved": tflops, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                         "frac": tflops / PEAK_FP32_VALU_TFLOPS, "traffic": None}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_quadratic(args) -> int:
+    """Def. 3.2 with Alg. 1 alone: the direct-adjoint loop with the two-way projected
+    Armijo search on the quadratic cost J, 512 x 512 x 3 bench image, R = 5, K = 50,
+    P = 50 DAL iterations from the cold controls.  One step = one such solve; the
+    value counts its sweeps (one adjoint sweep per DAL iteration, one forward sweep per
+    Armijo trial plus the starting one).  cpu_baseline: the oracle's same solve on the
+    central 256 x 256 crop cut to two DAL iterations, in the same unit."""
+    import torch
+
+    import paper_2510_16154_amd as A
+    from paper_2510_16154_amd.workloads import VORONOI512 as wl
+
+    c0n = wl.image()
+    c0 = torch.as_tensor(c0n, device="cuda")
+    params = wl.params(cost=A.ABC_COST_QUADRATIC, max_outer=1, max_inner=50, tol_alm=0.0)
+    for _ in range(args.warmup):
+        A.abc_solve(c0, params, want_v=False)
+    torch.cuda.synchronize()
+    times, st = [], None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        st = A.abc_solve(c0, params, want_v=False)["stats"]
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    sweeps = st["inner_iters"] + st["ls_evals"] + 1
+    out = {"metric": "agent-steps/sec (DAL, quadratic cost)", "value": wl.H * wl.W * wl.K * sweeps / t,
+           "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic (seeded Voronoi image)",
+           "config": {"workload": "quadratic512_rgb_r5_k50", "H": wl.H, "W": wl.W, "C": wl.C, "R": wl.R,
+                      "K": wl.K, "cost": "quadratic J (Def. 3.2)", "schedule": "P = 50 DAL iterations"},
+           "stats": {k: st[k] for k in ("inner_iters", "ls_evals", "K", "phi_first", "phi_last")},
+           "sweeps_per_solve": sweeps}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        op = O.Params(K=wl.K, R=wl.R, alpha=params.alpha, cost=1, max_outer=1, max_inner=2)
+        crop = np.ascontiguousarray(c0n[128:384, 128:384])
+        t0 = time.perf_counter()
+        ref = O.solve(crop, op)
+        dt = time.perf_counter() - t0
+        rs = ref["stats"]
+        n = rs["inner_iters"] + rs["ls_evals"] + 1
+        out["cpu_baseline"] = {"value": 256 * 256 * wl.K * n / dt, "unit": "agent-steps/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"the same solve on the central 256x256 crop, cut to {rs['inner_iters']} "
+                                         f"DAL iterations ({n} sweeps), FP64, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_support(args) -> int:
+    """eq. MAsystem summed over every pair inside the kernel's support: a 128 x 128 x 3
+    Voronoi image (6 regions, sigma 0.05, seed 1005), R = ABC_RADIUS_SUPPORT with
+    eps_x >= 2, which on this image is R* = 127 (all pairs), s = 1/N; K = 20, controls
+    eps_init.  One step = one forward and one adjoint sweep (HIP events); these radii
+    run the direct kernels.  cpu_baseline: the oracle's forward and adjoint sweeps of
+    the same image cut to 10 Euler steps, in the same unit."""
+    import torch
+
+    import paper_2510_16154_amd as A
+    from paper_2510_16154_amd.synth import voronoi_image
+
+    H = W = 128
+    C, K = 3, 20
+    c0n = voronoi_image(H, W, C, 6, 0.05, 1005)
+    c0 = torch.as_tensor(c0n, device="cuda")
+    params = A.Params(K=K, R=A.ABC_RADIUS_SUPPORT)
+    R = A.abc_support_radius(H, W, params.eps_min[0])
+    eps = torch.full((K, 2), params.eps_init, dtype=torch.float32, device="cuda")
+    gKn = np.random.default_rng(5).normal(size=(H, W, C))
+    gK = torch.as_tensor(gKn.astype(np.float32), device="cuda")
+    traj = torch.empty((K + 1, H, W, C), dtype=torch.float32, device="cuda")
+    ws_a = torch.empty(A.abc_workspace_bytes(A.ABC_WS_ADJOINT, H, W, C, params), dtype=torch.uint8, device="cuda")
+    g0 = torch.empty_like(c0)
+    geps = torch.empty((K, 2), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, adj = [], []
+    for rep in range(args.warmup + args.steps):
+        ev[0].record(stream)
+        A.abc_forward_dynamics(c0, eps, params, traj=traj)
+        ev[1].record(stream)
+        A.abc_adjoint_dynamics(traj, eps, params, gK, g0=g0, geps=geps, ws=ws_a)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        if rep >= args.warmup:
+            fwd.append(ev[0].elapsed_time(ev[1]) * 1e-3)
+            adj.append(ev[1].elapsed_time(ev[2]) * 1e-3)
+    t_f, t_a = float(np.median(fwd)), float(np.median(adj))
+    pairs = window_pairs(H, W, R)
+    adj_flops = pairs * flops_per_pair(C, "adj")
+    achieved = adj_flops * K / t_a / 1e12
+    out = {"metric": "agent-steps/sec (fwd+adjoint, un-windowed sum)", "value": H * W * K / (t_f + t_a),
+           "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": (t_f + t_a) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic (seeded Voronoi image)",
+           "config": {"workload": "support128_rgb_k20", "H": H, "W": W, "C": C, "R": R, "K": K,
+                      "window": "support of eps_x >= 2: every pair", "s": "1/N"},
+           "sweeps": {"fwd_ms": t_f * 1e3, "adj_ms": t_a * 1e3, "pairs_per_step": pairs,
+                      "fwd_tflops": pairs * flops_per_pair(C, "fwd") * K / t_f / 1e12},
+           "roofline": {"kernel": "adj_direct_kernel<3>", "bound": "alu", "achieved": achieved,
+                        "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                        "traffic": None, "flops_per_launch": adj_flops, "launch_ms": t_a / K * 1e3,
+                        "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                        "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS}}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        Ks = 10
+        op = O.Params(K=Ks, R=R, s=1.0 / (H * W))
+        e = np.full((Ks, 2), float(params.eps_init))
+        t0 = time.perf_counter()
+        tr = O.forward_sweep(c0n, op, e)
+        O.adjoint_sweep(tr, op, gKn, e)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": H * W * Ks / dt, "unit": "agent-steps/s", "cores": O.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"forward + adjoint sweep of {Ks} Euler steps of the same image, "
+                                         f"R = {R}, FP64, {dt:.1f} s"}
     print(json.dumps(out), flush=True)
     return 0
 

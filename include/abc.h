@@ -46,11 +46,12 @@ extern "C" {
 
 #define ABC_MAX_CHANNELS 64
 /* Radius up to which a tile must fit the LDS (ABC_EINVAL otherwise).  Past it
- * (up to ABC_MAX_DIRECT_RADIUS) a tile whose halo still fits runs the LDS-tiled
- * kernels, and one whose halo does not runs direct kernels that read each
- * pixel's window from global memory: O(N (2R+1)^2) work per step, meant for
- * small images, among them the un-windowed sum of eq. MAsystem (a window that
- * covers the image, with s = 1/N). */
+ * (up to ABC_MAX_DIRECT_RADIUS) a tile whose halo still leaves 8 waves per CU
+ * runs the LDS-tiled kernels, any other runs direct kernels that split each
+ * 8 x 8 pixel block's window over 4 to 16 waves (the tile's shape then does not
+ * matter): O(N (2R+1)^2) work per step, meant for small images, among them the
+ * un-windowed sum of eq. MAsystem (a window that covers the image, with
+ * s = 1/N). */
 #define ABC_MAX_RADIUS 16
 #define ABC_MAX_DIRECT_RADIUS 32767
 /* abc_params.R value asking for the radius of the kernel's support: the

@@ -303,11 +303,11 @@ SolveWs carve_solve(Carve& cv, const Shape& s, const abc_params* p, int tiles) {
 size_t ws_bytes_for(int kind, const Shape& s, const abc_params* p, const abc::Tile& tf, const abc::Tile& ta) {
     Carve cv(nullptr);
     switch (kind) {
-        case ABC_WS_SOLVE: carve_solve(cv, s, p, abc::tile_count(s.H, s.W, ta)); break;
+        case ABC_WS_SOLVE: carve_solve(cv, s, p, abc::adj_part_count(s.H, s.W, s.C, p->R, ta)); break;
         case ABC_WS_FORWARD:
             if (p->ckpt_every > 0) cv.take<float>(2 * s.field());
             break;
-        case ABC_WS_ADJOINT: carve_adjoint(cv, s, p, abc::tile_count(s.H, s.W, ta)); break;
+        case ABC_WS_ADJOINT: carve_adjoint(cv, s, p, abc::adj_part_count(s.H, s.W, s.C, p->R, ta)); break;
         case ABC_WS_PD: carve_pd(cv, s); break;
         default: return 0;
     }
@@ -637,7 +637,7 @@ int adjoint_dynamics_impl(const float* traj, int H, int W, int C, const float* e
     if (!ws || ws_bytes < need) return fail(ABC_EINVAL, "adjoint workspace too small");
     hipStream_t st = (hipStream_t)stream;
     const size_t f = s.field();
-    const int tiles = abc::tile_count(H, W, ta);
+    const int tiles = abc::adj_part_count(H, W, C, p->R, ta);
     Carve cv(ws);
     AdjointWs w = carve_adjoint(cv, s, p, tiles);
     const float snorm = norm_factor(p, s);
@@ -754,7 +754,7 @@ int abc_solve(const float* c0, int H, int W, int C, const abc_params* p, float* 
     hipStream_t st = (hipStream_t)stream;
     const int K = p->K;
     const size_t f = s.field();
-    const int tiles = abc::tile_count(H, W, ta);
+    const int tiles = abc::adj_part_count(H, W, C, p->R, ta);
     Carve cv(ws);
     SolveWs w = carve_solve(cv, s, p, tiles);
     const float snorm = norm_factor(p, s);

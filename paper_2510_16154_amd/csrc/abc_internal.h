@@ -75,13 +75,21 @@ int rows_per_thread(int C, int R);
 
 // True when the (C, R, tile) combination fits the hardware limits: ty a
 // multiple of rows_per_thread, a whole number of 64-lane waves, at most 256
-// threads (1024 for the wide kernels) and the LDS budget (past ABC_MAX_RADIUS a
-// tile whose halo does not fit runs the direct kernels instead).
+// threads (1024 for the wide kernels) and the LDS budget (past ABC_MAX_RADIUS any
+// such tile: one whose halo does not fit runs the direct kernels instead).
 bool tile_ok(int C, int R, Tile t, int fields);
 
 // True when a step of radius R with this tile runs the direct kernels: R past
-// ABC_MAX_RADIUS and the tile's halo too large for the LDS.
+// ABC_MAX_RADIUS and the tile's halo leaving fewer than 8 waves per CU (none
+// when it does not fit the LDS).
 bool direct_step(int C, int R, Tile t, int fields);
+
+// Workgroups (8 x 8 pixel blocks) of a direct step on an H x W image.
+int direct_blocks(int H, int W);
+
+// Control-gradient partial slots per step of the transposed sweep with adjoint
+// tile t: one per tile, or one per 8 x 8 block when the step runs direct.
+int adj_part_count(int H, int W, int C, int R, Tile t);
 
 // One explicit Euler step of the agent dynamics: cout = cin + dts * F(cin, eps^k).
 // eps points to the K x 2 device control array; step k reads eps[2k], eps[2k+1].

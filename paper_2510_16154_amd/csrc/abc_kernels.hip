@@ -582,63 +582,118 @@ adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 }
 
 // ----------------------------------------------------------------------------
-// Direct interaction steps, for radii past ABC_MAX_RADIUS whose tile halo no
-// longer fits the LDS, up to the whole image: with R at least the support
+// Direct interaction steps, for radii past ABC_MAX_RADIUS whose tile halo leaves
+// fewer than kMinTiledWaves waves per CU (or does not fit the LDS at all), up to
+// the whole image: with R at least the support
 // radius of eq. kernel (r_ij <= 1 needs eps_x/2 |x_j - x_i|^2 <= 1), or R
 // covering the image and s = 1/N, the window sum is the un-windowed sum of
-// eq. MAsystem.  Same grid and partial slots as the tiled kernels (NP pixels
-// per thread); each pixel reads its neighbours straight from global memory (a
-// small image stays in L2), clips its window to the image, which leaves out
-// only zero terms, and sums it in the (a, b) order with the tiled kernels'
-// operations (squares of the offsets taken in float, exact up to 4096 and
-// free of integer overflow for any radius).  O(N (2R+1)^2) work per step:
-// meant for small images.
+// eq. MAsystem.  These are the small images with huge windows, so the work is
+// split over the window as well as over the pixels: a workgroup owns an 8 x 8
+// pixel block (one pixel per lane) and S waves, and walks the block's window
+// (its pixels' windows joined and clipped to the image) in image coordinates,
+// wave s taking source rows r0 + s, r0 + s + S, ...  All lanes of a wave read
+// the same source pixel, so its loads are wave-uniform and come through the
+// scalar cache; each lane zeroes the kernel argument t of sources outside its
+// own window (no test at all when the window covers the image).  Out-of-image
+// neighbours never occur, and the pair (i, i) adds exact zeros.  The waves'
+// sums meet in LDS and are added in wave order, so every sum has a fixed order
+// whatever tile the caller asked for.  O(N (2R+1)^2) work per step.  Gradient
+// partials: part[2 * block + {0, 1}], one slot per 8 x 8 block (direct_blocks).
 template <int CP>
 __device__ __forceinline__ void load_global_px(const float* __restrict__ p, int C, float (&v)[CP]) {
+    // C == CP for 1 to 4 and 31 channels (the padded counts of those); otherwise no
+    // branch: channels past C reread the last one and are replaced by 0
+    constexpr bool kExact = CP <= 4 || CP == 31;
 #pragma unroll
-    for (int ch = 0; ch < CP; ++ch) v[ch] = ch < C ? p[ch] : 0.0f;
+    for (int ch = 0; ch < CP; ++ch) {
+        const float x = p[kExact ? ch : min(ch, C - 1)];
+        v[ch] = kExact || ch < C ? x : 0.0f;
+    }
 }
 
+constexpr int kDirectB = 8;
+
 template <int CP>
-__global__ void __launch_bounds__(kMaxThreads)
+struct Direct {
+    static constexpr int S = CP <= 8 ? 16 : (CP <= 16 ? 8 : 4);  // waves per workgroup
+};
+
+// Adds each lane's v[0..N) over the S waves in wave order; the sums end in wave 0.
+// red: S x 64 float4 of LDS.
+template <int N, int S>
+__device__ __forceinline__ void direct_wave_sum(float (&v)[N], float4* red) {
+    const int lane = threadIdx.x, s = threadIdx.y;
+#pragma unroll
+    for (int q0 = 0; q0 < N; q0 += 4) {
+        float x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = q0 + i < N ? v[q0 + i] : 0.0f;
+        if (s > 0) red[s * kWave + lane] = make_float4(x[0], x[1], x[2], x[3]);
+        __syncthreads();
+        if (s == 0) {
+            for (int w = 1; w < S; ++w) {
+                const float4 y = red[w * kWave + lane];
+                x[0] += y.x;
+                x[1] += y.y;
+                x[2] += y.z;
+                x[3] += y.w;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (q0 + i < N) v[q0 + i] = x[i];
+        }
+        __syncthreads();
+    }
+}
+
+template <int CP, bool MASK>
+__global__ void __launch_bounds__(kWave * Direct<CP>::S)
 fwd_direct_kernel(const float* __restrict__ cin, float* __restrict__ cout, const float* __restrict__ eps, int k,
-                  int H, int W, int C, int R, int tiles_x, int tiles_y, float dts, float dx2, float dy2) {
-    constexpr int NP = RowsPerThread<CP>::value;
-    int tcol, trow;
-    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
-    const int gx = tcol * blockDim.x + threadIdx.x;
-    if (gx >= W) return;
+                  int H, int W, int C, int R, int bw, float dts, float dx2, float dy2) {
+    constexpr int S = Direct<CP>::S;
+    __shared__ float4 red[S * kWave];
+    // the wave index is uniform: say so, so that the window loop and its loads are scalar
+    const int lane = threadIdx.x, s = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int by = blockIdx.x / bw, bx = blockIdx.x - by * bw;
+    const int x0 = bx * kDirectB, y0 = by * kDirectB;
+    const int gx = x0 + (lane & (kDirectB - 1)), gy = y0 + lane / kDirectB;
+    const bool live = gx < W && gy < H;
+    const int gxc = min(gx, W - 1), gyc = min(gy, H - 1);
     const float exh = 0.5f * eps[2 * k], ech = 0.5f * eps[2 * k + 1];
     const float Ax = exh * dx2, Ay = exh * dy2;
-    const int b0 = max(-R, -gx), b1 = min(R, W - 1 - gx);
-    for (int m = 0; m < NP; ++m) {
-        const int gy = (trow * blockDim.y + threadIdx.y) * NP + m;
-        if (gy >= H) break;
-        float ci[CP], acc[CP];
-        load_global_px<CP>(cin + ((size_t)gy * W + gx) * C, C, ci);
+    const float fx = (float)gxc, fy = (float)gyc, fR = (float)R;
+    float ci[CP], acc[CP];
+    load_global_px<CP>(cin + ((size_t)gyc * W + gxc) * C, C, ci);
 #pragma unroll
-        for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
-        const int a0 = max(-R, -gy), a1 = min(R, H - 1 - gy);
-        for (int a = a0; a <= a1; ++a) {
-            const float* row = cin + ((size_t)(gy + a) * W + gx) * C;
-            const float oma = fmaf(-Ay, ((float)a * (float)a), 1.0f);
-            for (int b = b0; b <= b1; ++b) {
-                if (a == 0 && b == 0) continue;
-                float cj[CP], d[CP];
-                load_global_px<CP>(row + (ptrdiff_t)b * C, C, cj);
-                float n2 = 0.0f;
+    for (int ch = 0; ch < CP; ++ch) acc[ch] = 0.0f;
+    const int r0 = max(y0 - R, 0), r1 = min(y0 + kDirectB - 1 + R, H - 1);
+    const int q0 = max(x0 - R, 0), q1 = min(x0 + kDirectB - 1 + R, W - 1);
+    for (int jr = r0 + s; jr <= r1; jr += S) {
+        const float a = (float)jr - fy;
+        const float oma = fmaf(-Ay, a * a, 1.0f);
+        const bool rin = !MASK || fabsf(a) <= fR;
+        const float* row = cin + (size_t)jr * W * C;
+#pragma unroll 4
+        for (int jc = q0; jc <= q1; ++jc) {
+            float cj[CP], d[CP];
+            load_global_px<CP>(row + (size_t)jc * C, C, cj);
+            const float b = (float)jc - fx;
+            float n2 = 0.0f;
 #pragma unroll
-                for (int ch = 0; ch < CP; ++ch) {
-                    d[ch] = cj[ch] - ci[ch];
-                    n2 = fmaf(d[ch], d[ch], n2);
-                }
-                const float t = clamp01(fmaf(-ech, n2, fmaf(-Ax, ((float)b * (float)b), oma)));
-                const float t2 = t * t;
-                const float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
-#pragma unroll
-                for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(w, d[ch], acc[ch]);
+            for (int ch = 0; ch < CP; ++ch) {
+                d[ch] = cj[ch] - ci[ch];
+                n2 = fmaf(d[ch], d[ch], n2);
             }
+            float t = clamp01(fmaf(-ech, n2, fmaf(-Ax, b * b, oma)));
+            if (MASK) t = (rin && fabsf(b) <= fR) ? t : 0.0f;
+            const float t2 = t * t;
+            const float w = fmaf(-4.0f, t, 5.0f) * (t2 * t2);
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) acc[ch] = fmaf(w, d[ch], acc[ch]);
         }
+    }
+    direct_wave_sum<CP, S>(acc, red);
+    if (s == 0 && live) {
         float* o = cout + ((size_t)gy * W + gx) * C;
 #pragma unroll
         for (int ch = 0; ch < CP; ++ch)
@@ -646,82 +701,86 @@ fwd_direct_kernel(const float* __restrict__ cin, float* __restrict__ cout, const
     }
 }
 
-// Transposed step in the direct form; part[2*tile + {0,1}] as in adj_tile (the
-// integrands summed over each pixel's whole window).
-template <int CP>
-__global__ void __launch_bounds__(kMaxThreads)
+// Transposed step in the direct form: v holds the lane's sums of w dp (CP), of
+// q D (CP) and the two control-gradient integrands over its whole window.
+template <int CP, bool MASK>
+__global__ void __launch_bounds__(kWave * Direct<CP>::S)
 adj_direct_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
-                  const float* __restrict__ eps, int k, int H, int W, int C, int R, int tiles_x, int tiles_y,
-                  float dts, float dx2, float dy2, double* __restrict__ part) {
-    constexpr int NP = RowsPerThread<CP>::value;
-    __shared__ double red[16];
-    int tcol, trow;
-    if (!strip_tile(tiles_x, tiles_y, tcol, trow)) return;
-    const int gx = tcol * blockDim.x + threadIdx.x;
+                  const float* __restrict__ eps, int k, int H, int W, int C, int R, int bw, float dts, float dx2,
+                  float dy2, double* __restrict__ part) {
+    constexpr int S = Direct<CP>::S, NQ = 2 * CP + 2;
+    __shared__ float4 red[S * kWave];
+    // the wave index is uniform: say so, so that the window loop and its loads are scalar
+    const int lane = threadIdx.x, s = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int by = blockIdx.x / bw, bx = blockIdx.x - by * bw;
+    const int x0 = bx * kDirectB, y0 = by * kDirectB;
+    const int gx = x0 + (lane & (kDirectB - 1)), gy = y0 + lane / kDirectB;
+    const bool live = gx < W && gy < H;
+    const int gxc = min(gx, W - 1), gyc = min(gy, H - 1);
     const float ex = eps[2 * k], ec = eps[2 * k + 1];
     const float exh = 0.5f * ex, ech = 0.5f * ec, ec20 = 20.0f * ec;
     const float Ax = exh * dx2, Ay = exh * dy2;
-    const int b0 = max(-R, -gx), b1 = min(R, W - 1 - gx);
-    double tsx = 0.0, tsc = 0.0;
-    for (int m = 0; m < NP; ++m) {
-        const int gy = (trow * blockDim.y + threadIdx.y) * NP + m;
-        if (gx >= W || gy >= H) break;
-        float ci[CP], pi[CP], acc[CP], accq[CP];
-        load_global_px<CP>(c + ((size_t)gy * W + gx) * C, C, ci);
-        load_global_px<CP>(pin + ((size_t)gy * W + gx) * C, C, pi);
+    const float fx = (float)gxc, fy = (float)gyc, fR = (float)R;
+    float ci[CP], pi[CP], v[NQ];
+    load_global_px<CP>(c + ((size_t)gyc * W + gxc) * C, C, ci);
+    load_global_px<CP>(pin + ((size_t)gyc * W + gxc) * C, C, pi);
 #pragma unroll
-        for (int ch = 0; ch < CP; ++ch) acc[ch] = accq[ch] = 0.0f;
-        float sx = 0.0f, sc = 0.0f;
-        const int a0 = max(-R, -gy), a1 = min(R, H - 1 - gy);
-        for (int a = a0; a <= a1; ++a) {
-            const size_t rbase = ((size_t)(gy + a) * W + gx) * C;
-            const float oma = fmaf(-Ay, ((float)a * (float)a), 1.0f);
-            const float d2a = dy2 * ((float)a * (float)a);
-            for (int b = b0; b <= b1; ++b) {
-                if (a == 0 && b == 0) continue;
-                float cj[CP], pj[CP], d[CP], dp[CP];
-                load_global_px<CP>(c + rbase + (ptrdiff_t)b * C, C, cj);
-                load_global_px<CP>(pin + rbase + (ptrdiff_t)b * C, C, pj);
-                const float d2 = fmaf(dx2, ((float)b * (float)b), d2a);
-                float n2 = 0.0f;
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0f;
+    const int r0 = max(y0 - R, 0), r1 = min(y0 + kDirectB - 1 + R, H - 1);
+    const int q0 = max(x0 - R, 0), q1 = min(x0 + kDirectB - 1 + R, W - 1);
+    for (int jr = r0 + s; jr <= r1; jr += S) {
+        const float a = (float)jr - fy;
+        const float oma = fmaf(-Ay, a * a, 1.0f);
+        const float d2a = dy2 * (a * a);
+        const bool rin = !MASK || fabsf(a) <= fR;
+        const size_t rbase = (size_t)jr * W * C;
+#pragma unroll 4
+        for (int jc = q0; jc <= q1; ++jc) {
+            float cj[CP], pj[CP], d[CP], dp[CP];
+            load_global_px<CP>(c + rbase + (size_t)jc * C, C, cj);
+            load_global_px<CP>(pin + rbase + (size_t)jc * C, C, pj);
+            const float b = (float)jc - fx;
+            const float d2 = fmaf(dx2, b * b, d2a);
+            float n2 = 0.0f;
 #pragma unroll
-                for (int ch = 0; ch < CP; ++ch) {
-                    d[ch] = cj[ch] - ci[ch];
-                    n2 = fmaf(d[ch], d[ch], n2);
-                }
-                const float t = clamp01(fmaf(-ech, n2, fmaf(-Ax, ((float)b * (float)b), oma)));
-                const float t3 = (t * t) * t;
-                const float u = fmaf(t3, t, -t3);
-                const float w = fmaf(u, fmaf(-4.0f, t, 1.0f), t3);
-                float ddp = 0.0f;
-#pragma unroll
-                for (int ch = 0; ch < CP; ++ch) {
-                    dp[ch] = pj[ch] - pi[ch];
-                    ddp = fmaf(d[ch], dp[ch], ddp);
-                }
-                const float q = u * ddp;
-#pragma unroll
-                for (int ch = 0; ch < CP; ++ch) {
-                    acc[ch] = fmaf(w, dp[ch], acc[ch]);
-                    accq[ch] = fmaf(q, d[ch], accq[ch]);
-                }
-                sx = fmaf(d2, q, sx);
-                sc = fmaf(n2, q, sc);
+            for (int ch = 0; ch < CP; ++ch) {
+                d[ch] = cj[ch] - ci[ch];
+                n2 = fmaf(d[ch], d[ch], n2);
             }
+            float t = clamp01(fmaf(-ech, n2, fmaf(-Ax, b * b, oma)));
+            if (MASK) t = (rin && fabsf(b) <= fR) ? t : 0.0f;
+            const float t3 = (t * t) * t;
+            const float u = fmaf(t3, t, -t3);
+            const float w = fmaf(u, fmaf(-4.0f, t, 1.0f), t3);
+            float ddp = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) {
+                dp[ch] = pj[ch] - pi[ch];
+                ddp = fmaf(d[ch], dp[ch], ddp);
+            }
+            const float q = u * ddp;
+#pragma unroll
+            for (int ch = 0; ch < CP; ++ch) {
+                v[ch] = fmaf(w, dp[ch], v[ch]);
+                v[CP + ch] = fmaf(q, d[ch], v[CP + ch]);
+            }
+            v[2 * CP] = fmaf(d2, q, v[2 * CP]);
+            v[2 * CP + 1] = fmaf(n2, q, v[2 * CP + 1]);
         }
+    }
+    direct_wave_sum<NQ, S>(v, red);
+    if (s != 0) return;
+    if (live) {
         float* o = pout + ((size_t)gy * W + gx) * C;
 #pragma unroll
         for (int ch = 0; ch < CP; ++ch)
-            if (ch < C) o[ch] = fmaf(dts, fmaf(ec20, accq[ch], acc[ch]), pi[ch]);
-        tsx += (double)sx;
-        tsc += (double)sc;
+            if (ch < C) o[ch] = fmaf(dts, fmaf(ec20, v[CP + ch], v[ch]), pi[ch]);
     }
-    const double bx = block_sum_f64(tsx, red);
-    const double bc = block_sum_f64(tsc, red);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
-        const int tile = trow * tiles_x + tcol;
-        part[2 * tile + 0] = bx;
-        part[2 * tile + 1] = bc;
+    const double bsx = wave_sum_f64(live ? (double)v[2 * CP] : 0.0);
+    const double bsc = wave_sum_f64(live ? (double)v[2 * CP + 1] : 0.0);
+    if (lane == 0) {
+        part[2 * (size_t)blockIdx.x + 0] = bsx;
+        part[2 * (size_t)blockIdx.x + 1] = bsc;
     }
 }
 
@@ -1556,27 +1615,28 @@ hipError_t adjb_wide_launch(const StepJob* jobs, int njobs, int total, int k, in
     return hipGetLastError();
 }
 
+// The window test is needed unless every pixel's window covers the image.
+bool direct_masks(int H, int W, int R) { return R < H - 1 || R < W - 1; }
+
 template <int CP>
 hipError_t fwd_direct_launch(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
-                             float dts, Tile t, hipStream_t s) {
-    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
-    dim3 grid;
-    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
+                             float dts, hipStream_t s) {
+    const int bw = (W + kDirectB - 1) / kDirectB;
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fwd_direct_kernel<CP>, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value), 0, s, cin, cout,
-                       eps, k, H, W, C, R, tiles_x, tiles_y, dts, dx2, dy2);
+    auto fn = direct_masks(H, W, R) ? fwd_direct_kernel<CP, true> : fwd_direct_kernel<CP, false>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)direct_blocks(H, W)), dim3(kWave, Direct<CP>::S), 0, s, cin, cout, eps, k,
+                       H, W, C, R, bw, dts, dx2, dy2);
     return hipGetLastError();
 }
 
 template <int CP>
 hipError_t adj_direct_launch(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
-                             int C, int R, float dts, Tile t, double* part, hipStream_t s) {
-    const int tiles_x = (W + t.tx - 1) / t.tx, tiles_y = (H + t.ty - 1) / t.ty;
-    dim3 grid;
-    if (!strip_grid(tiles_x, tiles_y, grid)) return hipErrorInvalidValue;
+                             int C, int R, float dts, double* part, hipStream_t s) {
+    const int bw = (W + kDirectB - 1) / kDirectB;
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(adj_direct_kernel<CP>, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value), 0, s, c, pin,
-                       pout, eps, k, H, W, C, R, tiles_x, tiles_y, dts, dx2, dy2, part);
+    auto fn = direct_masks(H, W, R) ? adj_direct_kernel<CP, true> : adj_direct_kernel<CP, false>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)direct_blocks(H, W)), dim3(kWave, Direct<CP>::S), 0, s, c, pin, pout, eps,
+                       k, H, W, C, R, bw, dts, dx2, dy2, part);
     return hipGetLastError();
 }
 
@@ -1585,7 +1645,7 @@ hipError_t adj_direct_launch(const float* c, const float* pin, float* pout, cons
 template <int CP>
 hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, int H, int W, int C, int R,
                         float dts, Tile t, hipStream_t s) {
-    if (direct_step(C, R, t, 1)) return fwd_direct_launch<CP>(cin, cout, eps, k, H, W, C, R, dts, t, s);
+    if (direct_step(C, R, t, 1)) return fwd_direct_launch<CP>(cin, cout, eps, k, H, W, C, R, dts, s);
     if constexpr (CP <= 4) {
         switch (R) {
             case 1: return fwd_launch_t<CP, 1>(cin, cout, eps, k, H, W, C, R, dts, t, s);
@@ -1609,7 +1669,7 @@ hipError_t fwd_launch_r(const float* cin, float* cout, const float* eps, int k, 
 template <int CP>
 hipError_t adj_launch_r(const float* c, const float* pin, float* pout, const float* eps, int k, int H, int W,
                         int C, int R, float dts, Tile t, double* part, hipStream_t s) {
-    if (direct_step(C, R, t, 2)) return adj_direct_launch<CP>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
+    if (direct_step(C, R, t, 2)) return adj_direct_launch<CP>(c, pin, pout, eps, k, H, W, C, R, dts, part, s);
     if constexpr (CP <= 4) {
         switch (R) {
             case 1: return adj_launch_t<CP, 1>(c, pin, pout, eps, k, H, W, C, R, dts, t, part, s);
@@ -1743,9 +1803,6 @@ bool tile_ok(int C, int R, Tile t, int fields) {
     return tile_lds_bytes(C, R, t, fields) <= kMaxLds || R > ABC_MAX_RADIUS;
 }
 
-bool direct_step(int C, int R, Tile t, int fields) {
-    return R > ABC_MAX_RADIUS && tile_lds_bytes(C, R, t, fields) > kMaxLds;
-}
 
 // Waves one CU can hold for a tile, limited by LDS and by 8 waves per SIMD.
 static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
@@ -1753,6 +1810,21 @@ static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
     const size_t lds = tile_lds_bytes(C, R, t, fields);
     const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
     return std::min(by_lds, 32 / wpb) * wpb;
+}
+
+// Past ABC_MAX_RADIUS a tile runs the tiled kernels only while its halo leaves
+// at least this many waves per CU (measured: with 8 the tiled forward step beats
+// the direct one, with 4 or fewer the direct kernels win).
+constexpr int kMinTiledWaves = 8;
+
+bool direct_step(int C, int R, Tile t, int fields) {
+    return R > ABC_MAX_RADIUS && tile_waves_per_cu(C, R, t, fields) < kMinTiledWaves;
+}
+
+int direct_blocks(int H, int W) { return ((W + kDirectB - 1) / kDirectB) * ((H + kDirectB - 1) / kDirectB); }
+
+int adj_part_count(int H, int W, int C, int R, Tile t) {
+    return direct_step(C, R, t, 2) ? direct_blocks(H, W) : tile_count(H, W, t);
 }
 
 // Workgroups of a persistent multi-image launch: as many as the GPU holds at

@@ -24,6 +24,14 @@ def test_library_exports_every_declared_symbol():
         assert f" T {n}" in out, n
 
 
+def test_library_leaves_no_symbol_of_its_own_unresolved():
+    """A helper declared for the other translation units but defined inside an
+    anonymous namespace links into a shared library as an undefined symbol and
+    fails only when first called; every abc:: symbol must be defined."""
+    out = subprocess.run(["nm", "-DC", "--undefined-only", B.LIB_PATH], capture_output=True, text=True).stdout
+    assert [ln for ln in out.splitlines() if "abc::" in ln or " abc_" in ln] == []
+
+
 def test_default_params_carry_the_papers_values():
     g = json.load(open(os.path.join(GOLD, "paper_parameters.json")))
     p = A.abc_default_params()
@@ -124,8 +132,8 @@ def test_support_radius_on_the_host():
         with pytest.raises(A.AbcError) as e:
             A.abc_support_radius(*bad)
         assert e.value.code == A.ABC_EINVAL
-    # the support mode sizes workspaces as the radius it resolves to; a tile too large for the LDS past radius 16
-    # runs the direct kernels
+    # the support mode sizes workspaces as the radius it resolves to; past radius 16 a tile that leaves fewer than
+    # 8 waves per CU runs the direct kernels
     p = A.Params(K=4, R=A.ABC_RADIUS_SUPPORT, eps_min=(20.0, 2.0))
     for kind in (A.ABC_WS_SOLVE, A.ABC_WS_ADJOINT):
         assert A.abc_workspace_bytes(kind, 40, 56, 3, p) == A.abc_workspace_bytes(kind, 40, 56, 3, p.replace(R=18))

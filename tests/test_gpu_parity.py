@@ -460,9 +460,11 @@ def test_unwindowed_paper_sum_matches_oracle(orc, C):
                                          (30, 33, 31, 6.0)])
 def test_support_radius_mode_matches_oracle(orc, H, W, C, emin):
     """R = ABC_RADIUS_SUPPORT: the library takes the window of the kernel's support at
-    the box's lower bound eps_x >= emin (eq. kernel vanishes for r >= 1), here beyond the
-    tiled kernels' radius 16, so the direct kernels run; at emin = 2 the window is the
-    whole image.  With s = 1/N that is the un-windowed sum of eq. MAsystem."""
+    the box's lower bound eps_x >= emin (eq. kernel vanishes for r >= 1), here beyond
+    radius 16: the tiled runtime-radius kernels run where the tile's halo fits the LDS
+    (C = 1, 3, 5 here), the direct kernels where it does not (C = 31); at emin = 2 the
+    window is the whole image.  With s = 1/N that is the un-windowed sum of
+    eq. MAsystem."""
     R = A.abc_support_radius(H, W, emin)
     assert R > A.ABC_MAX_RADIUS
     print(f"support radius case H={H} W={W} C={C} emin={emin} R={R}", flush=True)
@@ -480,6 +482,37 @@ def test_support_radius_mode_matches_oracle(orc, H, W, C, emin):
     # the same radius given explicitly runs the same kernels: the same bits
     traj2 = A.abc_forward_dynamics(T(c0), T(eps), gp.replace(R=R))
     assert torch.equal(traj, traj2)
+
+
+@pytest.mark.parametrize("H,W,C,R", [(61, 70, 3, 40), (45, 37, 3, 60), (100, 90, 1, 99), (40, 44, 8, 20),
+                                      (33, 35, 16, 17), (9, 130, 5, 129)])
+def test_direct_kernels_match_oracle(orc, H, W, C, R):
+    """Radii whose tile halo does not fit the LDS run the direct kernels (8 x 8 pixel
+    blocks, the window's rows dealt out to the waves): windows cut by the image and
+    windows covering it (no per-pair window test), blocks past the image's edge, 1 to 16
+    channels.  At 1 and 3 channels two tiles whose halos do not fit give the same bits:
+    the direct kernels do not depend on the tile asked for."""
+    print(f"[case] direct H={H} W={W} C={C} R={R}", flush=True)
+    c0 = voronoi_image(H, W, C, 4, 0.05, 70 + C)
+    eps = rand_eps(3, 71, lo=2.0, hi=60.0)
+    gp, op = both_params(orc, H, W, K=3, R=R)
+    traj = A.abc_forward_dynamics(T(c0), T(eps), gp)
+    want = orc.forward_sweep(c0, op, eps)
+    assert relinf(N(traj), want) < FIELD_TOL / 10
+    gK = np.random.default_rng(72).normal(size=c0.shape)
+    g0, geps = A.abc_adjoint_dynamics(traj, T(eps), gp, T(gK))
+    p0, ge = orc.adjoint_sweep(want, op, gK, eps)
+    print(f"  errors: c^K {relinf(N(traj), want):.2e} p^0 {relinf(N(g0), p0):.2e} dl/deps {rel2(N(geps), ge):.2e}",
+          flush=True)
+    assert relinf(N(g0), p0) < FIELD_TOL and rel2(N(geps), ge) < FIELD_TOL
+    if C > 3:
+        return
+    runs = []
+    for tx, ty in ((32, 16), (64, 8)):  # both halos too large for the LDS at these radii
+        q = gp.replace(tile_x=tx, tile_y=ty, adj_tile_x=tx, adj_tile_y=ty)
+        tr = A.abc_forward_dynamics(T(c0), T(eps), q)
+        runs.append((tr,) + A.abc_adjoint_dynamics(tr, T(eps), q, T(gK)))
+    assert all(torch.equal(a, b) for a, b in zip(*runs))
 
 
 def test_support_radius_solve_matches_oracle(orc):
