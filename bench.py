@@ -35,10 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak (packed FP32 issue)
-# Issue-rate ceiling of code built without packed FP32 (every kernel here):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz.
-PEAK_FP32_NONPACKED_TFLOPS = 78.6
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel of each workload, from the rocprofv3
@@ -258,9 +255,7 @@ def main() -> int:
                    "fwd_tflops": fwd_flops * K / t_fwd / 1e12, "adj_tflops": adj_flops * K / t_adj / 1e12},
         "roofline": {"kernel": "adj_step_kernel<3,5>", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": traffic, "flops_per_launch": adj_flops, "launch_ms": adj_launch * 1e3,
-                     "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
-                     "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS},
+                     "traffic": traffic, "flops_per_launch": adj_flops, "launch_ms": adj_launch * 1e3},
         "last_step_stats": {k: st[k] for k in ("K", "TV", "fid", "r_rel")},
     }
     sweep_s = None
@@ -675,9 +670,7 @@ def bench_support(args) -> int:
                       "fwd_tflops": pairs * flops_per_pair(C, "fwd") * K / t_f / 1e12},
            "roofline": {"kernel": "adj_direct_kernel<3>", "bound": "alu", "achieved": achieved,
                         "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                        "traffic": None, "flops_per_launch": adj_flops, "launch_ms": t_a / K * 1e3,
-                        "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
-                        "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS}}
+                        "traffic": None, "flops_per_launch": adj_flops, "launch_ms": t_a / K * 1e3}}
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         Ks = 10
