@@ -70,8 +70,8 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 
 // FP64 sum of v over the workgroup, valid in thread 0.  `red` holds >= 16 doubles.
 __device__ __forceinline__ double block_sum_f64(double v, double* red) {
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int nthreads = blockDim.x * blockDim.y;
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
     v = wave_sum_f64(v);
     const int w = tid / kWave;
     if ((tid % kWave) == 0) red[w] = v;
@@ -131,6 +131,16 @@ struct RowsPerThread {
     static constexpr int value = CP <= 4 ? 2 : 1;
 };
 
+// Thread layers of the transposed step: with up to 4 channels and a compile-time
+// radius each pixel's window is split by rows over two threads (blockDim.z = 2),
+// which doubles the waves of a workgroup; small images have too few tiles to give
+// a CU more than two workgroups, and two waves per SIMD leave most FP32
+// instructions unpaired.
+template <int CP, int RT>
+struct AdjSplit {
+    static constexpr int value = CP <= 4 && RT >= 1 ? 2 : 1;
+};
+
 template <int CP>
 __device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m) {
     if constexpr (CP == 1) {
@@ -168,15 +178,17 @@ __device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m
 template <int CP, bool EXACT>
 __device__ __forceinline__ void stage_cells(float* dst, const float* __restrict__ src, int H, int W, int C,
                                             int x0, int y0, int R, int LW, int LH) {
+    // rows are dealt out over every layer of the workgroup (blockDim.z > 1 in the split transposed step)
+    const int tyz = threadIdx.y + blockDim.y * threadIdx.z, byz = blockDim.y * blockDim.z;
     constexpr int NV = Slot<CP>::NV, CS = Slot<CP>::CS;
     const unsigned WC = (unsigned)W * (unsigned)C;
-    for (int ly0 = threadIdx.y; ly0 < LH; ly0 += 2 * blockDim.y) {
+    for (int ly0 = tyz; ly0 < LH; ly0 += 2 * byz) {
         unsigned rbase[2];
         bool row_in[2];
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
             // rows past the tile (no cell of theirs is written) read its last row
-            const int gy = y0 - R + min(ly0 + v * (int)blockDim.y, LH - 1);
+            const int gy = y0 - R + min(ly0 + v * (int)byz, LH - 1);
             const int gyc = min(max(gy, 0), H - 1);
             row_in[v] = gy == gyc;
             rbase[v] = (unsigned)gyc * WC;
@@ -187,7 +199,7 @@ __device__ __forceinline__ void stage_cells(float* dst, const float* __restrict_
             int cell[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int ly = ly0 + (u >> 1) * blockDim.y, lx = lx0 + (u & 1) * blockDim.x;
+                const int ly = ly0 + (u >> 1) * byz, lx = lx0 + (u & 1) * blockDim.x;
                 act[u] = ly < LH && lx < LW;
                 cell[u] = ly * LW + lx;
                 const int gx = x0 - R + min(lx, LW - 1);
@@ -376,7 +388,7 @@ __device__ __forceinline__ void for_batched_tiles(int* __restrict__ queue, int k
         const int per = total / 8, rem = total % 8;
         const int lo = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
         const int n = per + (x < rem ? 1 : 0);
-        const bool first = threadIdx.x == 0 && threadIdx.y == 0;
+        const bool first = threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0;
         for (;;) {
             if (first) next[0] = atomicAdd(queue + 8 * k + x, 1);
             __syncthreads();
@@ -420,16 +432,19 @@ fwd_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int 
 // sums its window in FP32; the sum over pixels is carried in FP64 (the
 // solver's projected steps can reach 1e13 or more, which amplifies rounding
 // in this sum directly into the controls).
-template <int CP, int RT, int NP, bool BORDER>
+template <int CP, int RT, int NP, bool BORDER, int PART>
 __device__ __forceinline__ void adj_window(const float* mc, const float* mp, int LW, int R,
                                            const float (&ci)[NP][CP], const float (&pi)[NP][CP],
                                            float (&acc)[NP][CP], float (&accq)[NP][CP], float (&sx)[NP],
                                            float (&sc)[NP], float Ax, float Ay, float ech, float dx2, float dy2) {
     constexpr int CS = Slot<CP>::CS;
     const int RR = RT > 0 ? RT : R;
-    // r: row of the neighbour relative to the thread's first pixel; pixel m sees it at a = r - m
+    // r: row of the neighbour relative to the thread's first pixel; pixel m sees it at a = r - m.
+    // PART 1 / 2 take the first / second half of those rows (the window split over two threads).
+    const int rmid = -RR + (2 * RR + NP) / 2;
+    const int rlo = PART == 2 ? rmid : -RR, rhi = PART == 1 ? rmid - 1 : RR + NP - 1;
 #pragma unroll
-    for (int r = -RR; r <= RR + NP - 1; ++r) {
+    for (int r = rlo; r <= rhi; ++r) {
         const float* rowc = mc + r * LW * CS;
         const float* rowp = mp + r * LW * CS;
 #pragma unroll
@@ -492,6 +507,7 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
                                          double* __restrict__ part, float* lds, double* red) {
     constexpr int CS = Slot<CP>::CS;
     constexpr int NP = RowsPerThread<CP>::value;
+    constexpr int SPLIT = AdjSplit<CP, RT>::value;  // blockDim.z
     const int TX = blockDim.x, TY = NP * blockDim.y;
     const int x0 = tcol * TX, y0 = trow * TY;
     const int LW = TX + 2 * R, LH = TY + 2 * R;
@@ -502,13 +518,14 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
     stage_tile<CP>(ldp, pin, H, W, C, x0, y0, R, LW, LH);
     __syncthreads();
     const int gx = x0 + threadIdx.x, gy = y0 + NP * threadIdx.y;
+    const bool live = gx < W && gy < H;
     double tsx = 0.0, tsc = 0.0;
-    if (gx < W && gy < H) {
+    float ci[NP][CP], pi[NP][CP], acc[NP][CP], accq[NP][CP], sx[NP], sc[NP], mi;
+    if (live) {
         const float exh = 0.5f * ex, ech = 0.5f * ec;
         const int off = ((NP * threadIdx.y + R) * LW + threadIdx.x + R) * CS;
         const float* mc = ldc + off;
         const float* mp = ldp + off;
-        float ci[NP][CP], pi[NP][CP], acc[NP][CP], accq[NP][CP], sx[NP], sc[NP], mi;
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
             load_px<CP>(mc + m * LW * CS, ci[m], mi);
@@ -517,12 +534,58 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
 #pragma unroll
             for (int ch = 0; ch < CP; ++ch) acc[m][ch] = accq[m][ch] = 0.0f;
         }
-        if (interior)
-            adj_window<CP, RT, NP, false>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
-                                          dy2);
-        else
-            adj_window<CP, RT, NP, true>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, exh * dx2, exh * dy2, ech, dx2,
-                                         dy2);
+        const float Ax = exh * dx2, Ay = exh * dy2;
+        if constexpr (SPLIT == 1) {
+            if (interior)
+                adj_window<CP, RT, NP, false, 0>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, Ax, Ay, ech, dx2, dy2);
+            else
+                adj_window<CP, RT, NP, true, 0>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, Ax, Ay, ech, dx2, dy2);
+        } else if (threadIdx.z == 0) {
+            if (interior)
+                adj_window<CP, RT, NP, false, 1>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, Ax, Ay, ech, dx2, dy2);
+            else
+                adj_window<CP, RT, NP, true, 1>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, Ax, Ay, ech, dx2, dy2);
+        } else {
+            if (interior)
+                adj_window<CP, RT, NP, false, 2>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, Ax, Ay, ech, dx2, dy2);
+            else
+                adj_window<CP, RT, NP, true, 2>(mc, mp, LW, R, ci, pi, acc, accq, sx, sc, Ax, Ay, ech, dx2, dy2);
+        }
+    }
+    if constexpr (SPLIT == 2) {
+        // the second layer's sums reach the first layer's threads through LDS past the two
+        // fields (quantity-major: consecutive threads, consecutive words); the first adds them,
+        // so every sum is (first half of the rows) + (second half)
+        constexpr int NQ = 2 * CP + 2;
+        const int nt = blockDim.x * blockDim.y, tt = threadIdx.x + blockDim.x * threadIdx.y;
+        float* comb = lds + 2 * LW * LH * CS;
+        if (threadIdx.z == 1 && live) {
+#pragma unroll
+            for (int m = 0; m < NP; ++m) {
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    comb[(m * NQ + ch) * nt + tt] = acc[m][ch];
+                    comb[(m * NQ + CP + ch) * nt + tt] = accq[m][ch];
+                }
+                comb[(m * NQ + 2 * CP) * nt + tt] = sx[m];
+                comb[(m * NQ + 2 * CP + 1) * nt + tt] = sc[m];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.z == 0 && live) {
+#pragma unroll
+            for (int m = 0; m < NP; ++m) {
+#pragma unroll
+                for (int ch = 0; ch < CP; ++ch) {
+                    acc[m][ch] += comb[(m * NQ + ch) * nt + tt];
+                    accq[m][ch] += comb[(m * NQ + CP + ch) * nt + tt];
+                }
+                sx[m] += comb[(m * NQ + 2 * CP) * nt + tt];
+                sc[m] += comb[(m * NQ + 2 * CP + 1) * nt + tt];
+            }
+        }
+    }
+    if (threadIdx.z == 0 && live) {
         const float ec20 = 20.0f * ec;
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
@@ -538,7 +601,7 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
     }
     const double bx = block_sum_f64(tsx, red);
     const double bc = block_sum_f64(tsc, red);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
+    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) {
         const int tile = trow * tiles_x + tcol;
         part[2 * tile + 0] = bx;
         part[2 * tile + 1] = bc;
@@ -546,7 +609,8 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
 }
 
 template <int CP, int RT>
-__global__ void __launch_bounds__(kMaxThreads)
+__global__ void __launch_bounds__((kMaxThreads * AdjSplit<CP, RT>::value))
+__attribute__((amdgpu_waves_per_eu(AdjSplit<CP, RT>::value == 2 ? 4 : 1)))
 adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, float* __restrict__ pout,
                 const float* __restrict__ eps, int k, int H, int W, int C, int Rrt, int tiles_x, int tiles_y,
                 float dts, float dx2, float dy2, double* __restrict__ part) {
@@ -563,7 +627,8 @@ adj_step_kernel(const float* __restrict__ c, const float* __restrict__ pin, floa
 // pa when K-1-k is even, else from pb, and p^k goes to the other buffer;
 // part receives K x tiles x 2 partials per job.
 template <int CP, int RT, bool PQ>
-__global__ void __launch_bounds__(kMaxThreads)
+__global__ void __launch_bounds__((kMaxThreads * AdjSplit<CP, RT>::value))
+__attribute__((amdgpu_waves_per_eu(AdjSplit<CP, RT>::value == 2 ? 4 : 1)))
 adj_step_batched_kernel(const StepJob* __restrict__ jobs, int njobs, int k, int K, int C, int Rrt, int total,
                         int* __restrict__ queue) {
     extern __shared__ __align__(16) float lds[];
@@ -1542,8 +1607,8 @@ hipError_t adj_launch_t(const float* c, const float* pin, float* pout, const flo
         if (e != hipSuccess) return e;
     }
     const float dx2 = 1.0f / ((float)W * (float)W), dy2 = 1.0f / ((float)H * (float)H);
-    hipLaunchKernelGGL(fn, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, c, pin, pout, eps, k, H, W,
-                       C, R, tiles_x, tiles_y, dts, dx2, dy2, part);
+    hipLaunchKernelGGL(fn, grid, dim3(t.tx, t.ty / RowsPerThread<CP>::value, AdjSplit<CP, RT>::value), lds, s, c,
+                       pin, pout, eps, k, H, W, C, R, tiles_x, tiles_y, dts, dx2, dy2, part);
     return hipGetLastError();
 }
 
@@ -1715,8 +1780,8 @@ hipError_t adjb_launch_t(const StepJob* jobs, int njobs, int total, int k, int K
         if (e != hipSuccess) return e;
     }
     const int grid = queue ? persistent_grid(C, R, t, 2, total) : total;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(t.tx, t.ty / RowsPerThread<CP>::value), lds, s, jobs, njobs, k, K, C,
-                       R, total, queue);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(t.tx, t.ty / RowsPerThread<CP>::value, AdjSplit<CP, RT>::value), lds, s,
+                       jobs, njobs, k, K, C, R, total, queue);
     return hipGetLastError();
 }
 
@@ -1776,6 +1841,12 @@ int wide_lanes(int C, int R) {
     return (cp >= 16 && R >= 1 && R <= 3) ? (cp + 7) / 8 : 1;
 }
 
+// Thread layers of the transposed step for (C, R) as launched (AdjSplit of the kernel that runs).
+int adj_split(int C, int R) {
+    const int cp = padded_channels(C);
+    return cp >= 1 && cp <= 4 && R >= 1 && R <= 5 ? 2 : 1;
+}
+
 size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     const int cp = padded_channels(C);
     if (cp < 0) return (size_t)-1;
@@ -1783,9 +1854,11 @@ size_t tile_lds_bytes(int C, int R, Tile t, int fields) {
     if (G > 1) return (size_t)fields * G * wide_plane_floats(t.tx + 2 * R, t.ty + 2 * R) * sizeof(float);
     const int nv = (cp + 1 + 3) / 4;
     const int cs = cp == 1 ? 2 : 4 * (nv % 2 ? nv : nv + 1);
-    // plus the forward step's offset-constant table ((2R+1)^2 floats)
+    // plus the forward step's offset-constant table ((2R+1)^2 floats), and in the split
+    // transposed step the second layer's sums (2 cp + 2 floats per pixel)
+    const size_t comb = fields == 2 && adj_split(C, R) == 2 ? (size_t)t.tx * t.ty * (2 * cp + 2) : 0;
     return ((size_t)fields * (size_t)(t.tx + 2 * R) * (size_t)(t.ty + 2 * R) * (size_t)cs +
-            (size_t)(2 * R + 1) * (2 * R + 1)) * sizeof(float);
+            (size_t)(2 * R + 1) * (2 * R + 1) + comb) * sizeof(float);
 }
 
 int rows_per_thread(int C, int R) {
@@ -1806,7 +1879,8 @@ bool tile_ok(int C, int R, Tile t, int fields) {
 
 // Waves one CU can hold for a tile, limited by LDS and by 8 waves per SIMD.
 static int tile_waves_per_cu(int C, int R, Tile t, int fields) {
-    const int wpb = (t.tx * (t.ty / rows_per_thread(C, R)) * wide_lanes(C, R) + kWave - 1) / kWave;
+    const int wpb = (t.tx * (t.ty / rows_per_thread(C, R)) * wide_lanes(C, R) * (fields == 2 ? adj_split(C, R) : 1) +
+                     kWave - 1) / kWave;
     const size_t lds = tile_lds_bytes(C, R, t, fields);
     const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
     return std::min(by_lds, 32 / wpb) * wpb;
@@ -1839,7 +1913,8 @@ int persistent_grid(int C, int R, Tile t, int fields, int total) {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
         cus[dev] = n;
     }
-    const int wpb = (t.tx * (t.ty / rows_per_thread(C, R)) * wide_lanes(C, R) + kWave - 1) / kWave;
+    const int wpb = (t.tx * (t.ty / rows_per_thread(C, R)) * wide_lanes(C, R) * (fields == 2 ? adj_split(C, R) : 1) +
+                     kWave - 1) / kWave;
     const int per_cu = std::max(1, tile_waves_per_cu(C, R, t, fields) / wpb);
     const int cap = (cus[dev] * per_cu + 7) / 8 * 8;
     return std::min(total, cap);
