@@ -85,7 +85,7 @@ def main() -> int:
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0,
                     help="repeat the oracle's full forward+adjoint sweep until this much time has passed")
     ap.add_argument("--workload", default="voronoi512", choices=["voronoi512", "batch64", "segment512", "hyper2048", "warmstart1024", "converge512",
-                             "transfer1024", "quadratic512", "support128"],
+                             "transfer1024", "quadratic512", "support128", "sweeps1024"],
                     help="voronoi512: the headline line (default); batch64: the batched form; segment512: "
                          "watershed labels and IRV/IRC/VS scores of a solved 512 x 512 image; hyper2048: the "
                          "differentiable form on 2048 x 2048 x 31 (checkpointed forward + backward); warmstart1024: "
@@ -93,7 +93,9 @@ def main() -> int:
                          "learned warm start; converge512: time to solve the 512 x 512 image to ALM residual 1e-5; "
                          "transfer1024: controls of the 512 x 512 solve applied to its 2x finer version; "
                          "quadratic512: the DAL with the quadratic cost J (Def. 3.2) on the 512 x 512 image; "
-                         "support128: the un-windowed sum (window from the kernel's support) on 128 x 128")
+                         "support128: the un-windowed sum (window from the kernel's support) on 128 x 128; "
+                         "sweeps1024: the headline sweeps on a 1024 x 1024 version of the image (a grid that fills "
+                         "the GPU)")
     ap.add_argument("--images", type=int, default=4, help="warmstart1024: held-out images to solve")
     ap.add_argument("--no-converge", action="store_true",
                     help="voronoi512: skip the time-to-converged part (converged solves, 32 x 32 solve, warm start)")
@@ -114,7 +116,7 @@ def main() -> int:
     # (steps, warmup) per workload when not given: the longer workloads time whole solves.
     defaults = {"voronoi512": (50, 100), "batch64": (3, 1), "segment512": (20, 3), "hyper2048": (5, 2),
                 "warmstart1024": (0, 1), "converge512": (1, 1), "transfer1024": (20, 5), "quadratic512": (3, 1),
-                "support128": (5, 2)}
+                "support128": (5, 2), "sweeps1024": (20, 20)}
     d_steps, d_warm = defaults[args.workload]
     if args.steps is None:
         args.steps = d_steps
@@ -153,6 +155,8 @@ def main() -> int:
         return bench_quadratic(args)
     if args.workload == "support128":
         return bench_support(args)
+    if args.workload == "sweeps1024":
+        return bench_sweeps1024(args)
 
     import paper_2510_16154_amd as A
     from paper_2510_16154_amd.workloads import VORONOI512 as wl
@@ -684,6 +688,60 @@ def bench_support(args) -> int:
                                "kind": "oracle",
                                "sample": f"forward + adjoint sweep of {Ks} Euler steps of the same image, "
                                          f"R = {R}, FP64, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_sweeps1024(args) -> int:
+    """The headline image's dynamics (R = 5, K = 50, controls eps_init) on a
+    1024 x 1024 x 3 Voronoi image of the same recipe (seed 1006): forward and
+    adjoint sweeps timed with HIP events.  At 512 x 512 the 512 tiles of a sweep
+    step give each CU two workgroups; here four, which shows what the same
+    kernels reach once the grid fills the GPU."""
+    import torch
+
+    import paper_2510_16154_amd as A
+    from paper_2510_16154_amd.synth import voronoi_image
+    from paper_2510_16154_amd.workloads import VORONOI512 as wl
+
+    H = W = 1024
+    C, K, R = wl.C, wl.K, wl.R
+    c0 = torch.as_tensor(voronoi_image(H, W, C, wl.regions, wl.sigma, 1006, gradient_amp=wl.gradient_amp),
+                         device="cuda")
+    params = A.Params(K=K, R=R)
+    eps = torch.full((K, 2), params.eps_init, dtype=torch.float32, device="cuda")
+    gK = torch.as_tensor(np.random.default_rng(6).normal(size=(H, W, C)).astype(np.float32), device="cuda")
+    traj = torch.empty((K + 1, H, W, C), dtype=torch.float32, device="cuda")
+    ws_a = torch.empty(A.abc_workspace_bytes(A.ABC_WS_ADJOINT, H, W, C, params), dtype=torch.uint8, device="cuda")
+    g0 = torch.empty_like(c0)
+    geps = torch.empty((K, 2), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, adj = [], []
+    for rep in range(args.warmup + args.steps):
+        ev[0].record(stream)
+        A.abc_forward_dynamics(c0, eps, params, traj=traj)
+        ev[1].record(stream)
+        A.abc_adjoint_dynamics(traj, eps, params, gK, g0=g0, geps=geps, ws=ws_a)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        if rep >= args.warmup:
+            fwd.append(ev[0].elapsed_time(ev[1]) * 1e-3)
+            adj.append(ev[1].elapsed_time(ev[2]) * 1e-3)
+    t_f, t_a = float(np.median(fwd)), float(np.median(adj))
+    pairs = window_pairs(H, W, R)
+    adj_flops = pairs * flops_per_pair(C, "adj")
+    achieved = adj_flops * K / t_a / 1e12
+    out = {"metric": "agent-steps/sec (fwd+adjoint sweeps)", "value": H * W * K / (t_f + t_a),
+           "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": (t_f + t_a) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic (seeded Voronoi image)",
+           "config": {"workload": "voronoi1024_rgb_r5_k50_sweeps", "H": H, "W": W, "C": C, "R": R, "K": K},
+           "sweeps": {"fwd_ms": t_f * 1e3, "adj_ms": t_a * 1e3,
+                      "fwd_tflops": pairs * flops_per_pair(C, "fwd") * K / t_f / 1e12},
+           "roofline": {"kernel": "adj_step_kernel<3,5>", "bound": "alu", "achieved": achieved,
+                        "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                        "traffic": None, "flops_per_launch": adj_flops, "launch_ms": t_a / K * 1e3}}
     print(json.dumps(out), flush=True)
     return 0
 
