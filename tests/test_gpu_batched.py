@@ -67,10 +67,12 @@ def test_batched_wide_channels_equal_individual_solves_and_graphs():
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("R,C,tile", [(7, 3, (32, 16)), (4, 2, (16, 16)), (3, 6, (32, 8))])
+@pytest.mark.parametrize("R,C,tile", [(7, 3, (32, 16)), (4, 2, (16, 16)), (3, 6, (32, 8)), (5, 4, (32, 16)),
+                                      (1, 1, (64, 4)), (3, 1, (16, 8))])
 def test_batched_default_and_runtime_radius_tiles_equal_individual_solves(R, C, tile):
-    """Two pixels per thread with a compile-time (R <= 5) and a runtime radius (R = 7),
-    and one pixel per thread for 6 channels, each in the batched launch and alone."""
+    """Two pixels per thread with a compile-time (R <= 5, the transposed step's window
+    split over two thread layers) and a runtime radius (R = 7), and one pixel per
+    thread for 6 channels, each in the batched launch and alone; 1 to 6 channels."""
     print(f"[case] batched vs individual, R={R} C={C} tile={tile}", flush=True)
     shapes = [(40, 57), (33, 33), (71, 24)]
     imgs = [voronoi_image(h, w, C, 4, 0.05, 800 + i) for i, (h, w) in enumerate(shapes)]

@@ -79,6 +79,10 @@ FWD_CASES = [
     (29, 31, 7, 4, 3, 21),
     (17, 9, 3, 4, 3, 22),
     (25, 30, 2, 9, 2, 23),
+    # the transposed step's two thread layers at every compile-time radius, 2 and 4 channels
+    (35, 41, 4, 5, 3, 24),
+    (26, 19, 2, 1, 3, 25),
+    (19, 50, 4, 3, 2, 26),
 ]
 
 
