@@ -174,10 +174,12 @@ __device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m
 // 4e9); with C == CP the channel offsets are constants of the load
 // instructions, otherwise they are clamped into the pixel.  Each pass has the
 // loads of up to four cells (two rows x two columns) in flight before it
-// writes LDS.
-template <int CP, bool EXACT>
-__device__ __forceinline__ void stage_cells(float* dst, const float* __restrict__ src, int H, int W, int C,
-                                            int x0, int y0, int R, int LW, int LH) {
+// writes LDS; with NF = 2 it stages two fields of the same image (dst1 from
+// src1) in the same passes, so that their loads are in flight together.
+template <int CP, bool EXACT, int NF>
+__device__ __forceinline__ void stage_cells(float* dst0, const float* __restrict__ src0, float* dst1,
+                                            const float* __restrict__ src1, int H, int W, int C, int x0, int y0,
+                                            int R, int LW, int LH) {
     // rows are dealt out over every layer of the workgroup (blockDim.z > 1 in the split transposed step)
     const int tyz = threadIdx.y + blockDim.y * threadIdx.z, byz = blockDim.y * blockDim.z;
     constexpr int NV = Slot<CP>::NV, CS = Slot<CP>::CS;
@@ -194,7 +196,7 @@ __device__ __forceinline__ void stage_cells(float* dst, const float* __restrict_
             rbase[v] = (unsigned)gyc * WC;
         }
         for (int lx0 = threadIdx.x; lx0 < LW; lx0 += 2 * blockDim.x) {
-            float t[4][CS];
+            float t[NF][4][CS];
             bool act[4];
             int cell[4];
 #pragma unroll
@@ -206,25 +208,31 @@ __device__ __forceinline__ void stage_cells(float* dst, const float* __restrict_
                 const int gxc = min(max(gx, 0), W - 1);
                 const bool in = act[u] && row_in[u >> 1] && gx == gxc;
                 const unsigned col = EXACT ? (unsigned)gxc * (unsigned)CP : (unsigned)gxc * (unsigned)C;
-                const float* s = src + (rbase[u >> 1] + col);
 #pragma unroll
-                for (int ch = 0; ch < CS; ++ch) {
-                    const float x = ch < CP ? s[EXACT ? ch : min(ch, C - 1)] : 0.0f;
-                    t[u][ch] = (in && ch < CP && (EXACT || ch < C)) ? x : 0.0f;
+                for (int f = 0; f < NF; ++f) {
+                    const float* s = (f == 0 ? src0 : src1) + (rbase[u >> 1] + col);
+#pragma unroll
+                    for (int ch = 0; ch < CS; ++ch) {
+                        const float x = ch < CP ? s[EXACT ? ch : min(ch, C - 1)] : 0.0f;
+                        t[f][u][ch] = (in && ch < CP && (EXACT || ch < C)) ? x : 0.0f;
+                    }
+                    t[f][u][CP] = in ? 1.0f : 0.0f;
                 }
-                t[u][CP] = in ? 1.0f : 0.0f;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (!act[u]) continue;
-                float* d = dst + cell[u] * CS;
-                if constexpr (CP == 1) {
-                    *reinterpret_cast<float2*>(d) = make_float2(t[u][0], t[u][1]);
-                } else {
+            for (int f = 0; f < NF; ++f) {
 #pragma unroll
-                    for (int i = 0; i < NV; ++i)
-                        reinterpret_cast<float4*>(d)[i] =
-                            make_float4(t[u][4 * i], t[u][4 * i + 1], t[u][4 * i + 2], t[u][4 * i + 3]);
+                for (int u = 0; u < 4; ++u) {
+                    if (!act[u]) continue;
+                    float* d = (f == 0 ? dst0 : dst1) + cell[u] * CS;
+                    if constexpr (CP == 1) {
+                        *reinterpret_cast<float2*>(d) = make_float2(t[f][u][0], t[f][u][1]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < NV; ++i)
+                            reinterpret_cast<float4*>(d)[i] = make_float4(t[f][u][4 * i], t[f][u][4 * i + 1],
+                                                                          t[f][u][4 * i + 2], t[f][u][4 * i + 3]);
+                    }
                 }
             }
         }
@@ -235,9 +243,27 @@ template <int CP>
 __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__ src, int H, int W, int C,
                                            int x0, int y0, int R, int LW, int LH) {
     if (C == CP)
-        stage_cells<CP, true>(dst, src, H, W, C, x0, y0, R, LW, LH);
+        stage_cells<CP, true, 1>(dst, src, nullptr, nullptr, H, W, C, x0, y0, R, LW, LH);
     else
-        stage_cells<CP, false>(dst, src, H, W, C, x0, y0, R, LW, LH);
+        stage_cells<CP, false, 1>(dst, src, nullptr, nullptr, H, W, C, x0, y0, R, LW, LH);
+}
+
+// Two fields of one image (the transposed step's c^k and p^{k+1}): staged in
+// the same passes for up to 4 channels (8 cells' loads in flight per thread),
+// one after the other for wider pixels, whose cells take more registers.
+template <int CP>
+__device__ __forceinline__ void stage_tile2(float* dst0, const float* __restrict__ src0, float* dst1,
+                                            const float* __restrict__ src1, int H, int W, int C, int x0, int y0,
+                                            int R, int LW, int LH) {
+    if constexpr (CP <= 4) {
+        if (C == CP)
+            stage_cells<CP, true, 2>(dst0, src0, dst1, src1, H, W, C, x0, y0, R, LW, LH);
+        else
+            stage_cells<CP, false, 2>(dst0, src0, dst1, src1, H, W, C, x0, y0, R, LW, LH);
+    } else {
+        stage_tile<CP>(dst0, src0, H, W, C, x0, y0, R, LW, LH);
+        stage_tile<CP>(dst1, src1, H, W, C, x0, y0, R, LW, LH);
+    }
 }
 
 // Offset constants of a window of radius RT, written by the threads of a
@@ -514,8 +540,7 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
     const bool interior = x0 >= R && y0 >= R && x0 + TX + R <= W && y0 + TY + R <= H;
     float* ldc = lds;
     float* ldp = lds + LW * LH * CS;
-    stage_tile<CP>(ldc, c, H, W, C, x0, y0, R, LW, LH);
-    stage_tile<CP>(ldp, pin, H, W, C, x0, y0, R, LW, LH);
+    stage_tile2<CP>(ldc, c, ldp, pin, H, W, C, x0, y0, R, LW, LH);
     __syncthreads();
     const int gx = x0 + threadIdx.x, gy = y0 + NP * threadIdx.y;
     const bool live = gx < W && gy < H;
