@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "f1b74a3f66fc879ff683ef4054a427f055eff07183c47249ed42fcf34e7f49e9",
+    "kernel_sha256": "f7c8d55da80342e19d3cfe1a648df8813ef257ff165db539bd0c50622b17fcc4",
     "adj_step_kernel<3,5>": 11.53e6,
     "adj_step_wide_kernel<31,2>": 1607.64e6,
 }

@@ -173,22 +173,22 @@ __device__ __forceinline__ void load_px(const float* p, float (&v)[CP], float& m
 // of cells outside the image are replaced by 0 afterwards.  Element indices are 32-bit (H W C is at most
 // 4e9); with C == CP the channel offsets are constants of the load
 // instructions, otherwise they are clamped into the pixel.  Each pass has the
-// loads of up to four cells (two rows x two columns) in flight before it
+// loads of up to 2 RU cells (RU rows x two columns) in flight before it
 // writes LDS; with NF = 2 it stages two fields of the same image (dst1 from
 // src1) in the same passes, so that their loads are in flight together.
-template <int CP, bool EXACT, int NF>
+template <int CP, bool EXACT, int NF, int RU>
 __device__ __forceinline__ void stage_cells(float* dst0, const float* __restrict__ src0, float* dst1,
                                             const float* __restrict__ src1, int H, int W, int C, int x0, int y0,
                                             int R, int LW, int LH) {
     // rows are dealt out over every layer of the workgroup (blockDim.z > 1 in the split transposed step)
     const int tyz = threadIdx.y + blockDim.y * threadIdx.z, byz = blockDim.y * blockDim.z;
-    constexpr int NV = Slot<CP>::NV, CS = Slot<CP>::CS;
+    constexpr int NV = Slot<CP>::NV, CS = Slot<CP>::CS, NC = 2 * RU;
     const unsigned WC = (unsigned)W * (unsigned)C;
-    for (int ly0 = tyz; ly0 < LH; ly0 += 2 * byz) {
-        unsigned rbase[2];
-        bool row_in[2];
+    for (int ly0 = tyz; ly0 < LH; ly0 += RU * byz) {
+        unsigned rbase[RU];
+        bool row_in[RU];
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < RU; ++v) {
             // rows past the tile (no cell of theirs is written) read its last row
             const int gy = y0 - R + min(ly0 + v * (int)byz, LH - 1);
             const int gyc = min(max(gy, 0), H - 1);
@@ -196,11 +196,11 @@ __device__ __forceinline__ void stage_cells(float* dst0, const float* __restrict
             rbase[v] = (unsigned)gyc * WC;
         }
         for (int lx0 = threadIdx.x; lx0 < LW; lx0 += 2 * blockDim.x) {
-            float t[NF][4][CS];
-            bool act[4];
-            int cell[4];
+            float t[NF][NC][CS];
+            bool act[NC];
+            int cell[NC];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < NC; ++u) {
                 const int ly = ly0 + (u >> 1) * byz, lx = lx0 + (u & 1) * blockDim.x;
                 act[u] = ly < LH && lx < LW;
                 cell[u] = ly * LW + lx;
@@ -222,7 +222,7 @@ __device__ __forceinline__ void stage_cells(float* dst0, const float* __restrict
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < NC; ++u) {
                     if (!act[u]) continue;
                     float* d = (f == 0 ? dst0 : dst1) + cell[u] * CS;
                     if constexpr (CP == 1) {
@@ -239,13 +239,16 @@ __device__ __forceinline__ void stage_cells(float* dst0, const float* __restrict
     }
 }
 
+// One field: four rows x two columns per pass for up to 4 channels (a 32 x 16
+// tile and its halo of 5 in one pass of 256 threads), two rows for wider pixels.
 template <int CP>
 __device__ __forceinline__ void stage_tile(float* dst, const float* __restrict__ src, int H, int W, int C,
                                            int x0, int y0, int R, int LW, int LH) {
+    constexpr int RU = CP <= 4 ? 4 : 2;
     if (C == CP)
-        stage_cells<CP, true, 1>(dst, src, nullptr, nullptr, H, W, C, x0, y0, R, LW, LH);
+        stage_cells<CP, true, 1, RU>(dst, src, nullptr, nullptr, H, W, C, x0, y0, R, LW, LH);
     else
-        stage_cells<CP, false, 1>(dst, src, nullptr, nullptr, H, W, C, x0, y0, R, LW, LH);
+        stage_cells<CP, false, 1, RU>(dst, src, nullptr, nullptr, H, W, C, x0, y0, R, LW, LH);
 }
 
 // Two fields of one image (the transposed step's c^k and p^{k+1}): staged in
@@ -257,9 +260,9 @@ __device__ __forceinline__ void stage_tile2(float* dst0, const float* __restrict
                                             int R, int LW, int LH) {
     if constexpr (CP <= 4) {
         if (C == CP)
-            stage_cells<CP, true, 2>(dst0, src0, dst1, src1, H, W, C, x0, y0, R, LW, LH);
+            stage_cells<CP, true, 2, 2>(dst0, src0, dst1, src1, H, W, C, x0, y0, R, LW, LH);
         else
-            stage_cells<CP, false, 2>(dst0, src0, dst1, src1, H, W, C, x0, y0, R, LW, LH);
+            stage_cells<CP, false, 2, 2>(dst0, src0, dst1, src1, H, W, C, x0, y0, R, LW, LH);
     } else {
         stage_tile<CP>(dst0, src0, H, W, C, x0, y0, R, LW, LH);
         stage_tile<CP>(dst1, src1, H, W, C, x0, y0, R, LW, LH);
